@@ -1,0 +1,689 @@
+/*
+ * Plain FP64 CPU oracle for matching-based AMG-preconditioned CG.
+ *
+ * TEST INFRASTRUCTURE: loaded only by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark. It is deliberately serial and simple so
+ * that each step can be read against the paper:
+ *
+ *   Section 3.1   A_{l+1} = P_l^T A_l P_l and the V-cycle of eq. (amg)
+ *   Section 3.2   eq. (weights), maximum-weight matching (half-approximate,
+ *                 locally dominant class), eq. (prolongator), restriction
+ *                 of w to the coarse level, products of pairwise sweeps
+ *   Section 3.3   l1-Jacobi, eq. (l1weights) with blocks of size one
+ *   Section 5     CG outer iteration, relative residual stop, coarsest size
+ *
+ * Readings of points the paper leaves open (all pinned by tests):
+ *   - ties in the matching are broken by the strict key
+ *     (weight descending, lo ascending, hi ascending); under a strict key the
+ *     locally-dominant algorithm and the greedy scan give the same matching;
+ *   - the maximum-product objective and its log transform order edges the
+ *     same way as c itself, so the matching is taken on c directly;
+ *   - coarse indices are numbered by the smallest member of each aggregate;
+ *   - one level runs `sweeps` pairwise sweeps; a sweep that matches nothing
+ *     ends the level's sweeps; a level whose size does not shrink becomes
+ *     the coarsest (an error if it exceeds ORC_MAX_DENSE);
+ *   - the coarsest level is factored by dense Cholesky.
+ *
+ * Arithmetic: IEEE binary64, round to nearest, built with -ffp-contract=off
+ * and without fast-math. Every sum starts from its first term and runs in
+ * the order stated next to it.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAX_DENSE 4096
+#define ORC_MAX_LEVELS 64
+
+/* ------------------------------------------------------------------------ */
+/* small helpers                                                            */
+/* ------------------------------------------------------------------------ */
+
+static int same_bits(double a, double b) {
+  uint64_t x, y;
+  memcpy(&x, &a, 8);
+  memcpy(&y, &b, 8);
+  return x == y;
+}
+
+/* position of column j in row i, or -1 (binary search, columns ascending) */
+static int64_t find_entry(const orc_csr *A, int32_t i, int32_t j) {
+  int64_t lo = A->rp[i], hi = (int64_t)A->rp[i + 1] - 1;
+  while (lo <= hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (A->ci[mid] == j) return mid;
+    if (A->ci[mid] < j) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+static double diag_of(const orc_csr *A, int32_t i) {
+  int64_t k = find_entry(A, i, i);
+  return k >= 0 ? A->val[k] : 0.0;
+}
+
+static double dot(int64_t n, const double *x, const double *y) {
+  if (n == 0) return 0.0;
+  double s = x[0] * y[0];
+  for (int64_t i = 1; i < n; ++i) s = s + x[i] * y[i];
+  return s;
+}
+
+static int csr_alloc(orc_csr *A, int32_t n, int64_t nnz) {
+  A->n = n;
+  A->nnz = nnz;
+  A->rp = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  A->ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  A->val = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+  if (!A->rp || !A->ci || !A->val) {
+    orc_csr_free(A);
+    return ORC_ERR_OOM;
+  }
+  return ORC_OK;
+}
+
+void orc_csr_free(orc_csr *A) {
+  if (!A) return;
+  free(A->rp);
+  free(A->ci);
+  free(A->val);
+  A->rp = NULL;
+  A->ci = NULL;
+  A->val = NULL;
+  A->n = 0;
+  A->nnz = 0;
+}
+
+static int csr_copy(const orc_csr *A, orc_csr *B) {
+  int st = csr_alloc(B, A->n, A->nnz);
+  if (st) return st;
+  memcpy(B->rp, A->rp, sizeof(int32_t) * ((size_t)A->n + 1));
+  memcpy(B->ci, A->ci, sizeof(int32_t) * (size_t)A->nnz);
+  memcpy(B->val, A->val, sizeof(double) * (size_t)A->nnz);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* single steps                                                             */
+/* ------------------------------------------------------------------------ */
+
+void orc_spmv(const orc_csr *A, const double *x, double *y) {
+  for (int32_t i = 0; i < A->n; ++i) {
+    int64_t b = A->rp[i], e = A->rp[i + 1];
+    double s = 0.0;
+    if (e > b) {
+      s = A->val[b] * x[A->ci[b]];
+      for (int64_t k = b + 1; k < e; ++k) s = s + A->val[k] * x[A->ci[k]];
+    }
+    y[i] = s;
+  }
+}
+
+int orc_check(const orc_csr *A) {
+  if (A->n <= 0 || A->rp[0] != 0 || (int64_t)A->rp[A->n] != A->nnz) return ORC_ERR_ARG;
+  for (int32_t i = 0; i < A->n; ++i) {
+    if (A->rp[i + 1] < A->rp[i]) return ORC_ERR_ARG;
+    for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+      if (A->ci[k] < 0 || A->ci[k] >= A->n) return ORC_ERR_ARG;
+      if (k > A->rp[i] && A->ci[k] <= A->ci[k - 1]) return ORC_ERR_ARG;
+      if (!isfinite(A->val[k])) return ORC_ERR_ARG;
+    }
+  }
+  for (int32_t i = 0; i < A->n; ++i) {
+    int64_t d = find_entry(A, i, i);
+    if (d < 0 || !(A->val[d] > 0.0)) return ORC_ERR_NOT_SPD;
+  }
+  for (int32_t i = 0; i < A->n; ++i) {
+    for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+      int64_t t = find_entry(A, A->ci[k], i);
+      if (t < 0 || !same_bits(A->val[t], A->val[k])) return ORC_ERR_NOT_SYMMETRIC;
+    }
+  }
+  return ORC_OK;
+}
+
+int64_t orc_num_edges(const orc_csr *A) {
+  int64_t ne = 0;
+  for (int32_t i = 0; i < A->n; ++i)
+    for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k)
+      if (A->ci[k] > i) ++ne;
+  return ne;
+}
+
+/* eq. (weights) */
+void orc_edge_weights(const orc_csr *A, const double *w, int32_t *lo,
+                      int32_t *hi, double *c) {
+  int64_t e = 0;
+  for (int32_t i = 0; i < A->n; ++i) {
+    double aii = diag_of(A, i);
+    for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+      int32_t j = A->ci[k];
+      if (j <= i) continue;
+      double a = A->val[k];
+      double ajj = diag_of(A, j);
+      double num = ((2.0 * a) * w[i]) * w[j];
+      double den = (aii * w[i]) * w[i] + (ajj * w[j]) * w[j];
+      lo[e] = i;
+      hi[e] = j;
+      c[e] = 1.0 - num / den;
+      ++e;
+    }
+  }
+}
+
+/* sort key for the matching: c descending, then lo ascending, hi ascending */
+typedef struct {
+  double c;
+  int32_t lo, hi;
+} edge_key;
+
+static int edge_cmp(const void *pa, const void *pb) {
+  const edge_key *a = (const edge_key *)pa, *b = (const edge_key *)pb;
+  if (a->c > b->c) return -1;
+  if (a->c < b->c) return 1;
+  if (a->lo != b->lo) return a->lo < b->lo ? -1 : 1;
+  if (a->hi != b->hi) return a->hi < b->hi ? -1 : 1;
+  return 0;
+}
+
+int64_t orc_greedy_matching(int32_t n, int64_t ne, const int32_t *lo,
+                            const int32_t *hi, const double *c, int32_t *mate) {
+  edge_key *ek = (edge_key *)malloc(sizeof(edge_key) * (size_t)(ne > 0 ? ne : 1));
+  for (int64_t e = 0; e < ne; ++e) {
+    ek[e].c = c[e];
+    ek[e].lo = lo[e];
+    ek[e].hi = hi[e];
+  }
+  qsort(ek, (size_t)ne, sizeof(edge_key), edge_cmp);
+  for (int32_t v = 0; v < n; ++v) mate[v] = -1;
+  int64_t nm = 0;
+  for (int64_t e = 0; e < ne; ++e) {
+    int32_t a = ek[e].lo, b = ek[e].hi;
+    if (a != b && mate[a] < 0 && mate[b] < 0) {
+      mate[a] = b;
+      mate[b] = a;
+      ++nm;
+    }
+  }
+  free(ek);
+  return nm;
+}
+
+int32_t orc_number_aggregates(int32_t n, const int32_t *mate, int32_t *agg) {
+  for (int32_t v = 0; v < n; ++v) agg[v] = -1;
+  int32_t next = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    if (agg[v] >= 0) continue;
+    agg[v] = next;
+    if (mate[v] >= 0) agg[mate[v]] = next;
+    ++next;
+  }
+  return next;
+}
+
+/* eq. (prolongator): orthonormal projection of w on each pair, w_s/|w_s| on
+ * singletons. */
+void orc_pairwise_prolongator(int32_t n, const int32_t *mate, const double *w,
+                              double *p) {
+  for (int32_t v = 0; v < n; ++v) {
+    if (mate[v] < 0) {
+      p[v] = w[v] / fabs(w[v]);
+    } else {
+      int32_t i = v < mate[v] ? v : mate[v];
+      int32_t j = v < mate[v] ? mate[v] : v;
+      double s = w[i] * w[i] + w[j] * w[j];
+      p[v] = w[v] / sqrt(s);
+    }
+  }
+}
+
+void orc_restrict(int32_t n, int32_t nc, const int32_t *agg, const double *p,
+                  const double *v, double *vc) {
+  char *seen = (char *)calloc((size_t)(nc > 0 ? nc : 1), 1);
+  for (int32_t i = 0; i < n; ++i) { /* ascending i within every aggregate */
+    int32_t I = agg[i];
+    double t = p[i] * v[i];
+    if (!seen[I]) {
+      vc[I] = t;
+      seen[I] = 1;
+    } else {
+      vc[I] = vc[I] + t;
+    }
+  }
+  for (int32_t I = 0; I < nc; ++I)
+    if (!seen[I]) vc[I] = 0.0;
+  free(seen);
+}
+
+/* one Galerkin term of the pairwise product */
+typedef struct {
+  int32_t J, lo, hi;
+  double t;
+} rap_term;
+
+static int rap_cmp(const void *pa, const void *pb) {
+  const rap_term *a = (const rap_term *)pa, *b = (const rap_term *)pb;
+  if (a->J != b->J) return a->J < b->J ? -1 : 1;
+  if (a->lo != b->lo) return a->lo < b->lo ? -1 : 1;
+  if (a->hi != b->hi) return a->hi < b->hi ? -1 : 1;
+  return 0; /* equal keys carry equal terms (A is bitwise symmetric) */
+}
+
+int orc_galerkin_pairwise(const orc_csr *A, int32_t nc, const int32_t *agg,
+                          const double *p, orc_csr *Ac) {
+  int32_t n = A->n;
+  /* members of each aggregate, ascending (at most two) */
+  int32_t *m0 = (int32_t *)malloc(sizeof(int32_t) * (size_t)nc);
+  int32_t *m1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)nc);
+  for (int32_t I = 0; I < nc; ++I) m0[I] = m1[I] = -1;
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t I = agg[i];
+    if (m0[I] < 0) m0[I] = i;
+    else if (m1[I] < 0) m1[I] = i;
+    else { free(m0); free(m1); return ORC_ERR_ARG; } /* not pairwise */
+  }
+  int32_t maxrow = 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (A->rp[i + 1] - A->rp[i] > maxrow) maxrow = A->rp[i + 1] - A->rp[i];
+  rap_term *buf = (rap_term *)malloc(sizeof(rap_term) * (size_t)(2 * maxrow + 1));
+
+  /* pass 1: row lengths; pass 2: fill */
+  int32_t *rp = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nc + 1));
+  int32_t *ci = NULL;
+  double *vv = NULL;
+  rp[0] = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int32_t I = 0; I < nc; ++I) {
+      int32_t cnt = 0;
+      int32_t mem[2] = {m0[I], m1[I]};
+      for (int q = 0; q < 2; ++q) {
+        int32_t f = mem[q];
+        if (f < 0) continue;
+        for (int64_t k = A->rp[f]; k < A->rp[f + 1]; ++k) {
+          int32_t j = A->ci[k];
+          int32_t lo = f < j ? f : j;
+          int32_t hi = f < j ? j : f;
+          double a = A->val[find_entry(A, lo, hi)]; /* a from row lo */
+          buf[cnt].J = agg[j];
+          buf[cnt].lo = lo;
+          buf[cnt].hi = hi;
+          buf[cnt].t = (p[lo] * a) * p[hi];
+          ++cnt;
+        }
+      }
+      qsort(buf, (size_t)cnt, sizeof(rap_term), rap_cmp);
+      int32_t out = 0;
+      for (int32_t k = 0; k < cnt; ++k) {
+        if (k == 0 || buf[k].J != buf[k - 1].J) {
+          if (pass == 1) {
+            ci[rp[I] + out] = buf[k].J;
+            vv[rp[I] + out] = buf[k].t;
+          }
+          ++out;
+        } else if (pass == 1) {
+          vv[rp[I] + out - 1] = vv[rp[I] + out - 1] + buf[k].t;
+        }
+      }
+      if (pass == 0) rp[I + 1] = rp[I] + out;
+    }
+    if (pass == 0) {
+      ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(rp[nc] > 0 ? rp[nc] : 1));
+      vv = (double *)malloc(sizeof(double) * (size_t)(rp[nc] > 0 ? rp[nc] : 1));
+    }
+  }
+  free(buf);
+  free(m0);
+  free(m1);
+  Ac->n = nc;
+  Ac->nnz = rp[nc];
+  Ac->rp = rp;
+  Ac->ci = ci;
+  Ac->val = vv;
+  return ORC_OK;
+}
+
+/* eq. (l1weights), nb = 1 */
+void orc_l1_diag(const orc_csr *A, double *m) {
+  for (int32_t i = 0; i < A->n; ++i) {
+    double aii = 0.0, s = 0.0;
+    int first = 1;
+    for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+      if (A->ci[k] == i) {
+        aii = A->val[k];
+      } else if (first) {
+        s = fabs(A->val[k]);
+        first = 0;
+      } else {
+        s = s + fabs(A->val[k]);
+      }
+    }
+    m[i] = aii + s;
+  }
+}
+
+int orc_cholesky(int32_t n, double *a) {
+  for (int32_t j = 0; j < n; ++j) {
+    double s = a[(int64_t)j * n + j];
+    for (int32_t k = 0; k < j; ++k) s = s - a[(int64_t)j * n + k] * a[(int64_t)j * n + k];
+    if (!(s > 0.0)) return ORC_ERR_NOT_SPD;
+    double d = sqrt(s);
+    a[(int64_t)j * n + j] = d;
+    for (int32_t i = j + 1; i < n; ++i) {
+      double t = a[(int64_t)i * n + j];
+      for (int32_t k = 0; k < j; ++k) t = t - a[(int64_t)i * n + k] * a[(int64_t)j * n + k];
+      a[(int64_t)i * n + j] = t / d;
+    }
+  }
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t j = i + 1; j < n; ++j) a[(int64_t)i * n + j] = 0.0;
+  return ORC_OK;
+}
+
+void orc_cholesky_solve(int32_t n, const double *L, const double *r, double *z) {
+  double *y = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  for (int32_t i = 0; i < n; ++i) {
+    double t = r[i];
+    for (int32_t k = 0; k < i; ++k) t = t - L[(int64_t)i * n + k] * y[k];
+    y[i] = t / L[(int64_t)i * n + i];
+  }
+  for (int32_t i = n - 1; i >= 0; --i) {
+    double t = y[i];
+    for (int32_t k = i + 1; k < n; ++k) t = t - L[(int64_t)k * n + i] * z[k];
+    z[i] = t / L[(int64_t)i * n + i];
+  }
+  free(y);
+}
+
+/* ------------------------------------------------------------------------ */
+/* hierarchy                                                                */
+/* ------------------------------------------------------------------------ */
+
+struct orc_hier {
+  int32_t nlev;
+  orc_csr A[ORC_MAX_LEVELS];
+  double *w[ORC_MAX_LEVELS];
+  int32_t *agg[ORC_MAX_LEVELS]; /* level l -> l+1 composed map */
+  double *p[ORC_MAX_LEVELS];    /* composed prolongator values */
+  double *m[ORC_MAX_LEVELS];    /* l1-Jacobi diagonal */
+  int32_t nsweeps[ORC_MAX_LEVELS];
+  int32_t nL;
+  double *L; /* coarsest Cholesky factor */
+};
+
+void orc_free(orc_hier *h) {
+  if (!h) return;
+  for (int32_t l = 0; l < ORC_MAX_LEVELS; ++l) {
+    orc_csr_free(&h->A[l]);
+    free(h->w[l]);
+    free(h->agg[l]);
+    free(h->p[l]);
+    free(h->m[l]);
+  }
+  free(h->L);
+  free(h);
+}
+
+/* One pairwise sweep (Section 3.2) on (A, w): weights, matching, numbering,
+ * prolongator, Galerkin product and restriction of w. Returns the number of
+ * matched edges (0: nothing produced), or a negative status. */
+static int64_t pairwise_sweep(const orc_csr *A, const double *w, orc_csr *Ac,
+                              double **wc, int32_t **agg, double **p) {
+  int32_t n = A->n;
+  int64_t ne = orc_num_edges(A);
+  int32_t *lo = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ne > 0 ? ne : 1));
+  int32_t *hi = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ne > 0 ? ne : 1));
+  double *c = (double *)malloc(sizeof(double) * (size_t)(ne > 0 ? ne : 1));
+  int32_t *mate = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  orc_edge_weights(A, w, lo, hi, c);
+  int64_t nm = orc_greedy_matching(n, ne, lo, hi, c, mate);
+  free(lo);
+  free(hi);
+  free(c);
+  if (nm == 0) {
+    free(mate);
+    return 0;
+  }
+  *agg = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  *p = (double *)malloc(sizeof(double) * (size_t)n);
+  int32_t nc = orc_number_aggregates(n, mate, *agg);
+  orc_pairwise_prolongator(n, mate, w, *p);
+  free(mate);
+  int st = orc_galerkin_pairwise(A, nc, *agg, *p, Ac);
+  if (st) return -st;
+  *wc = (double *)malloc(sizeof(double) * (size_t)nc);
+  orc_restrict(n, nc, *agg, *p, w, *wc);
+  return nm;
+}
+
+int orc_setup(const orc_csr *A0, const double *w0, int32_t sweeps,
+              int32_t max_coarse, int32_t max_levels, orc_hier **out) {
+  *out = NULL;
+  if (!A0 || sweeps < 1 || max_coarse < 1 || max_levels < 1) return ORC_ERR_ARG;
+  if (max_levels > ORC_MAX_LEVELS) max_levels = ORC_MAX_LEVELS;
+  int st = orc_check(A0);
+  if (st) return st;
+  if (w0)
+    for (int32_t i = 0; i < A0->n; ++i)
+      if (!(w0[i] != 0.0) || !isfinite(w0[i])) return ORC_ERR_ARG;
+  orc_hier *h = (orc_hier *)calloc(1, sizeof(orc_hier));
+  csr_copy(A0, &h->A[0]);
+  h->w[0] = (double *)malloc(sizeof(double) * (size_t)A0->n);
+  for (int32_t i = 0; i < A0->n; ++i) h->w[0][i] = w0 ? w0[i] : 1.0;
+
+  int32_t l = 0;
+  for (;;) {
+    int32_t n = h->A[l].n;
+    if (n <= max_coarse || l == max_levels - 1) break;
+    /* m pairwise sweeps whose product is P_l (Section 3.2) */
+    orc_csr cur = h->A[l];
+    double *wcur = h->w[l];
+    int own = 0; /* cur/wcur owned by this loop (not the level's) */
+    int32_t *agg_c = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    double *p_c = (double *)malloc(sizeof(double) * (size_t)n);
+    int32_t done = 0;
+    for (int32_t k = 0; k < sweeps; ++k) {
+      orc_csr nxt = {0};
+      double *wn = NULL;
+      int32_t *ag = NULL;
+      double *pk = NULL;
+      int64_t nm = pairwise_sweep(&cur, wcur, &nxt, &wn, &ag, &pk);
+      if (nm < 0) {
+        orc_free(h);
+        return (int)(-nm);
+      }
+      if (nm == 0) break;
+      /* compose: P_l(i) = ((p_1(i) p_2(agg_1(i))) p_3(agg_2(agg_1(i)))) */
+      for (int32_t i = 0; i < n; ++i) {
+        if (k == 0) {
+          p_c[i] = pk[i];
+          agg_c[i] = ag[i];
+        } else {
+          int32_t a = agg_c[i];
+          p_c[i] = p_c[i] * pk[a];
+          agg_c[i] = ag[a];
+        }
+      }
+      free(ag);
+      free(pk);
+      if (own) {
+        orc_csr_free(&cur);
+        free(wcur);
+      }
+      cur = nxt;
+      wcur = wn;
+      own = 1;
+      ++done;
+    }
+    if (done == 0) { /* nothing matched: this level is the coarsest */
+      free(agg_c);
+      free(p_c);
+      break;
+    }
+    h->agg[l] = agg_c;
+    h->p[l] = p_c;
+    h->nsweeps[l] = done;
+    h->A[l + 1] = cur;
+    h->w[l + 1] = wcur;
+    ++l;
+  }
+  h->nlev = l + 1;
+  for (int32_t k = 0; k < l; ++k) {
+    h->m[k] = (double *)malloc(sizeof(double) * (size_t)h->A[k].n);
+    orc_l1_diag(&h->A[k], h->m[k]);
+  }
+  /* coarsest: dense Cholesky */
+  orc_csr *C = &h->A[l];
+  if (C->n > ORC_MAX_DENSE) {
+    orc_free(h);
+    return ORC_ERR_STALL;
+  }
+  h->nL = C->n;
+  h->L = (double *)calloc((size_t)C->n * (size_t)C->n, sizeof(double));
+  for (int32_t i = 0; i < C->n; ++i)
+    for (int64_t k = C->rp[i]; k < C->rp[i + 1]; ++k)
+      h->L[(int64_t)i * C->n + C->ci[k]] = C->val[k];
+  st = orc_cholesky(C->n, h->L);
+  if (st) {
+    orc_free(h);
+    return st;
+  }
+  *out = h;
+  return ORC_OK;
+}
+
+int32_t orc_num_levels(const orc_hier *h) { return h->nlev; }
+int64_t orc_level_n(const orc_hier *h, int32_t l) { return h->A[l].n; }
+int64_t orc_level_nnz(const orc_hier *h, int32_t l) { return h->A[l].nnz; }
+int32_t orc_level_sweeps(const orc_hier *h, int32_t l) { return h->nsweeps[l]; }
+
+void orc_level_csr(const orc_hier *h, int32_t l, int32_t *rp, int32_t *ci, double *val) {
+  const orc_csr *A = &h->A[l];
+  memcpy(rp, A->rp, sizeof(int32_t) * ((size_t)A->n + 1));
+  memcpy(ci, A->ci, sizeof(int32_t) * (size_t)A->nnz);
+  memcpy(val, A->val, sizeof(double) * (size_t)A->nnz);
+}
+
+void orc_level_transfer(const orc_hier *h, int32_t l, int32_t *agg, double *p) {
+  memcpy(agg, h->agg[l], sizeof(int32_t) * (size_t)h->A[l].n);
+  memcpy(p, h->p[l], sizeof(double) * (size_t)h->A[l].n);
+}
+
+void orc_level_l1diag(const orc_hier *h, int32_t l, double *m) {
+  memcpy(m, h->m[l], sizeof(double) * (size_t)h->A[l].n);
+}
+
+void orc_level_w(const orc_hier *h, int32_t l, double *w) {
+  memcpy(w, h->w[l], sizeof(double) * (size_t)h->A[l].n);
+}
+
+void orc_coarse_factor(const orc_hier *h, double *L) {
+  memcpy(L, h->L, sizeof(double) * (size_t)h->nL * (size_t)h->nL);
+}
+
+/* eq. (amg): pre-smoothing M^-1 from a zero guess, coarse correction,
+ * post-smoothing M^-T = M^-1 (M diagonal). */
+void orc_vcycle(const orc_hier *h, int32_t l, int32_t pre, int32_t post,
+                const double *r, double *z) {
+  int32_t L = h->nlev - 1;
+  if (l == L) {
+    orc_cholesky_solve(h->nL, h->L, r, z);
+    return;
+  }
+  const orc_csr *A = &h->A[l];
+  int32_t n = A->n, nc = h->A[l + 1].n;
+  const double *m = h->m[l];
+  double *t = (double *)malloc(sizeof(double) * (size_t)n);
+  double *rc = (double *)malloc(sizeof(double) * (size_t)nc);
+  double *zc = (double *)malloc(sizeof(double) * (size_t)nc);
+  /* pre-smoothing */
+  for (int32_t i = 0; i < n; ++i) z[i] = pre > 0 ? r[i] / m[i] : 0.0;
+  for (int32_t s = 1; s < pre; ++s) {
+    orc_spmv(A, z, t);
+    for (int32_t i = 0; i < n; ++i) z[i] = z[i] + (r[i] - t[i]) / m[i];
+  }
+  /* residual, restriction, coarse solve, prolongation */
+  orc_spmv(A, z, t);
+  for (int32_t i = 0; i < n; ++i) t[i] = r[i] - t[i];
+  orc_restrict(n, nc, h->agg[l], h->p[l], t, rc);
+  orc_vcycle(h, l + 1, pre, post, rc, zc);
+  for (int32_t i = 0; i < n; ++i) z[i] = z[i] + h->p[l][i] * zc[h->agg[l][i]];
+  /* post-smoothing */
+  for (int32_t s = 0; s < post; ++s) {
+    orc_spmv(A, z, t);
+    for (int32_t i = 0; i < n; ++i) z[i] = z[i] + (r[i] - t[i]) / m[i];
+  }
+  free(t);
+  free(rc);
+  free(zc);
+}
+
+int orc_pcg(const orc_hier *h, int32_t pre, int32_t post, const double *b,
+            double *x, double rtol, int32_t maxit, double *out) {
+  const orc_csr *A = &h->A[0];
+  int32_t n = A->n;
+  double *r = (double *)malloc(sizeof(double) * (size_t)n);
+  double *z = (double *)malloc(sizeof(double) * (size_t)n);
+  double *p = (double *)malloc(sizeof(double) * (size_t)n);
+  double *q = (double *)malloc(sizeof(double) * (size_t)n);
+  int st = ORC_NOT_CONVERGED;
+  int32_t it = 0;
+  double bnorm = sqrt(dot(n, b, b));
+  double rnorm = 0.0;
+  if (bnorm == 0.0) {
+    for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+    st = ORC_OK;
+    goto done;
+  }
+  orc_spmv(A, x, q);
+  for (int32_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+  rnorm = sqrt(dot(n, r, r));
+  if (rnorm <= rtol * bnorm) {
+    st = ORC_OK;
+    goto done;
+  }
+  orc_vcycle(h, 0, pre, post, r, z);
+  for (int32_t i = 0; i < n; ++i) p[i] = z[i];
+  double rho = dot(n, r, z);
+  for (it = 1; it <= maxit; ++it) {
+    orc_spmv(A, p, q);
+    double pq = dot(n, p, q);
+    if (!(pq > 0.0) || !(rho > 0.0)) {
+      st = ORC_ERR_BREAKDOWN;
+      --it;
+      break;
+    }
+    double alpha = rho / pq;
+    for (int32_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+    for (int32_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+    rnorm = sqrt(dot(n, r, r));
+    if (rnorm <= rtol * bnorm) {
+      st = ORC_OK;
+      break;
+    }
+    if (it == maxit) break;
+    orc_vcycle(h, 0, pre, post, r, z);
+    double rz = dot(n, r, z);
+    double beta = rz / rho;
+    rho = rz;
+    for (int32_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+  }
+  if (it > maxit) it = maxit;
+done:
+  out[0] = (double)it;
+  out[1] = st == ORC_OK ? 1.0 : 0.0;
+  out[2] = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+  if (bnorm > 0.0) {
+    orc_spmv(A, x, q);
+    for (int32_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+    out[3] = sqrt(dot(n, r, r)) / bnorm;
+  } else {
+    out[3] = 0.0;
+  }
+  free(r);
+  free(z);
+  free(p);
+  free(q);
+  return st;
+}
