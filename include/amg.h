@@ -1,0 +1,186 @@
+/*
+ * amg.h - C ABI of the MI355X (gfx950) matching-AMG preconditioned CG library.
+ *
+ * Method: D'Ambra, Durastante, Filippone, "AMG preconditioners for linear
+ * solvers towards extreme scale".
+ *   - The system: s.p.d. A x = b (Section 1, eq. (sys); Section 3.1).
+ *   - Hierarchy: A_{l+1} = P_l^T A_l P_l (Section 3.1), with P_l the product
+ *     of `sweeps` pairwise prolongators built by coupled aggregation based on
+ *     compatible weighted matching: edge weights eq. (weights), an
+ *     approximate maximum-weight matching of the locally-dominant class,
+ *     eq. (prolongator), and the restriction of the smooth vector w to the
+ *     next level (Section 3.2). Coarsening stops once a level has at most
+ *     `max_coarse` unknowns (Section 5).
+ *   - Smoother: l1-Jacobi, eqs. (ml1hgs)/(l1weights) with blocks of one row
+ *     (Section 3.3); one pre- and one post-sweep by default.
+ *   - Preconditioner: the V-cycle of eq. (amg); the coarsest system is
+ *     solved exactly with a dense Cholesky factorisation.
+ *   - Solver: preconditioned CG, stopped on the relative residual (Section 5).
+ *
+ * Matching ties are broken by the strict key (weight descending, smaller
+ * endpoint ascending, larger endpoint ascending); aggregates are numbered by
+ * their smallest member. With these rules the hierarchy is fully determined
+ * and the library reproduces it bit for bit on every run.
+ *
+ * Conventions shared by every entry point:
+ *   - All array arguments named "device" are HIP device pointers on the
+ *     current device (hipGetDevice at the time of the call); arrays named
+ *     "host" are host pointers. The library never takes ownership of caller
+ *     arrays; it owns only what it allocates inside a hierarchy.
+ *   - Indices are 0-based int32. CSR rows hold strictly ascending columns,
+ *     the diagonal is stored and positive, and A is bitwise symmetric.
+ *   - Calls are ordered on the hierarchy's stream (amg_params.stream; NULL
+ *     is the device's default stream). Every call returns after its results
+ *     are complete on the device.
+ *   - One hierarchy is used by one host thread at a time. Distinct
+ *     hierarchies may be used concurrently from different threads.
+ *   - No call aborts or throws; failures return a status code and leave the
+ *     outputs unspecified unless stated.
+ */
+#ifndef AMG_H
+#define AMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amg_hierarchy amg_hierarchy; /* opaque; owns its device memory */
+
+typedef enum {
+  AMG_OK = 0,
+  AMG_ERR_ARG = 1,           /* invalid argument or malformed CSR */
+  AMG_ERR_NOT_SYMMETRIC = 2, /* A is not bitwise symmetric */
+  AMG_ERR_NOT_SPD = 3,       /* non-positive diagonal or Cholesky pivot */
+  AMG_ERR_STALL = 4,         /* coarsening stopped above the dense limit */
+  AMG_ERR_OOM = 5,           /* device allocation failed */
+  AMG_ERR_HIP = 6,           /* a HIP runtime call failed */
+  AMG_ERR_BREAKDOWN = 7,     /* CG breakdown: (p, Ap) <= 0 or NaN */
+  AMG_NOT_CONVERGED = 8      /* maxit reached; x and info are still written */
+} amg_status;
+
+/* precision of the stored hierarchy and of the V-cycle arithmetic */
+enum { AMG_FP64 = 0, AMG_FP32 = 1 };
+
+/* amg_params.flags */
+enum {
+  AMG_FLAG_NO_GRAPH = 1,   /* launch the solve kernels directly, no hipGraph */
+  AMG_FLAG_SKIP_CHECKS = 2 /* skip the symmetry/structure validation pass */
+};
+
+/* Largest coarsest level the dense Cholesky accepts (AMG_ERR_STALL above). */
+#define AMG_MAX_DENSE 4096
+
+/* Square CSR matrix: device pointers, n + 1 row offsets, nnz columns and
+ * values. nnz must be below 2^31. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int32_t *row_ptr; /* device, n + 1 */
+  const int32_t *col;     /* device, nnz */
+  const double *val;      /* device, nnz */
+} amg_csr;
+
+typedef struct {
+  int32_t sweeps;     /* pairwise sweeps per level (aggregates <= 2^sweeps); 3 */
+  int32_t max_coarse; /* stop coarsening at n_l <= max_coarse; 200 */
+  int32_t max_levels; /* hard cap on the number of levels; 32 */
+  int32_t pre, post;  /* l1-Jacobi sweeps before / after the coarse correction; 1, 1 */
+  int32_t precision;  /* AMG_FP64 or AMG_FP32 (hierarchy values and V-cycle) */
+  const double *w;    /* device, n: smooth vector, no zero entry; NULL = ones */
+  void *stream;       /* hipStream_t for every call on this hierarchy; NULL = the
+                         device's default stream */
+  int32_t flags;      /* AMG_FLAG_* */
+} amg_params;
+
+typedef struct {
+  int32_t iterations;  /* CG iterations performed */
+  int32_t converged;   /* 1 if ||r_k||_2 <= rtol ||b||_2 */
+  double rel_res;      /* recursive residual ||r_k|| / ||b|| */
+  double rel_res_true; /* ||b - A x|| / ||b|| recomputed at exit */
+  double ms;           /* wall time of the call */
+} amg_solve_info;
+
+/* Fills the defaults listed beside each field above. */
+void amg_params_default(amg_params *p);
+
+/* Builds the hierarchy of A (Sections 3.1-3.3, see the header comment).
+ * A's arrays are copied; the caller may free them on return. The whole setup
+ * runs in device kernels on the hierarchy's stream.
+ * Errors: AMG_ERR_ARG (n < 1, bad sizes, unsorted or out-of-range columns,
+ * zero or non-finite w, bad params), AMG_ERR_NOT_SYMMETRIC, AMG_ERR_NOT_SPD
+ * (diagonal <= 0 or coarsest Cholesky failure), AMG_ERR_STALL (a level that
+ * no longer coarsens holds more than AMG_MAX_DENSE unknowns), AMG_ERR_OOM,
+ * AMG_ERR_HIP. On error *out is NULL. */
+amg_status amg_setup(const amg_csr *A, const amg_params *params, amg_hierarchy **out);
+
+/* Preconditioned CG on A x = b with the V-cycle as preconditioner.
+ * b: device, n (read). x: device, n (in: initial guess, out: iterate).
+ * Stops when ||r_k||_2 <= rtol ||b||_2 or after maxit iterations; b = 0 gives
+ * x = 0 after 0 iterations. rtol = 0 runs exactly maxit iterations.
+ * info may be NULL. Returns AMG_OK, AMG_NOT_CONVERGED (x and info written),
+ * AMG_ERR_BREAKDOWN, AMG_ERR_ARG, AMG_ERR_HIP. */
+amg_status amg_pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol,
+                         int32_t maxit, amg_solve_info *info);
+
+/* k independent PCG solves sharing the hierarchy: column j of the n x k
+ * row-major blocks B (device, read) and X (device, in: x0, out: x) is solved
+ * with its own CG recurrence (own alpha, beta, stop test); the V-cycle runs
+ * once per iteration on the whole block. info: host array of k, may be NULL.
+ * Returns AMG_OK if every column converged, else AMG_NOT_CONVERGED, or an
+ * error. k = 0 is a no-op. */
+amg_status amg_pcg_solve_batch(amg_hierarchy *h, int32_t k, const double *B, double *X,
+                               double rtol, int32_t maxit, amg_solve_info *info);
+
+/* One application of the preconditioner, z = B_0 r (eq. (amg)).
+ * r, z: device, n. */
+amg_status amg_vcycle_apply(amg_hierarchy *h, const double *r, double *z);
+
+/* Releases the hierarchy and all its device memory. NULL is a no-op. */
+void amg_free(amg_hierarchy *h);
+
+/* ---- introspection (tests, serving, benchmarks) ------------------------ */
+
+amg_status amg_num_levels(const amg_hierarchy *h, int32_t *nlev);
+/* size and nnz of level l, 0 <= l < nlev */
+amg_status amg_level_info(const amg_hierarchy *h, int32_t l, int64_t *n, int64_t *nnz);
+/* Copies level l's CSR (FP64 values) to host arrays of n + 1, nnz, nnz. */
+amg_status amg_get_level_csr(const amg_hierarchy *h, int32_t l, int32_t *row_ptr_host,
+                             int32_t *col_host, double *val_host);
+/* Copies the composed aggregate map and prolongator values of level l
+ * (l < nlev - 1): agg_host[i] is the level-(l+1) index of fine row i and
+ * p_host[i] the entry P_l(i, agg_host[i]). Either pointer may be NULL. */
+amg_status amg_get_transfer(const amg_hierarchy *h, int32_t l, int32_t *agg_host,
+                            double *p_host);
+/* Copies the l1-Jacobi diagonal m of level l (l < nlev - 1). */
+amg_status amg_get_l1diag(const amg_hierarchy *h, int32_t l, double *m_host);
+/* Copies the smooth vector w restricted to level l. */
+amg_status amg_get_w(const amg_hierarchy *h, int32_t l, double *w_host);
+/* Device bytes owned by the hierarchy. */
+size_t amg_footprint_bytes(const amg_hierarchy *h);
+/* Upper estimate of the device bytes amg_setup and one amg_pcg_solve need
+ * for an n x n matrix with nnz entries (used for admission control). */
+size_t amg_estimate_footprint(int64_t n, int64_t nnz, const amg_params *params);
+/* Milliseconds of the last amg_setup, split by stage (host array of 8):
+ * validate, weights+matching, numbering+prolongator, Galerkin, compose,
+ * smoother+coarsest, solve-format conversion, total. */
+amg_status amg_setup_times(const amg_hierarchy *h, double *ms_host);
+/* Number of matching rounds run when building level l (sum over sweeps). */
+amg_status amg_matching_rounds(const amg_hierarchy *h, int32_t l, int32_t *rounds);
+
+/* Times `reps` launches of one solve-phase kernel on level l with live data
+ * between HIP events on the hierarchy's stream; *ms = mean per launch and
+ * *bytes = the kernel's algorithmic HBM bytes per launch. kernel:
+ * 0 = pre-smoothing + residual, 1 = post-smoothing, 2 = restriction,
+ * 3 = prolongation, 4 = outer-CG SpMV with dot product. */
+amg_status amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
+                           double *ms, double *bytes);
+
+const char *amg_status_string(amg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMG_H */

@@ -1,0 +1,259 @@
+// C ABI of the library (include/amg.h): argument checks, hierarchy lifetime,
+// introspection. The numerical work is in setup.hip, solve.hip and batch.hip.
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace amg {
+
+amg_status dev_alloc(amg_hierarchy *h, void **p, size_t bytes) {
+  *p = nullptr;
+  void *q = nullptr;
+  AMG_HIP(hipMalloc(&q, bytes));
+  h->allocs.push_back(q);
+  h->bytes += bytes;
+  *p = q;
+  return AMG_OK;
+}
+
+void dev_release(amg_hierarchy *h, void *p) {
+  for (auto &q : h->allocs)
+    if (q == p) {
+      (void)hipFree(q);
+      q = nullptr;
+    }
+}
+
+}  // namespace amg
+
+using namespace amg;
+
+namespace {
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+void destroy(amg_hierarchy *h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->iter_exec) (void)hipGraphExecDestroy(h->iter_exec);
+  if (h->iter_graph) (void)hipGraphDestroy(h->iter_graph);
+  for (void *p : h->allocs)
+    if (p) (void)hipFree(p);
+  if (h->batch_mem) (void)hipFree(h->batch_mem);
+  if (h->scal_host) (void)hipHostFree(h->scal_host);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+amg_status check_params(const amg_params *p) {
+  if (p->sweeps < 1 || p->sweeps > 8) return AMG_ERR_ARG;
+  if (p->max_coarse < 1 || p->max_coarse > AMG_MAX_DENSE) return AMG_ERR_ARG;
+  if (p->max_levels < 1 || p->max_levels > 64) return AMG_ERR_ARG;
+  if (p->pre < 1 || p->pre > 8 || p->post < 1 || p->post > 8) return AMG_ERR_ARG;
+  if (p->precision != AMG_FP64 && p->precision != AMG_FP32) return AMG_ERR_ARG;
+  return AMG_OK;
+}
+
+bool on_device(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+extern "C" {
+
+void amg_params_default(amg_params *p) {
+  if (!p) return;
+  p->sweeps = 3;
+  p->max_coarse = 200;
+  p->max_levels = 32;
+  p->pre = 1;
+  p->post = 1;
+  p->precision = AMG_FP64;
+  p->w = nullptr;
+  p->stream = nullptr;
+  p->flags = 0;
+}
+
+amg_status amg_setup(const amg_csr *A, const amg_params *params, amg_hierarchy **out) {
+  if (!out) return AMG_ERR_ARG;
+  *out = nullptr;
+  if (!A || A->n < 1 || A->n > INT32_MAX - 1 || A->nnz < A->n || A->nnz > INT32_MAX)
+    return AMG_ERR_ARG;
+  if (!on_device(A->row_ptr) || !on_device(A->col) || !on_device(A->val)) return AMG_ERR_ARG;
+  amg_params P;
+  if (params) P = *params;
+  else amg_params_default(&P);
+  AMG_TRY(check_params(&P));
+  if (P.w && !on_device(P.w)) return AMG_ERR_ARG;
+  amg_hierarchy *h = new (std::nothrow) amg_hierarchy();
+  if (!h) return AMG_ERR_OOM;
+  h->params = P;
+  h->params.w = nullptr;  // not retained after setup
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return AMG_ERR_HIP;
+  }
+  // NULL selects the device's default stream, so calls are ordered with
+  // other default-stream work of the caller
+  h->stream = reinterpret_cast<hipStream_t>(P.stream);
+  h->own_stream = false;
+  amg_params Pw = P;
+  h->params.w = Pw.w;
+  amg_status st = build_hierarchy(h, A);
+  h->params.w = nullptr;
+  if (st != AMG_OK) {
+    (void)hipGetLastError();
+    destroy(h);
+    return st;
+  }
+  *out = h;
+  return AMG_OK;
+}
+
+amg_status amg_pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol,
+                         int32_t maxit, amg_solve_info *info) {
+  if (!h || !b || !x || !(rtol >= 0.0) || maxit < 0) return AMG_ERR_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return AMG_ERR_HIP;
+  return pcg(h, b, x, rtol, maxit, info);
+}
+
+amg_status amg_pcg_solve_batch(amg_hierarchy *h, int32_t k, const double *B, double *X,
+                               double rtol, int32_t maxit, amg_solve_info *info) {
+  if (!h || k < 0 || !(rtol >= 0.0) || maxit < 0) return AMG_ERR_ARG;
+  if (k == 0) return AMG_OK;
+  if (!B || !X) return AMG_ERR_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return AMG_ERR_HIP;
+  return pcg_batch(h, k, B, X, rtol, maxit, info);
+}
+
+amg_status amg_vcycle_apply(amg_hierarchy *h, const double *r, double *z) {
+  if (!h || !r || !z) return AMG_ERR_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return AMG_ERR_HIP;
+  AMG_TRY(vcycle(h, r, z, false, h->zero_flag));
+  AMG_HIP(hipStreamSynchronize(h->stream));
+  return AMG_OK;
+}
+
+void amg_free(amg_hierarchy *h) { destroy(h); }
+
+amg_status amg_num_levels(const amg_hierarchy *h, int32_t *nlev) {
+  if (!h || !nlev) return AMG_ERR_ARG;
+  *nlev = (int32_t)h->lv.size();
+  return AMG_OK;
+}
+
+amg_status amg_level_info(const amg_hierarchy *h, int32_t l, int64_t *n, int64_t *nnz) {
+  if (!h || l < 0 || l >= (int32_t)h->lv.size()) return AMG_ERR_ARG;
+  if (n) *n = h->lv[l].n;
+  if (nnz) *nnz = h->lv[l].nnz;
+  return AMG_OK;
+}
+
+amg_status amg_get_level_csr(const amg_hierarchy *h, int32_t l, int32_t *rp, int32_t *ci,
+                             double *val) {
+  if (!h || l < 0 || l >= (int32_t)h->lv.size()) return AMG_ERR_ARG;
+  const Level &L = h->lv[l];
+  if (rp) AMG_HIP(hipMemcpy(rp, L.rp, sizeof(int32_t) * (L.n + 1), hipMemcpyDeviceToHost));
+  if (ci) AMG_HIP(hipMemcpy(ci, L.ci, sizeof(int32_t) * L.nnz, hipMemcpyDeviceToHost));
+  if (val) AMG_HIP(hipMemcpy(val, L.val, sizeof(double) * L.nnz, hipMemcpyDeviceToHost));
+  return AMG_OK;
+}
+
+amg_status amg_get_transfer(const amg_hierarchy *h, int32_t l, int32_t *agg, double *p) {
+  if (!h || l < 0 || l + 1 >= (int32_t)h->lv.size()) return AMG_ERR_ARG;
+  const Level &L = h->lv[l];
+  if (agg) AMG_HIP(hipMemcpy(agg, L.agg, sizeof(int32_t) * L.n, hipMemcpyDeviceToHost));
+  if (p) AMG_HIP(hipMemcpy(p, L.p64, sizeof(double) * L.n, hipMemcpyDeviceToHost));
+  return AMG_OK;
+}
+
+amg_status amg_get_l1diag(const amg_hierarchy *h, int32_t l, double *m) {
+  if (!h || !m || l < 0 || l + 1 >= (int32_t)h->lv.size()) return AMG_ERR_ARG;
+  const Level &L = h->lv[l];
+  AMG_HIP(hipMemcpy(m, L.m, sizeof(double) * L.n, hipMemcpyDeviceToHost));
+  return AMG_OK;
+}
+
+amg_status amg_get_w(const amg_hierarchy *h, int32_t l, double *w) {
+  if (!h || !w || l < 0 || l >= (int32_t)h->lv.size()) return AMG_ERR_ARG;
+  const Level &L = h->lv[l];
+  AMG_HIP(hipMemcpy(w, L.w, sizeof(double) * L.n, hipMemcpyDeviceToHost));
+  return AMG_OK;
+}
+
+size_t amg_footprint_bytes(const amg_hierarchy *h) {
+  return h ? h->bytes + h->batch_bytes : 0;
+}
+
+size_t amg_estimate_footprint(int64_t n, int64_t nnz, const amg_params *params) {
+  amg_params P;
+  if (params) P = *params;
+  else amg_params_default(&P);
+  const double V = P.precision == AMG_FP32 ? 4.0 : 8.0;
+  // geometric bound of the level sizes (coarsening by >= 2 per sweep)
+  const double shrink = 1.0 / (1 << (P.sweeps < 1 ? 1 : P.sweeps));
+  const double sn = n / (1.0 - shrink), sz = nnz / (1.0 - shrink);
+  double b = 0;
+  b += sz * (4 + 8) + sn * 4 * 2;          // FP64 CSR of every level
+  b += 8 * sn * 2;                          // w, m
+  b += 1.01 * sz * (4 + V) + 8.0 * nnz;     // SELL (+ FP64 values of level 0)
+  b += sn * (V + 4 + V + 4 + V);            // minv, agg, p, mptr/mem, pm
+  b += 4 * V * sn;                          // V-cycle vectors
+  b += 4 * 8.0 * n;                         // CG vectors
+  // peak of the setup temporaries (weights, Galerkin staging, sweep matrices)
+  b += 8.0 * nnz + 12.0 * nnz + 2 * (12.0 * nnz + 16.0 * n);
+  const double nL = P.max_coarse;
+  b += 3 * 8.0 * nL * nL;
+  return (size_t)(b + (1 << 20));
+}
+
+amg_status amg_setup_times(const amg_hierarchy *h, double *ms) {
+  if (!h || !ms) return AMG_ERR_ARG;
+  for (int k = 0; k < 8; ++k) ms[k] = h->setup_ms[k];
+  return AMG_OK;
+}
+
+amg_status amg_matching_rounds(const amg_hierarchy *h, int32_t l, int32_t *rounds) {
+  if (!h || !rounds || l < 0 || l >= (int32_t)h->lv.size()) return AMG_ERR_ARG;
+  *rounds = h->lv[l].rounds;
+  return AMG_OK;
+}
+
+amg_status amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
+                           double *ms, double *bytes) {
+  if (!h || !ms || !bytes || kernel < 0 || kernel > 4) return AMG_ERR_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return AMG_ERR_HIP;
+  return time_kernel(h, kernel, level, reps, ms, bytes);
+}
+
+const char *amg_status_string(amg_status s) {
+  switch (s) {
+    case AMG_OK: return "ok";
+    case AMG_ERR_ARG: return "invalid argument";
+    case AMG_ERR_NOT_SYMMETRIC: return "matrix is not symmetric";
+    case AMG_ERR_NOT_SPD: return "matrix is not positive definite";
+    case AMG_ERR_STALL: return "coarsening stalled above the dense limit";
+    case AMG_ERR_OOM: return "out of device memory";
+    case AMG_ERR_HIP: return "HIP runtime error";
+    case AMG_ERR_BREAKDOWN: return "CG breakdown";
+    case AMG_NOT_CONVERGED: return "not converged";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

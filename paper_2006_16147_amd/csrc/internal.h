@@ -1,0 +1,166 @@
+// Internal declarations of the gfx950 matching-AMG library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "amg.h"
+
+namespace amg {
+
+// ---------------------------------------------------------------------------
+// error handling: every host routine returns amg_status
+// ---------------------------------------------------------------------------
+#define AMG_HIP(call)                                  \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) {                            \
+      (void)hipGetLastError();                         \
+      return e_ == hipErrorOutOfMemory ? AMG_ERR_OOM   \
+                                       : AMG_ERR_HIP;  \
+    }                                                  \
+  } while (0)
+
+#define AMG_TRY(call)                  \
+  do {                                 \
+    amg_status s_ = (call);            \
+    if (s_ != AMG_OK) return s_;       \
+  } while (0)
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kSlice = 64;       // rows per SELL slice (one wavefront)
+constexpr int kBlock = 256;      // threads per block of the streaming kernels
+constexpr int kMaxReduceBlocks = 2048;
+constexpr int kNumXcd = 8;       // MI355X: 8 XCDs, blocks dispatched round-robin
+
+// Solve-phase PCG scalars, resident on the device.
+struct PcgScal {
+  double rho;     // (r, z) of the current iterate
+  double pq;      // (p, A p)
+  double alpha, beta;
+  double rr;      // (r, r)
+  double bb;      // (b, b)
+  double rtol;
+  double tol2;    // (rtol ||b||)^2
+  double rr_true; // (b - A x, b - A x) at exit
+  int32_t iter;
+  int32_t maxit;
+  int32_t done;   // 0 running, 1 converged, 2 maxit, 3 breakdown, 4 zero rhs
+  int32_t phase;  // 0: next (r, z) initialises rho; 1: it also forms beta
+};
+
+// Sliced ELLPACK, 64 rows per slice, column-major inside a slice so that
+// lane i of a wavefront reads row i's k-th entry at consecutive addresses.
+struct Sell {
+  int32_t n = 0;
+  int32_t nslices = 0;
+  int64_t nnz_padded = 0;
+  int32_t *sptr = nullptr;  // nslices + 1 element offsets (multiples of 64)
+  int32_t *col = nullptr;
+  double *v64 = nullptr;
+  float *v32 = nullptr;
+};
+
+struct Level {
+  int32_t n = 0;
+  int64_t nnz = 0;
+  // FP64 CSR of A_l (kept for the next level's setup and introspection)
+  int32_t *rp = nullptr, *ci = nullptr;
+  double *val = nullptr;
+  double *w = nullptr;       // smooth vector restricted to this level
+  double *m = nullptr;       // l1-Jacobi diagonal (FP64)
+  Sell S;                    // solve format
+  double *minv64 = nullptr;  // 1 / m
+  float *minv32 = nullptr;
+  // transfer to level + 1 (absent on the coarsest level)
+  int32_t *agg = nullptr;    // fine row -> coarse index
+  double *p64 = nullptr;     // P(i, agg[i])
+  float *p32 = nullptr;
+  int32_t *mptr = nullptr;   // coarse index -> range of its members in mem
+  int32_t *mem = nullptr;    // members, ascending inside each aggregate
+  double *pm64 = nullptr;    // p of each member, in mem order
+  float *pm32 = nullptr;
+  // V-cycle work vectors in the hierarchy precision
+  void *r = nullptr, *z = nullptr, *t = nullptr, *y = nullptr;
+  int32_t sweeps = 0;
+  int32_t rounds = 0;
+};
+
+struct Coarse {
+  int32_t n = 0;
+  double *Linv = nullptr;   // L^-1, row-major n x n (lower triangular)
+  double *LinvT = nullptr;  // (L^-1)^T, row-major
+};
+
+}  // namespace amg
+
+struct amg_hierarchy {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  amg_params params{};
+  std::vector<amg::Level> lv;
+  amg::Coarse C;
+  // outer PCG state (FP64, level-0 size)
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *partials = nullptr;     // kMaxReduceBlocks x 4
+  unsigned *ticket = nullptr;     // last-block counters (4)
+  amg::PcgScal *scal = nullptr;   // device
+  amg::PcgScal *scal_host = nullptr;  // pinned mirror
+  int32_t *zero_flag = nullptr;   // device int 0 (for kernels outside CG)
+  // batch solve state (allocated on first use)
+  int32_t batch_k = 0;
+  void *batch_mem = nullptr;
+  size_t batch_bytes = 0;
+  // graph of one CG iteration
+  hipGraphExec_t iter_exec = nullptr;
+  hipGraph_t iter_graph = nullptr;
+  // bookkeeping
+  std::vector<void *> allocs;
+  size_t bytes = 0;
+  double setup_ms[8] = {0};
+};
+
+namespace amg {
+
+// allocation owned by the hierarchy (freed in amg_free)
+amg_status dev_alloc(amg_hierarchy *h, void **p, size_t bytes);
+template <typename T>
+inline amg_status dalloc(amg_hierarchy *h, T **p, size_t count) {
+  return dev_alloc(h, reinterpret_cast<void **>(p), count * sizeof(T) + 16);
+}
+void dev_release(amg_hierarchy *h, void *p);
+
+// exclusive prefix sum of n int32 values; writes n + 1 outputs (out[n] = total)
+amg_status scan_exclusive_i32(const int32_t *in, int32_t *out, int32_t n, hipStream_t s);
+
+// setup (setup.hip)
+amg_status build_hierarchy(amg_hierarchy *h, const amg_csr *A);
+
+// solve-phase helpers (solve.hip)
+amg_status build_solve_formats(amg_hierarchy *h);
+amg_status vcycle(amg_hierarchy *h, const double *r, double *z, bool fuse_dot, const int32_t *done);
+amg_status pcg(amg_hierarchy *h, const double *b, double *x, double rtol, int32_t maxit,
+               amg_solve_info *info);
+amg_status pcg_batch(amg_hierarchy *h, int32_t k, const double *B, double *X, double rtol,
+                     int32_t maxit, amg_solve_info *info);
+amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
+                       double *ms, double *bytes);
+
+// grid helpers
+inline int32_t ceil_div(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
+
+// XCD-aware block index: blocks are dispatched round-robin over the XCDs, so
+// block b runs on XCD b % 8. Remap so that each XCD owns a contiguous range of
+// logical blocks (neighbouring rows share that XCD's L2).
+__device__ __forceinline__ int32_t xcd_block(int32_t b, int32_t nb) {
+  int32_t per = nb / kNumXcd;
+  if (per == 0) return b;
+  int32_t full = per * kNumXcd;
+  if (b >= full) return b;
+  return (b % kNumXcd) * per + b / kNumXcd;
+}
+
+}  // namespace amg

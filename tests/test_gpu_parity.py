@@ -1,0 +1,236 @@
+"""GPU parity of the HIP library (through the C ABI) against the CPU oracle.
+
+Hierarchies (sizes, sparsity, values, aggregates, prolongators, restricted
+w, l1 diagonals) must be bit-exact. Solutions are compared at equal
+iteration counts (oracle run with rtol = 0 and maxit = the GPU's count),
+within 1e-8 relative in FP64; iteration counts within +-1.
+"""
+
+import numpy as np
+import pytest
+
+from paper_2006_16147_amd import inputs
+
+from gpu_helpers import assert_same_hierarchy, setup, setup_status, solve, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2006_16147_amd import amg
+
+    amg.load_library()
+    torch.cuda.set_device(0)
+
+
+# ---------------------------------------------------------------------------
+# setup: bit-exact hierarchies
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [2, 5, 8, 13, 20, 24])
+def test_setup_poisson_bit_exact(orc, N):
+    A = inputs.laplacian7(N)
+    h = setup(A)
+    ho = orc.Hierarchy(A)
+    assert_same_hierarchy(h, ho)
+
+
+@pytest.mark.parametrize("sweeps,max_coarse", [(1, 50), (2, 30), (4, 10)])
+def test_setup_sweeps_variants(orc, sweeps, max_coarse):
+    A = inputs.laplacian7(12)
+    h = setup(A, sweeps=sweeps, max_coarse=max_coarse)
+    ho = orc.Hierarchy(A, sweeps=sweeps, max_coarse=max_coarse)
+    assert_same_hierarchy(h, ho)
+
+
+def test_setup_anisotropic_blocks_bit_exact(orc):
+    rng = np.random.default_rng(2)
+    ex, ey = inputs.block_log_uniform_eps(24, 8, rng)
+    A = inputs.diffusion7(24, ex, ey, 1.0)
+    h = setup(A)
+    ho = orc.Hierarchy(A)
+    assert_same_hierarchy(h, ho)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_setup_random_spd_with_w(orc, seed):
+    A = inputs.random_spd_graph(3000 + 17 * seed, 7.0, seed=seed)
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.5, 2.0, A.n) * rng.choice([-1.0, 1.0], A.n)
+    st, h = setup_status(A, w=w, max_coarse=40)
+    assert st == 0
+    ho = orc.Hierarchy(A, w=w, max_coarse=40)
+    assert_same_hierarchy(h, ho)
+
+
+def test_setup_long_rows_take_block_path(orc):
+    """A hub vertex of degree 300 makes coarse rows exceed the per-thread
+    buffer; the block-per-row Galerkin path must give the same bits."""
+    A = inputs.random_spd_graph(2000, 4.0, seed=7, hub_degree=300)
+    h = setup(A, max_coarse=30)
+    ho = orc.Hierarchy(A, max_coarse=30)
+    assert_same_hierarchy(h, ho)
+
+
+def test_setup_degenerate_cases(orc):
+    from paper_2006_16147_amd import amg
+
+    # n = 1
+    one = inputs.Csr(1, [0, 1], [0], [3.0])
+    h = setup(one)
+    assert h.sizes() == [1]
+    # n <= max_coarse: a single level solved directly
+    A = inputs.laplacian7(5)
+    h = setup(A)
+    assert h.sizes() == [125]
+    # no off-diagonal entries: nothing to match
+    n = 300
+    D = inputs.Csr(n, np.arange(n + 1), np.arange(n), np.full(n, 2.0))
+    h = setup(D, max_coarse=10)
+    assert h.sizes() == [n]
+    n = 5000
+    D = inputs.Csr(n, np.arange(n + 1), np.arange(n), np.full(n, 2.0))
+    st, _ = setup_status(D, max_coarse=10)
+    assert st == amg.Status.ERR_STALL
+    assert orc.Hierarchy(D, max_coarse=10).status == orc.Status.ERR_STALL
+
+
+def test_setup_error_codes(orc):
+    from paper_2006_16147_amd import amg
+
+    A = inputs.laplacian7(4)
+    bad = inputs.Csr(A.n, A.row_ptr, A.col, A.val.copy())
+    bad.val[1] = -0.5
+    assert setup_status(bad)[0] == amg.Status.ERR_NOT_SYMMETRIC
+    neg = inputs.Csr(A.n, A.row_ptr, A.col, A.val.copy())
+    neg.val[0] = -6.0
+    assert setup_status(neg)[0] == amg.Status.ERR_NOT_SPD
+    uns = inputs.Csr(A.n, A.row_ptr, A.col.copy(), A.val)
+    uns.col[[0, 1]] = uns.col[[1, 0]]
+    assert setup_status(uns)[0] == amg.Status.ERR_ARG
+    w = np.ones(A.n)
+    w[3] = 0.0
+    assert setup_status(A, w=w)[0] == amg.Status.ERR_ARG
+    assert setup_status(A, sweeps=0)[0] == amg.Status.ERR_ARG
+    # indefinite coarsest: positive diagonal, symmetric, but not SPD
+    M = inputs.Csr(3, [0, 3, 6, 9], [0, 1, 2] * 3, [1.0, 2.0, 2.0, 2.0, 1.0, 2.0, 2.0, 2.0, 1.0])
+    assert setup_status(M)[0] == amg.Status.ERR_NOT_SPD
+
+
+def test_setup_is_deterministic():
+    A = inputs.diffusion7(16, 0.01, 1.0, 0.3)
+    h1, h2 = setup(A), setup(A)
+    assert h1.sizes() == h2.sizes()
+    for l in range(h1.num_levels):
+        a, b = h1.level_csr(l), h2.level_csr(l)
+        for u, v in zip(a, b):
+            np.testing.assert_array_equal(u, v)
+
+
+# ---------------------------------------------------------------------------
+# solve: V-cycle and PCG
+# ---------------------------------------------------------------------------
+
+def test_vcycle_matches_oracle(orc):
+    import torch
+
+    from paper_2006_16147_amd import amg
+
+    A = inputs.laplacian7(20)
+    h = setup(A)
+    ho = orc.Hierarchy(A)
+    r = np.random.default_rng(4).uniform(-1, 1, A.n)
+    z = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    amg.amg_vcycle_apply(h, to_dev(r), z)
+    zo = ho.vcycle(r)
+    np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=1e-12 * np.abs(zo).max())
+
+
+@pytest.mark.parametrize("case", ["poisson20", "aniso24", "random"])
+def test_pcg_matches_oracle_at_equal_iterations(orc, case):
+    if case == "poisson20":
+        c = inputs.small_case(20, seed=0)
+        A, b, rtol = c["A"], c["b"], c["rtol"]
+    elif case == "aniso24":
+        rng = np.random.default_rng(2)
+        ex, ey = inputs.block_log_uniform_eps(24, 8, rng)
+        A = inputs.diffusion7(24, ex, ey, 1.0)
+        b = rng.uniform(-1, 1, A.n)
+        rtol = 1e-8
+    else:
+        A = inputs.random_spd_graph(4000, 6.0, seed=3)
+        b = np.random.default_rng(3).uniform(-1, 1, A.n)
+        rtol = 1e-8
+    h = setup(A)
+    ho = orc.Hierarchy(A)
+    st, info, x = solve(h, b, rtol=rtol, maxit=500)
+    assert st == 0 and info["converged"], info
+    xo_conv, io = ho.pcg(b, rtol=rtol, maxit=500)
+    assert abs(info["iterations"] - io["iterations"]) <= 1, (info, io)
+    k = info["iterations"]
+    xo, _ = ho.pcg(b, rtol=0.0, maxit=k)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    assert err < 1e-8, err
+    assert info["rel_res_true"] <= rtol * 1.001
+
+
+def test_pcg_edge_cases(orc):
+    from paper_2006_16147_amd import amg
+
+    c = inputs.small_case(8, seed=0)
+    A, b = c["A"], c["b"]
+    h = setup(A, max_coarse=20)
+    # b = 0: x = 0 after 0 iterations, even from a nonzero x0
+    st, info, x = solve(h, np.zeros(A.n), x0=np.ones(A.n))
+    assert st == 0 and info["iterations"] == 0 and not x.any()
+    # rtol = 0 runs exactly maxit iterations
+    st, info, x = solve(h, b, rtol=0.0, maxit=3)
+    assert st == amg.Status.NOT_CONVERGED and info["iterations"] == 3
+    ho = orc.Hierarchy(A, max_coarse=20)
+    xo, _ = ho.pcg(b, rtol=0.0, maxit=3)
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-10
+    # maxit = 0 with a nonzero residual
+    st, info, x = solve(h, b, rtol=1e-8, maxit=0)
+    assert st == amg.Status.NOT_CONVERGED and info["iterations"] == 0
+    # nonzero initial guess
+    x0 = np.random.default_rng(1).uniform(-1, 1, A.n)
+    st, info, x = solve(h, b, x0=x0, rtol=1e-10, maxit=100)
+    assert st == 0
+    xo, io = ho.pcg(b, x0=x0, rtol=0.0, maxit=info["iterations"])
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8
+    # single-level hierarchy: one iteration is a direct solve
+    A5 = inputs.laplacian7(5)
+    h5 = setup(A5)
+    b5 = np.random.default_rng(0).uniform(-1, 1, A5.n)
+    st, info, x = solve(h5, b5, rtol=1e-12)
+    assert st == 0 and info["iterations"] == 1
+
+
+def test_pcg_deterministic_bitwise():
+    c = inputs.small_case(20, seed=0)
+    h = setup(c["A"])
+    _, i1, x1 = solve(h, c["b"], rtol=1e-10)
+    _, i2, x2 = solve(h, c["b"], rtol=1e-10)
+    assert i1["iterations"] == i2["iterations"]
+    np.testing.assert_array_equal(x1.view(np.uint64), x2.view(np.uint64))
+
+
+def test_fp32_hierarchy_reaches_fp64_residual(orc):
+    from paper_2006_16147_amd import amg
+
+    c = inputs.small_case(20, seed=0)
+    A, b = c["A"], c["b"]
+    h64 = setup(A)
+    h32 = setup(A, precision=amg.FP32)
+    st, i32, x32 = solve(h32, b, rtol=1e-8)
+    st64, i64, x64 = solve(h64, b, rtol=1e-8)
+    assert st == 0 and i32["converged"]
+    assert i32["rel_res_true"] <= 1.01e-8
+    assert abs(i32["iterations"] - i64["iterations"]) <= 2
+    xo, _ = orc.Hierarchy(A).pcg(b, rtol=1e-12)
+    err = np.linalg.norm(x32 - xo) / np.linalg.norm(xo)
+    assert err < 1e-6, err
