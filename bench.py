@@ -1,0 +1,284 @@
+#!/usr/bin/env python
+"""Benchmark of the matching-AMG preconditioned CG on one MI355X.
+
+Workload: 3D Poisson, 7-point Laplacian on the 160^3 interior grid
+(n = 4 096 000, nnz = 28 518 400), b = A u with u ~ U(-1, 1) (seed 1),
+x0 = 0, PCG to a relative residual of 1e-8. Hierarchy: 3 pairwise matching
+sweeps per level with w = 1, unsmoothed prolongator, 1 + 1 l1-Jacobi sweeps,
+coarsest level (<= 200 unknowns) solved by dense Cholesky.
+
+One step is one complete PCG solve (the hierarchy is built once, before the
+timed region, as the solver reuses it across right-hand sides). The headline
+value is the p99 solve time with the FP64 hierarchy; the same system solved
+with the FP32 hierarchy (FP64 outer CG) is reported beside it, as are the
+V-cycle bandwidths, the dominant kernel's roofline position and the FP64 CPU
+oracle timed on the host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "AMG-PCG solve ms & V-cycle HBM GB/s (160^3 Poisson), FP32-prec vs FP64; p99"
+HBM_PEAK_GBS = 8000.0
+KERNEL_NAMES = {0: "pre-smoothing + residual", 1: "post-smoothing", 2: "restriction",
+                3: "prolongation", 4: "outer-CG SpMV + dot"}
+
+
+def source_hash() -> str:
+    """Hash of the HIP sources (ties stored counter readings to a build)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2006_16147_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def vcycle_bytes(sizes, nnzs, V, nL):
+    """Algorithmic HBM bytes of one V-cycle with this library's kernel set.
+
+    Per level l < L (n rows, z entries, nc coarse rows; Vr = 8 on level 0,
+    whose right-hand side and output are the FP64 CG vectors, else V):
+      pre-smoothing + residual  z (V + 4) + 4 (n + 1) + n (Vr + 3 V)
+      restriction               n (4 + 2 V) + 4 (nc + 1) + nc V
+      prolongation              n (4 + 3 V) + nc V
+      post-smoothing            z (V + 4) + 4 (n + 1) + n (2 Vr + 2 V)
+    each array read or written once (CSR values, int32 columns and int32
+    row offsets for the SpMVs); plus the coarsest solve, which reads the two
+    triangular factors of the inverse Cholesky factor and its vectors."""
+    total = 0.0
+    L = len(sizes) - 1
+    for l in range(L):
+        n, z, nc = sizes[l], nnzs[l], sizes[l + 1]
+        Vr = 8.0 if l == 0 else V
+        total += z * (V + 4) + 4 * (n + 1) + n * (Vr + 3 * V)
+        total += n * (4 + 2 * V) + 4 * (nc + 1) + nc * V
+        total += n * (4 + 3 * V) + nc * V
+        total += z * (V + 4) + 4 * (n + 1) + n * (2 * Vr + 2 * V)
+    total += 2 * 8.0 * nL * (nL + 1) / 2 + 2 * nL * (8.0 if L == 0 else V)
+    return total
+
+
+def percentile(a, q):
+    return float(np.percentile(np.asarray(a), q))
+
+
+def load_traffic(kernel_key):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel_key)
+    if not k:
+        return None
+    return float(k["bytes_per_launch"])
+
+
+def cpu_baseline(case, gpu_iters):
+    import oracle
+
+    t0 = time.perf_counter()
+    ho = oracle.Hierarchy(case["A"])
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    x, info = ho.pcg(case["b"], rtol=case["rtol"], maxit=1000)
+    t_solve = time.perf_counter() - t0
+    return {
+        "value": round(t_solve * 1e3, 1),
+        "unit": "ms",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": ("one complete FP64 oracle PCG solve of the same 160^3 system to rtol 1e-8 "
+                   "(%d iterations; GPU: %d); oracle setup %.0f ms, not included"
+                   % (info["iterations"], gpu_iters, t_setup * 1e3)),
+        "setup_ms": round(t_setup * 1e3, 1),
+        "iterations": info["iterations"],
+        "rel_res_true": info["rel_res_true"],
+    }, x
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--N", type=int, default=160)
+    ap.add_argument("--vcycles", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2006_16147_amd import amg, inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    amg.load_library()
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)  # noqa: E731
+
+    case = inputs.headline_case(args.N, seed=1)
+    A = case["A"]
+    log("problem %d^3: n=%d nnz=%d" % (args.N, A.n, A.nnz))
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    ci = torch.from_numpy(A.col).to(dev)
+    va = torch.from_numpy(A.val).to(dev)
+    b = torch.from_numpy(case["b"]).to(dev)
+    rtol = case["rtol"]
+
+    res = {}
+    hier = {}
+    for prec, name in ((amg.FP64, "fp64"), (amg.FP32, "fp32_prec")):
+        setup_ms = []
+        for rep in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = amg.amg_setup(rp, ci, va, precision=prec)
+            torch.cuda.synchronize()
+            setup_ms.append((time.perf_counter() - t0) * 1e3)
+            if rep < 2:
+                h.close()
+        hier[name] = h
+        res[name] = {"setup_ms_min": round(min(setup_ms), 2),
+                     "setup_stages_ms": {k: round(v, 2) for k, v in h.setup_times().items()},
+                     "levels": h.sizes(), "opc": round(h.opc(), 5)}
+        log(name, "setup %.1f ms, levels %s" % (min(setup_ms), h.sizes()))
+
+    x = torch.zeros_like(b)
+
+    def one_solve(h):
+        x.zero_()
+        st, info = amg.amg_pcg_solve(h, b, x, rtol=rtol, maxit=1000)
+        if st != amg.Status.OK:
+            raise RuntimeError("solve failed: %s" % info)
+        return info
+
+    for name in ("fp64", "fp32_prec"):
+        h = hier[name]
+        for _ in range(args.warmup):
+            one_solve(h)
+        times = []
+        torch.cuda.synchronize()
+        t_all = time.perf_counter()
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            info = one_solve(h)
+            times.append((time.perf_counter() - t0) * 1e3)
+        torch.cuda.synchronize()
+        total = (time.perf_counter() - t_all) * 1e3
+        xg = x.cpu().numpy()
+        err_u = float(np.linalg.norm(xg - case["u"]) / np.linalg.norm(case["u"]))
+        res[name].update({
+            "p50_ms": round(percentile(times, 50), 3), "p99_ms": round(percentile(times, 99), 3),
+            "mean_ms": round(total / args.steps, 3), "iterations": info["iterations"],
+            "rel_res_true": info["rel_res_true"], "err_vs_u": err_u,
+            "ms_per_iteration": round(percentile(times, 50) / max(info["iterations"], 1), 4),
+        })
+        res[name]["_x"] = xg
+        log(name, "solve p50 %.2f ms p99 %.2f ms, %d it, true rel res %.2e" % (
+            res[name]["p50_ms"], res[name]["p99_ms"], info["iterations"], info["rel_res_true"]))
+
+    # V-cycle bandwidth (algorithmic bytes / time of repeated applications)
+    r = torch.from_numpy(np.random.default_rng(7).uniform(-1, 1, A.n)).to(dev)
+    z = torch.zeros_like(r)
+    for name, V in (("fp64", 8.0), ("fp32_prec", 4.0)):
+        h = hier[name]
+        for _ in range(3):
+            amg.amg_vcycle_apply(h, r, z)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.vcycles):
+            amg.amg_vcycle_apply(h, r, z)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.vcycles
+        by = vcycle_bytes(h.sizes(), h.nnzs(), V, h.sizes()[-1])
+        res[name]["vcycle_ms"] = round(ms, 4)
+        res[name]["vcycle_gbs"] = round(by / ms / 1e6, 1)
+        res[name]["vcycle_bytes"] = by
+        log(name, "V-cycle %.3f ms, %.0f GB/s algorithmic" % (ms, by / ms / 1e6))
+
+    # dominant level-0 kernel of the FP64 solve, timed with HIP events on the
+    # hierarchy's stream
+    h = hier["fp64"]
+    kt = {}
+    for k in KERNEL_NAMES:
+        ms, by = h.time_kernel(k, 0, reps=20)
+        kt[k] = (ms, by)
+    per_solve = {k: kt[k][0] for k in (0, 1, 4)}  # each launches once per iteration
+    dom = max(per_solve, key=per_solve.get)
+    ms, by = kt[dom]
+    achieved = by / ms / 1e6
+    traffic = load_traffic("fp64_level0_%d" % dom)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": KERNEL_NAMES[dom] + " (level 0, FP64)",
+                "kernel_ms": round(ms, 4), "algorithmic_bytes": by}
+    res["level0_kernels"] = {KERNEL_NAMES[k]: {"ms": round(v[0], 4),
+                                               "GB/s": round(v[1] / v[0] / 1e6, 1)}
+                             for k, v in kt.items()}
+    log("dominant kernel:", roofline)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle ...")
+        cpu, xo = cpu_baseline(case, res["fp64"]["iterations"])
+        xg = res["fp64"]["_x"]
+        res["fp64"]["rel_diff_vs_oracle"] = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+        log("cpu baseline:", cpu)
+    for name in ("fp64", "fp32_prec"):
+        res[name].pop("_x", None)
+
+    line = {
+        "metric": METRIC,
+        "value": res["fp64"]["p99_ms"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["fp64"]["mean_ms"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "poisson7_%d^3_b=Au_seed1_rtol1e-8" % args.N, "n": A.n,
+                   "nnz": A.nnz, "rtol": rtol,
+                   "hierarchy": "matching, 3 sweeps, w=1, l1-Jacobi 1+1, dense Cholesky <=200"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64": res["fp64"],
+        "fp32_prec": res["fp32_prec"],
+        "fp32_prec_speedup_p50": round(res["fp64"]["p50_ms"] / res["fp32_prec"]["p50_ms"], 3),
+        "level0_kernels": res["level0_kernels"],
+        "source_hash": source_hash(),
+    }
+    for hh in hier.values():
+        hh.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

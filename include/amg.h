@@ -178,6 +178,11 @@ amg_status amg_matching_rounds(const amg_hierarchy *h, int32_t l, int32_t *round
 amg_status amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
                            double *ms, double *bytes);
 
+/* Column tile the batch solve's autotuner chose for the last k used with
+ * this hierarchy (the V-cycle covers 64 / tile rows x tile columns per
+ * wavefront); 0 before any batch solve. */
+amg_status amg_batch_tile(const amg_hierarchy *h, int32_t *tile);
+
 const char *amg_status_string(amg_status s);
 
 #ifdef __cplusplus

@@ -31,7 +31,7 @@ EXPORTED_SYMBOLS = (
     "amg_vcycle_apply", "amg_free", "amg_num_levels", "amg_level_info", "amg_get_level_csr",
     "amg_get_transfer", "amg_get_l1diag", "amg_get_w", "amg_footprint_bytes",
     "amg_estimate_footprint", "amg_setup_times", "amg_matching_rounds", "amg_time_kernel",
-    "amg_status_string",
+    "amg_batch_tile", "amg_status_string",
 )
 
 
@@ -111,6 +111,7 @@ def load_library():
         "amg_setup_times": (C.c_int, [V, V]),
         "amg_matching_rounds": (C.c_int, [V, I32, P(I32)]),
         "amg_time_kernel": (C.c_int, [V, I32, I32, I32, P(D), P(D)]),
+        "amg_batch_tile": (C.c_int, [V, P(I32)]),
         "amg_status_string": (C.c_char_p, [C.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -251,6 +252,11 @@ class Hierarchy:
         v = C.c_int32()
         self._check(load_library().amg_matching_rounds(self._h, l, C.byref(v)),
                     "amg_matching_rounds")
+        return int(v.value)
+
+    def batch_tile(self) -> int:
+        v = C.c_int32()
+        self._check(load_library().amg_batch_tile(self._h, C.byref(v)), "amg_batch_tile")
         return int(v.value)
 
     def time_kernel(self, kernel, level=0, reps=20):

@@ -20,6 +20,12 @@ amg_status dev_alloc(amg_hierarchy *h, void **p, size_t bytes) {
   return AMG_OK;
 }
 
+amg_status join_user_stream(amg_hierarchy *h) {
+  AMG_HIP(hipEventRecord(h->join_event, h->user_stream));
+  AMG_HIP(hipStreamWaitEvent(h->stream, h->join_event, 0));
+  return AMG_OK;
+}
+
 void dev_release(amg_hierarchy *h, void *p) {
   for (auto &q : h->allocs)
     if (q == p) {
@@ -47,9 +53,10 @@ void destroy(amg_hierarchy *h) {
   if (h->iter_graph) (void)hipGraphDestroy(h->iter_graph);
   for (void *p : h->allocs)
     if (p) (void)hipFree(p);
-  if (h->batch_mem) (void)hipFree(h->batch_mem);
+  if (h->batch) free_batch(h->batch);
   if (h->scal_host) (void)hipHostFree(h->scal_host);
-  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  if (h->join_event) (void)hipEventDestroy(h->join_event);
+  if (h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
 }
 
@@ -108,10 +115,20 @@ amg_status amg_setup(const amg_csr *A, const amg_params *params, amg_hierarchy *
     delete h;
     return AMG_ERR_HIP;
   }
-  // NULL selects the device's default stream, so calls are ordered with
-  // other default-stream work of the caller
-  h->stream = reinterpret_cast<hipStream_t>(P.stream);
-  h->own_stream = false;
+  // all work runs on the library's own stream (default priority), ordered
+  // after the caller's stream (NULL: the device's default stream) at every
+  // entry point; every entry point returns after its work has completed
+  h->user_stream = reinterpret_cast<hipStream_t>(P.stream);
+  if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->join_event, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    destroy(h);
+    return AMG_ERR_HIP;
+  }
+  if (join_user_stream(h) != AMG_OK) {
+    destroy(h);
+    return AMG_ERR_HIP;
+  }
   amg_params Pw = P;
   h->params.w = Pw.w;
   amg_status st = build_hierarchy(h, A);
@@ -129,6 +146,7 @@ amg_status amg_pcg_solve(amg_hierarchy *h, const double *b, double *x, double rt
                          int32_t maxit, amg_solve_info *info) {
   if (!h || !b || !x || !(rtol >= 0.0) || maxit < 0) return AMG_ERR_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return AMG_ERR_HIP;
+  AMG_TRY(join_user_stream(h));
   return pcg(h, b, x, rtol, maxit, info);
 }
 
@@ -138,12 +156,14 @@ amg_status amg_pcg_solve_batch(amg_hierarchy *h, int32_t k, const double *B, dou
   if (k == 0) return AMG_OK;
   if (!B || !X) return AMG_ERR_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return AMG_ERR_HIP;
+  AMG_TRY(join_user_stream(h));
   return pcg_batch(h, k, B, X, rtol, maxit, info);
 }
 
 amg_status amg_vcycle_apply(amg_hierarchy *h, const double *r, double *z) {
   if (!h || !r || !z) return AMG_ERR_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return AMG_ERR_HIP;
+  AMG_TRY(join_user_stream(h));
   AMG_TRY(vcycle(h, r, z, false, h->zero_flag));
   AMG_HIP(hipStreamSynchronize(h->stream));
   return AMG_OK;
@@ -238,7 +258,13 @@ amg_status amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int3
                            double *ms, double *bytes) {
   if (!h || !ms || !bytes || kernel < 0 || kernel > 4) return AMG_ERR_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return AMG_ERR_HIP;
+  AMG_TRY(join_user_stream(h));
   return time_kernel(h, kernel, level, reps, ms, bytes);
+}
+
+amg_status amg_batch_tile(const amg_hierarchy *h, int32_t *kt) {
+  if (!h || !kt) return AMG_ERR_ARG;
+  return batch_kt(h, kt);
 }
 
 const char *amg_status_string(amg_status s) {

@@ -32,7 +32,7 @@ namespace amg {
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kSlice = 64;       // rows per SELL slice (one wavefront)
 constexpr int kBlock = 256;      // threads per block of the streaming kernels
-constexpr int kMaxReduceBlocks = 2048;
+constexpr int kMaxParts = 65536;   // most blocks of a reducing kernel (partials buffer)
 constexpr int kNumXcd = 8;       // MI355X: 8 XCDs, blocks dispatched round-robin
 
 // Solve-phase PCG scalars, resident on the device.
@@ -91,32 +91,52 @@ struct Level {
 struct Coarse {
   int32_t n = 0;
   double *Linv = nullptr;   // L^-1, row-major n x n (lower triangular)
-  double *LinvT = nullptr;  // (L^-1)^T, row-major
+  double *Ainv = nullptr;   // A_L^-1 = L^-T L^-1, row-major n x n
 };
+
+// Multi-right-hand-side state: n_l x k row-major blocks on every level, the
+// FP64 CG blocks on level 0 and per-column CG scalars.
+struct Batch {
+  int32_t k = 0;
+  int32_t kt = 0;  // autotuned column tile (rows per wavefront = 64 / kt)
+  std::vector<void *> r, z, t, y;  // per level, hierarchy precision
+  double *X = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr;
+  double *partials = nullptr;  // 2 x kBatchBlocks x k
+  double *col = nullptr;       // per-column scalars, 8 x k (see batch.hip)
+  int32_t *iter = nullptr, *done = nullptr, *all_done = nullptr;
+  double *col_host = nullptr;  // pinned mirrors
+  int32_t *iter_host = nullptr, *done_host = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<void *> allocs;
+  size_t bytes = 0;
+};
+
+void free_batch(Batch *b);
 
 }  // namespace amg
 
 struct amg_hierarchy {
   int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
+  hipStream_t stream = nullptr;       // the library's own work stream
+  hipStream_t user_stream = nullptr;  // amg_params.stream (NULL: default stream)
+  hipEvent_t join_event = nullptr;    // orders the work stream after the caller's
   amg_params params{};
   std::vector<amg::Level> lv;
   amg::Coarse C;
   // outer PCG state (FP64, level-0 size)
-  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
-  double *partials = nullptr;     // kMaxReduceBlocks x 4
-  unsigned *ticket = nullptr;     // last-block counters (4)
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *partials = nullptr;     // 2 x kMaxParts block partial sums
   amg::PcgScal *scal = nullptr;   // device
   amg::PcgScal *scal_host = nullptr;  // pinned mirror
   int32_t *zero_flag = nullptr;   // device int 0 (for kernels outside CG)
-  // batch solve state (allocated on first use)
-  int32_t batch_k = 0;
-  void *batch_mem = nullptr;
+  // batch (multi-right-hand-side) solve state, allocated for the last k used
+  amg::Batch *batch = nullptr;
   size_t batch_bytes = 0;
   // graph of one CG iteration
   hipGraphExec_t iter_exec = nullptr;
   hipGraph_t iter_graph = nullptr;
+  bool graph_failed = false;
   // bookkeeping
   std::vector<void *> allocs;
   size_t bytes = 0;
@@ -133,6 +153,9 @@ inline amg_status dalloc(amg_hierarchy *h, T **p, size_t count) {
 }
 void dev_release(amg_hierarchy *h, void *p);
 
+// orders the work stream after everything queued so far on the caller's stream
+amg_status join_user_stream(amg_hierarchy *h);
+
 // exclusive prefix sum of n int32 values; writes n + 1 outputs (out[n] = total)
 amg_status scan_exclusive_i32(const int32_t *in, int32_t *out, int32_t n, hipStream_t s);
 
@@ -146,6 +169,7 @@ amg_status pcg(amg_hierarchy *h, const double *b, double *x, double rtol, int32_
                amg_solve_info *info);
 amg_status pcg_batch(amg_hierarchy *h, int32_t k, const double *B, double *X, double rtol,
                      int32_t maxit, amg_solve_info *info);
+amg_status batch_kt(const amg_hierarchy *h, int32_t *kt);
 amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
                        double *ms, double *bytes);
 

@@ -237,7 +237,7 @@ __device__ __forceinline__ bool better(double c1, int32_t lo1, int32_t hi1, doub
 // For every free vertex: keep its proposal if the proposed vertex is still
 // free (the free set only shrinks, so it is still the best), else propose to
 // the best free neighbour under the strict key; a free vertex with no free
-// neighbour becomes a singleton. Counts vertices still proposing.
+// neighbour becomes a singleton. Flags the round if any vertex still proposes.
 __global__ void k_match_propose(int32_t n, const int32_t *rp, const int32_t *ci,
                                 const double *c, int32_t *mate, int32_t *cand,
                                 int32_t *active) {
@@ -266,8 +266,9 @@ __global__ void k_match_propose(int32_t n, const int32_t *rp, const int32_t *ci,
       if (best < 0) mate[v] = kDead; else live = true;
     }
   }
-  const unsigned long long bal = __ballot(live);
-  if ((threadIdx.x & (kWave - 1)) == 0 && bal) atomicAdd(active, (int32_t)__popcll(bal));
+  // one plain store per block that still has a proposing vertex (a per-wave
+  // atomic on one counter serialises tens of thousands of waves per round)
+  if (__syncthreads_or(live) && threadIdx.x == 0) *active = 1;
 }
 
 // Mutual proposals are locally dominant edges: match them.
@@ -625,6 +626,16 @@ __global__ void k_tri_inverse(int32_t n, const double *L, double *X, double *XT)
   }
 }
 
+// A^-1 = L^-T L^-1: entry (i, j) sums X(k, i) X(k, j) over k >= max(i, j)
+__global__ void k_inverse_from_factor(int32_t n, const double *X, double *Ainv) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int32_t i = (int32_t)(e / n), j = (int32_t)(e % n);
+  double s = 0.0;
+  for (int32_t k = max(i, j); k < n; ++k) s += X[(int64_t)k * n + i] * X[(int64_t)k * n + j];
+  Ainv[e] = s;
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -977,9 +988,12 @@ amg_status build_hierarchy(amg_hierarchy *h, const amg_csr *A) {
     AMG_TRY(read_i32(err, &herr, s));
     if (herr) return AMG_ERR_NOT_SPD;
     h->C.n = nL;
+    double *LinvT;
+    AMG_TRY(tmp.get(&LinvT, (size_t)nL * nL));
     AMG_TRY(dalloc(h, &h->C.Linv, (size_t)nL * nL));
-    AMG_TRY(dalloc(h, &h->C.LinvT, (size_t)nL * nL));
-    k_tri_inverse<<<grid(nL), kBlock, 0, s>>>(nL, D, h->C.Linv, h->C.LinvT);
+    AMG_TRY(dalloc(h, &h->C.Ainv, (size_t)nL * nL));
+    k_tri_inverse<<<grid(nL), kBlock, 0, s>>>(nL, D, h->C.Linv, LinvT);
+    k_inverse_from_factor<<<grid((int64_t)nL * nL), kBlock, 0, s>>>(nL, h->C.Linv, h->C.Ainv);
     AMG_HIP(hipStreamSynchronize(s));
   }
   T[5] = now_ms() - ts;

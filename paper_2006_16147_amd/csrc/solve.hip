@@ -47,10 +47,11 @@ struct Geom {
 };
 
 Geom geom(int64_t n, bool reduce) {
+  (void)reduce;
   int64_t blocks = (n + kBlock - 1) / kBlock;
   if (blocks < 1) blocks = 1;
-  if (reduce && blocks > kMaxReduceBlocks) {
-    int64_t chunk = ((n + kMaxReduceBlocks - 1) / kMaxReduceBlocks + kBlock - 1) / kBlock * kBlock;
+  if (blocks > kMaxParts) {
+    int64_t chunk = ((n + kMaxParts - 1) / kMaxParts + kBlock - 1) / kBlock * kBlock;
     return {ceil_div(n, chunk), (int32_t)chunk};
   }
   return {(int32_t)blocks, kBlock};
@@ -64,11 +65,15 @@ __device__ __forceinline__ void rows_of_block(int32_t n, int32_t chunk, int32_t 
 }
 
 // ---------------------------------------------------------------------------
-// deterministic two-stage reductions
+// deterministic two-stage reductions: every block writes its partial sums;
+// a one-block finalize kernel adds them in block order and updates the CG
+// scalars. (No in-kernel cross-block handshake: on gfx950 a device-scope
+// fence per block writes back the XCD's L2 and costs more than a launch.)
 // ---------------------------------------------------------------------------
 
 template <int NV>
-__device__ void block_sum(double (&v)[NV], double (*sh)[kBlock / kWave]) {
+__device__ void block_partial(double (&v)[NV], double *partials) {
+  __shared__ double sh[NV][kBlock / kWave];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
@@ -80,47 +85,80 @@ __device__ void block_sum(double (&v)[NV], double (*sh)[kBlock / kWave]) {
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      double s = sh[q][0];
-      for (int k = 1; k < kBlock / kWave; ++k) s += sh[q][k];
-      v[q] = s;
+      double t = sh[q][0];
+      for (int k = 1; k < kBlock / kWave; ++k) t += sh[q][k];
+      partials[(int64_t)q * kMaxParts + blockIdx.x] = t;
     }
   }
 }
 
-// Writes this block's partials; returns true in the last block to arrive,
-// whose thread 0 then holds the grid totals in v (summed in block order).
-template <int NV>
-__device__ bool grid_sum(double (&v)[NV], double *partials, unsigned *ticket) {
-  __shared__ double sh[NV][kBlock / kWave];
-  __shared__ bool last;
-  block_sum<NV>(v, sh);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) partials[q * kMaxReduceBlocks + blockIdx.x] = v[q];
-    __threadfence();
-    const unsigned t = atomicAdd(ticket, 1u);
-    last = (t == gridDim.x - 1);
+enum FinOp : int32_t { kFinInit = 0, kFinPQ = 1, kFinRR = 2, kFinRZ = 3, kFinTrue = 4 };
+
+__device__ __forceinline__ bool converged(double rr, double bb, double rtol) {
+  return sqrt(rr) <= rtol * sqrt(bb);
+}
+
+// Sums nparts partials of one or two quantities in a fixed order and applies
+// the CG scalar update of `op`.
+__global__ void __launch_bounds__(1024) k_finalize(int32_t op, int32_t nparts,
+                                                   const double *__restrict__ partials,
+                                                   PcgScal *scal, const int32_t *done) {
+  if (done && *done) return;
+  __shared__ double sh[2][1024 / kWave];
+  const int nv = op == kFinInit ? 2 : 1;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  double tot[2] = {0.0, 0.0};
+  for (int q = 0; q < nv; ++q) {
+    double a = 0.0;
+    for (int32_t b = threadIdx.x; b < nparts; b += blockDim.x) a += partials[(int64_t)q * kMaxParts + b];
+    for (int o = kWave / 2; o > 0; o >>= 1) a += __shfl_down(a, o, kWave);
+    if (lane == 0) sh[q][wid] = a;
   }
   __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  // fixed-order sum of the partials: thread k sums blocks k, k+256, ...,
-  // then a fixed tree over threads
-  double acc[NV];
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
-      s += partials[q * kMaxReduceBlocks + b];
-    acc[q] = s;
+  if (threadIdx.x != 0) return;
+  const int nw = blockDim.x / kWave;
+  for (int q = 0; q < nv; ++q) {
+    double t = sh[q][0];
+    for (int k = 1; k < nw; ++k) t += sh[q][k];
+    tot[q] = t;
   }
-  block_sum<NV>(acc, sh);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = acc[q];
-    *ticket = 0u;
+  switch (op) {
+    case kFinInit: {
+      const double rtol = scal->rtol;
+      scal->bb = tot[0];
+      scal->rr = tot[1];
+      scal->tol2 = rtol * rtol * tot[0];
+      if (tot[0] == 0.0) scal->done = 4;
+      else if (converged(tot[1], tot[0], rtol)) scal->done = 1;
+      else if (scal->maxit <= 0) scal->done = 2;
+      break;
+    }
+    case kFinPQ:
+      scal->pq = tot[0];
+      if (!(tot[0] > 0.0)) scal->done = 3;
+      else scal->alpha = scal->rho / tot[0];
+      break;
+    case kFinRR:
+      scal->rr = tot[0];
+      scal->iter += 1;
+      if (converged(tot[0], scal->bb, scal->rtol)) scal->done = 1;
+      else if (scal->iter >= scal->maxit) scal->done = 2;
+      break;
+    case kFinRZ:
+      if (!(tot[0] > 0.0)) {
+        scal->done = 3;
+      } else if (scal->phase == 0) {
+        scal->rho = tot[0];
+        scal->phase = 1;
+      } else {
+        scal->beta = tot[0] / scal->rho;
+        scal->rho = tot[0];
+      }
+      break;
+    default:
+      scal->rr_true = tot[0];
+      break;
   }
-  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -164,7 +202,6 @@ __global__ void k_demote(int64_t n, const double *a, float *b) {
 // side (double on level 0, TV below); TO: type of the level's output.
 // ---------------------------------------------------------------------------
 
-template <typename TV>
 __device__ __forceinline__ void sell_slice(const int32_t *sptr, int32_t row, int32_t *base,
                                            int32_t *w) {
   const int32_t s = row / kSlice;
@@ -183,7 +220,7 @@ __global__ void __launch_bounds__(kBlock) k_pre_residual(
   rows_of_block(n, chunk, &rb, &re);
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
-    sell_slice<TV>(sptr, row, &base, &w);
+    sell_slice(sptr, row, &base, &w);
     TV acc = 0;
     for (int32_t k = 0; k < w; ++k) {
       const int32_t idx = base + k * kSlice;
@@ -196,20 +233,20 @@ __global__ void __launch_bounds__(kBlock) k_pre_residual(
   }
 }
 
-// y = z + M^-1 (r - A z); with DOT also (r, y) for CG (rho / beta update)
+// y = z + M^-1 (r - A z); with DOT also the block partials of (r, y)
 template <typename TV, typename TR, typename TO, bool DOT>
 __global__ void __launch_bounds__(kBlock) k_post(
     int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
     const TV *__restrict__ val, const TV *__restrict__ minv, const TR *__restrict__ r,
-    const TV *__restrict__ z, TO *__restrict__ y, double *partials, unsigned *ticket,
-    PcgScal *scal, const int32_t *__restrict__ done) {
+    const TV *__restrict__ z, TO *__restrict__ y, double *__restrict__ partials,
+    const int32_t *__restrict__ done) {
   if (*done) return;
   int32_t rb, re;
   rows_of_block(n, chunk, &rb, &re);
   double d[1] = {0.0};
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
-    sell_slice<TV>(sptr, row, &base, &w);
+    sell_slice(sptr, row, &base, &w);
     TV acc = 0;
     for (int32_t k = 0; k < w; ++k) {
       const int32_t idx = base + k * kSlice;
@@ -220,24 +257,8 @@ __global__ void __launch_bounds__(kBlock) k_post(
     y[row] = yo;
     if (DOT) d[0] += (double)rr * (double)yo;
   }
-  if (DOT) {
-    if (grid_sum<1>(d, partials, ticket) && threadIdx.x == 0) {
-      const double rz = d[0];
-      if (!(rz > 0.0)) {
-        scal->done = 3;
-      } else if (scal->phase == 0) {
-        scal->rho = rz;
-        scal->phase = 1;
-      } else {
-        scal->beta = rz / scal->rho;
-        scal->rho = rz;
-      }
-    }
-  }
+  if (DOT) block_partial<1>(d, partials);
 }
-
-// extra smoothing sweep: y = z + M^-1 (r - A z) (no reduction)
-// (k_post with DOT = false)
 
 // z = M^-1 r (first of several pre-smoothing sweeps)
 template <typename TV, typename TR>
@@ -258,7 +279,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(
   rows_of_block(n, chunk, &rb, &re);
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
-    sell_slice<TV>(sptr, row, &base, &w);
+    sell_slice(sptr, row, &base, &w);
     TV acc = 0;
     for (int32_t k = 0; k < w; ++k) {
       const int32_t idx = base + k * kSlice;
@@ -293,53 +314,36 @@ __global__ void k_prolong(int32_t n, const int32_t *__restrict__ agg, const TV *
   if (i < n) z[i] += p[i] * zc[agg[i]];
 }
 
-// coarsest level: z = L^-T (L^-1 r) in one workgroup (n <= AMG_MAX_DENSE)
+// Coarsest level: z = A_L^-1 r with A_L^-1 = L^-T L^-1 formed from the
+// Cholesky factor at setup (row-major, symmetric). One wavefront per row,
+// lanes stride the columns (coalesced), so every row's loads are in flight
+// together instead of two sequential triangular sweeps.
+constexpr int kCoarseWaves = 4;
 template <typename TI, typename TO>
-__global__ void __launch_bounds__(1024) k_coarse_solve(int32_t n, const double *__restrict__ Linv,
-                                                       const double *__restrict__ LinvT,
-                                                       const TI *__restrict__ r,
-                                                       TO *__restrict__ z,
-                                                       const int32_t *__restrict__ done) {
-  extern __shared__ double sm[];
+__global__ void __launch_bounds__(kWave *kCoarseWaves) k_coarse_solve(
+    int32_t n, const double *__restrict__ Ainv, const TI *__restrict__ r, TO *__restrict__ z,
+    const int32_t *__restrict__ done) {
   if (*done) return;
-  double *rs = sm, *ys = sm + n;
-  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) rs[i] = (double)r[i];
-  __syncthreads();
-  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
-    double y = 0.0;
-    for (int32_t k = 0; k <= i; ++k) y += LinvT[(int64_t)k * n + i] * rs[k];
-    ys[i] = y;
-  }
-  __syncthreads();
-  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
-    double s = 0.0;
-    for (int32_t k = i; k < n; ++k) s += Linv[(int64_t)k * n + i] * ys[k];
-    z[i] = (TO)s;
-  }
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t i = blockIdx.x * kCoarseWaves + threadIdx.x / kWave;
+  if (i >= n) return;
+  const double *row = Ainv + (int64_t)i * n;
+  double s = 0.0;
+  for (int32_t k = lane; k < n; k += kWave) s += row[k] * (double)r[k];
+  for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_down(s, o, kWave);
+  if (lane == 0) z[i] = (TO)s;
 }
 
-// (r, z) for CG when the V-cycle has no post-smoother on level 0 to fuse it into
+// partials of (r, z) when level 0 is itself the coarsest level
 __global__ void __launch_bounds__(kBlock) k_dot_rz(int32_t n, int32_t chunk, const double *r,
                                                    const double *z, double *partials,
-                                                   unsigned *ticket, PcgScal *scal,
                                                    const int32_t *done) {
   if (*done) return;
   int32_t rb, re;
   rows_of_block(n, chunk, &rb, &re);
   double d[1] = {0.0};
   for (int32_t i = rb + threadIdx.x; i < re; i += kBlock) d[0] += r[i] * z[i];
-  if (grid_sum<1>(d, partials, ticket) && threadIdx.x == 0) {
-    const double rz = d[0];
-    if (!(rz > 0.0)) {
-      scal->done = 3;
-    } else if (scal->phase == 0) {
-      scal->rho = rz;
-      scal->phase = 1;
-    } else {
-      scal->beta = rz / scal->rho;
-      scal->rho = rz;
-    }
-  }
+  block_partial<1>(d, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -362,21 +366,17 @@ __global__ void k_scal_init(PcgScal *s, double rtol, int32_t maxit) {
   s->phase = 0;
 }
 
-__device__ __forceinline__ bool converged(double rr, double bb, double rtol) {
-  return sqrt(rr) <= rtol * sqrt(bb);
-}
-
-// r = b - A x ; (b, b), (r, r)
+// r = b - A x ; partials of (b, b), (r, r)
 __global__ void __launch_bounds__(kBlock) k_init_residual(
     int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
     const double *__restrict__ val, const double *__restrict__ b, const double *__restrict__ x,
-    double *__restrict__ r, double *partials, unsigned *ticket, PcgScal *scal) {
+    double *__restrict__ r, double *__restrict__ partials) {
   int32_t rb, re;
   rows_of_block(n, chunk, &rb, &re);
   double d[2] = {0.0, 0.0};
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
-    sell_slice<double>(sptr, row, &base, &w);
+    sell_slice(sptr, row, &base, &w);
     double acc = 0.0;
     for (int32_t k = 0; k < w; ++k) {
       const int32_t idx = base + k * kSlice;
@@ -388,28 +388,20 @@ __global__ void __launch_bounds__(kBlock) k_init_residual(
     d[0] += bi * bi;
     d[1] += ri * ri;
   }
-  if (grid_sum<2>(d, partials, ticket) && threadIdx.x == 0) {
-    const double rtol = scal->rtol;
-    scal->bb = d[0];
-    scal->rr = d[1];
-    scal->tol2 = rtol * rtol * d[0];
-    if (d[0] == 0.0) scal->done = 4;
-    else if (converged(d[1], d[0], rtol)) scal->done = 1;
-    else if (scal->maxit <= 0) scal->done = 2;
-  }
+  block_partial<2>(d, partials);
 }
 
-// ||b - A x||^2 at exit
+// partials of ||b - A x||^2 at exit
 __global__ void __launch_bounds__(kBlock) k_true_residual(
     int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
     const double *__restrict__ val, const double *__restrict__ b, const double *__restrict__ x,
-    double *partials, unsigned *ticket, PcgScal *scal) {
+    double *__restrict__ partials) {
   int32_t rb, re;
   rows_of_block(n, chunk, &rb, &re);
   double d[1] = {0.0};
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
-    sell_slice<double>(sptr, row, &base, &w);
+    sell_slice(sptr, row, &base, &w);
     double acc = 0.0;
     for (int32_t k = 0; k < w; ++k) {
       const int32_t idx = base + k * kSlice;
@@ -418,7 +410,7 @@ __global__ void __launch_bounds__(kBlock) k_true_residual(
     const double ri = b[row] - acc;
     d[0] += ri * ri;
   }
-  if (grid_sum<1>(d, partials, ticket) && threadIdx.x == 0) scal->rr_true = d[0];
+  block_partial<1>(d, partials);
 }
 
 __global__ void k_zero_if_zero_rhs(int32_t n, double *x, const PcgScal *scal) {
@@ -427,18 +419,18 @@ __global__ void k_zero_if_zero_rhs(int32_t n, double *x, const PcgScal *scal) {
   if (i < n) x[i] = 0.0;
 }
 
-// q = A p ; (p, q) ; alpha = rho / (p, q)
+// q = A p ; partials of (p, q)
 __global__ void __launch_bounds__(kBlock) k_spmv_dot(
     int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
     const double *__restrict__ val, const double *__restrict__ p, double *__restrict__ q,
-    double *partials, unsigned *ticket, PcgScal *scal, const int32_t *__restrict__ done) {
+    double *__restrict__ partials, const int32_t *__restrict__ done) {
   if (*done) return;
   int32_t rb, re;
   rows_of_block(n, chunk, &rb, &re);
   double d[1] = {0.0};
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
-    sell_slice<double>(sptr, row, &base, &w);
+    sell_slice(sptr, row, &base, &w);
     double acc = 0.0;
     for (int32_t k = 0; k < w; ++k) {
       const int32_t idx = base + k * kSlice;
@@ -447,22 +439,17 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot(
     q[row] = acc;
     d[0] += p[row] * acc;
   }
-  if (grid_sum<1>(d, partials, ticket) && threadIdx.x == 0) {
-    const double pq = d[0];
-    scal->pq = pq;
-    if (!(pq > 0.0)) scal->done = 3;
-    else scal->alpha = scal->rho / pq;
-  }
+  block_partial<1>(d, partials);
 }
 
-// x += alpha p ; r -= alpha q ; (r, r) ; stop test
+// x += alpha p ; r -= alpha q ; partials of (r, r)
 __global__ void __launch_bounds__(kBlock) k_update_xr(int32_t n, int32_t chunk,
                                                       double *__restrict__ x,
                                                       double *__restrict__ r,
                                                       const double *__restrict__ p,
                                                       const double *__restrict__ q,
-                                                      double *partials, unsigned *ticket,
-                                                      PcgScal *scal,
+                                                      double *__restrict__ partials,
+                                                      const PcgScal *__restrict__ scal,
                                                       const int32_t *__restrict__ done) {
   if (*done) return;
   const double alpha = scal->alpha;
@@ -475,12 +462,7 @@ __global__ void __launch_bounds__(kBlock) k_update_xr(int32_t n, int32_t chunk,
     r[i] = ri;
     d[0] += ri * ri;
   }
-  if (grid_sum<1>(d, partials, ticket) && threadIdx.x == 0) {
-    scal->rr = d[0];
-    scal->iter += 1;
-    if (converged(d[0], scal->bb, scal->rtol)) scal->done = 1;
-    else if (scal->iter >= scal->maxit) scal->done = 2;
-  }
+  block_partial<1>(d, partials);
 }
 
 // p = z + beta p
@@ -530,67 +512,70 @@ const double *pmvals<double>(const Level &L) { return L.pm64; }
 template <>
 const float *pmvals<float>(const Level &L) { return L.pm32; }
 
-// pre-smoothing (nu sweeps) + residual on level l: z_l, t_l from right-hand side r
+void finalize(amg_hierarchy *h, int32_t op, int32_t nparts, const int32_t *done) {
+  k_finalize<<<1, 1024, 0, h->stream>>>(op, nparts, h->partials, h->scal, done);
+}
+
+// Pre-smoothing (pre sweeps) and residual on level l from right-hand side r.
+// Leaves t_l = r - A z in L.t and returns the buffer that holds z.
 template <typename TV, typename TR>
-void launch_down(amg_hierarchy *h, int32_t l, const TR *r, const int32_t *done) {
+TV *launch_down(amg_hierarchy *h, int32_t l, const TR *r, const int32_t *done) {
   hipStream_t s = h->stream;
   Level &L = h->lv[l];
-  TV *z = (TV *)L.z, *t = (TV *)L.t, *y = (TV *)L.y;
+  TV *z = (TV *)L.z, *tmp = (TV *)L.y, *t = (TV *)L.t;
   const Geom g = geom(L.n, false);
   const int32_t pre = h->params.pre;
   if (pre == 1) {
     k_pre_residual<TV, TR><<<g.grid, kBlock, 0, s>>>(L.n, g.chunk, L.S.sptr, L.S.col, vals<TV>(L),
                                                    minv<TV>(L), r, z, t, done);
-    return;
+    return z;
   }
   k_jacobi0<TV, TR><<<grid1(L.n), kBlock, 0, s>>>(L.n, minv<TV>(L), r, z, done);
   for (int32_t k = 1; k < pre; ++k) {
     k_post<TV, TR, TV, false><<<g.grid, kBlock, 0, s>>>(L.n, g.chunk, L.S.sptr, L.S.col,
-                                                       vals<TV>(L), minv<TV>(L), r, z, y,
-                                                       nullptr, nullptr, nullptr, done);
-    std::swap(L.z, L.y);
-    z = (TV *)L.z;
-    y = (TV *)L.y;
+                                                       vals<TV>(L), minv<TV>(L), r, z, tmp,
+                                                       nullptr, done);
+    std::swap(z, tmp);
   }
   k_residual<TV, TR><<<g.grid, kBlock, 0, s>>>(L.n, g.chunk, L.S.sptr, L.S.col, vals<TV>(L), r, z,
                                              t, done);
+  return z;
 }
 
-// prolongation + post-smoothing on level l; output to `out`
+// Prolongation into z and post-smoothing on level l; the last sweep writes
+// `out` (a buffer other than z and L.t), with the (r, out) partials if dot.
 template <typename TV, typename TR, typename TO>
-void launch_up(amg_hierarchy *h, int32_t l, const TR *r, const TV *zc, TO *out, bool dot,
+void launch_up(amg_hierarchy *h, int32_t l, const TR *r, TV *z, const TV *zc, TO *out, bool dot,
                const int32_t *done) {
   hipStream_t s = h->stream;
   Level &L = h->lv[l];
-  TV *z = (TV *)L.z, *y = (TV *)L.y;
+  TV *tmp = (TV *)L.t;  // free once the restriction has read it
   k_prolong<TV><<<grid1(L.n), kBlock, 0, s>>>(L.n, L.agg, pvals<TV>(L), zc, z, done);
+  const Geom g = geom(L.n, dot);
   const int32_t post = h->params.post;
   for (int32_t k = 0; k + 1 < post; ++k) {
-    const Geom g = geom(L.n, false);
     k_post<TV, TR, TV, false><<<g.grid, kBlock, 0, s>>>(L.n, g.chunk, L.S.sptr, L.S.col,
-                                                       vals<TV>(L), minv<TV>(L), r, z, y,
-                                                       nullptr, nullptr, nullptr, done);
-    std::swap(L.z, L.y);
-    z = (TV *)L.z;
-    y = (TV *)L.y;
+                                                       vals<TV>(L), minv<TV>(L), r, z, tmp,
+                                                       nullptr, done);
+    std::swap(z, tmp);
   }
-  const Geom g = geom(L.n, dot);
-  if (dot)
+  if (dot) {
     k_post<TV, TR, TO, true><<<g.grid, kBlock, 0, s>>>(L.n, g.chunk, L.S.sptr, L.S.col,
                                                       vals<TV>(L), minv<TV>(L), r, z, out,
-                                                      h->partials, h->ticket, h->scal, done);
-  else
+                                                      h->partials, done);
+    finalize(h, kFinRZ, g.grid, done);
+  } else {
     k_post<TV, TR, TO, false><<<g.grid, kBlock, 0, s>>>(L.n, g.chunk, L.S.sptr, L.S.col,
                                                        vals<TV>(L), minv<TV>(L), r, z, out,
-                                                       nullptr, nullptr, nullptr, done);
+                                                       nullptr, done);
+  }
 }
 
 template <typename TI, typename TO>
 void launch_coarse(amg_hierarchy *h, const TI *r, TO *z, const int32_t *done) {
   const int32_t n = h->C.n;
-  const int threads = n <= 64 ? 64 : (n <= 256 ? 256 : 1024);
-  k_coarse_solve<TI, TO><<<1, threads, sizeof(double) * 2 * n, h->stream>>>(
-      n, h->C.Linv, h->C.LinvT, r, z, done);
+  k_coarse_solve<TI, TO><<<ceil_div(n, kCoarseWaves), kWave * kCoarseWaves, 0, h->stream>>>(
+      n, h->C.Ainv, r, z, done);
 }
 
 template <typename TV>
@@ -600,27 +585,25 @@ void vcycle_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const in
     launch_coarse<double, double>(h, r0, z0, done);
     if (dot) {
       const Geom g = geom(h->lv[0].n, true);
-      k_dot_rz<<<g.grid, kBlock, 0, h->stream>>>(h->lv[0].n, g.chunk, r0, z0, h->partials,
-                                                 h->ticket, h->scal, done);
+      k_dot_rz<<<g.grid, kBlock, 0, h->stream>>>(h->lv[0].n, g.chunk, r0, z0, h->partials, done);
+      finalize(h, kFinRZ, g.grid, done);
     }
     return;
   }
-  // down
-  launch_down<TV, double>(h, 0, r0, done);
+  std::vector<TV *> zbuf(L);
+  zbuf[0] = launch_down<TV, double>(h, 0, r0, done);
   for (int32_t l = 0; l < L; ++l) {
     Level &F = h->lv[l];
     Level &C = h->lv[l + 1];
     k_restrict<TV><<<grid1(C.n), kBlock, 0, h->stream>>>(C.n, F.mptr, F.mem, pmvals<TV>(F),
                                                          (const TV *)F.t, (TV *)C.r, done);
-    if (l + 1 < L) launch_down<TV, TV>(h, l + 1, (const TV *)C.r, done);
+    if (l + 1 < L) zbuf[l + 1] = launch_down<TV, TV>(h, l + 1, (const TV *)C.r, done);
   }
-  // coarsest
   launch_coarse<TV, TV>(h, (const TV *)h->lv[L].r, (TV *)h->lv[L].y, done);
-  // up
   for (int32_t l = L - 1; l >= 1; --l)
-    launch_up<TV, TV, TV>(h, l, (const TV *)h->lv[l].r, (const TV *)h->lv[l + 1].y,
+    launch_up<TV, TV, TV>(h, l, (const TV *)h->lv[l].r, zbuf[l], (const TV *)h->lv[l + 1].y,
                           (TV *)h->lv[l].y, false, done);
-  launch_up<TV, double, double>(h, 0, r0, (const TV *)h->lv[1].y, z0, dot, done);
+  launch_up<TV, double, double>(h, 0, r0, zbuf[0], (const TV *)h->lv[1].y, z0, dot, done);
 }
 
 amg_status alloc_level_vectors(amg_hierarchy *h, Level &L, size_t vbytes) {
@@ -642,7 +625,7 @@ amg_status build_solve_formats(amg_hierarchy *h) {
     Level &L = h->lv[l];
     const bool coarsest = (l == nlev - 1);
     // level 0 always needs the FP64 SELL for the outer CG; the V-cycle levels
-    // need the hierarchy precision; the coarsest uses its dense factor only
+    // need the hierarchy precision; the coarsest uses its dense inverse only
     const bool need64 = (l == 0) || (!coarsest && !fp32);
     const bool need32 = !coarsest && fp32;
     if (need64 || need32) {
@@ -666,29 +649,26 @@ amg_status build_solve_formats(amg_hierarchy *h) {
       k_sell_fill<<<ceil_div((int64_t)S.nslices * kSlice, kBlock), kBlock, 0, s>>>(
           L.n, S.nslices, L.rp, L.ci, L.val, S.sptr, S.col, S.v64, S.v32);
     }
-    if (!coarsest) {
-      if (fp32) {
-        AMG_TRY(dalloc(h, &L.minv32, (size_t)L.n));
-        AMG_TRY(dalloc(h, &L.p32, (size_t)L.n));
-        AMG_TRY(dalloc(h, &L.pm32, (size_t)L.n));
-        k_demote<<<grid1(L.n), kBlock, 0, s>>>(L.n, L.minv64, L.minv32);
-        k_demote<<<grid1(L.n), kBlock, 0, s>>>(L.n, L.p64, L.p32);
-        k_demote<<<grid1(L.n), kBlock, 0, s>>>(L.n, L.pm64, L.pm32);
-      }
+    if (!coarsest && fp32) {
+      AMG_TRY(dalloc(h, &L.minv32, (size_t)L.n));
+      AMG_TRY(dalloc(h, &L.p32, (size_t)L.n));
+      AMG_TRY(dalloc(h, &L.pm32, (size_t)L.n));
+      k_demote<<<grid1(L.n), kBlock, 0, s>>>(L.n, L.minv64, L.minv32);
+      k_demote<<<grid1(L.n), kBlock, 0, s>>>(L.n, L.p64, L.p32);
+      k_demote<<<grid1(L.n), kBlock, 0, s>>>(L.n, L.pm64, L.pm32);
     }
     AMG_TRY(alloc_level_vectors(h, L, vbytes));
   }
   // outer CG vectors and scalars
   const int32_t n0 = h->lv[0].n;
+  AMG_TRY(dalloc(h, &h->x, (size_t)n0));
   AMG_TRY(dalloc(h, &h->r, (size_t)n0));
   AMG_TRY(dalloc(h, &h->z, (size_t)n0));
   AMG_TRY(dalloc(h, &h->p, (size_t)n0));
   AMG_TRY(dalloc(h, &h->q, (size_t)n0));
-  AMG_TRY(dalloc(h, &h->partials, (size_t)kMaxReduceBlocks * 4));
-  AMG_TRY(dalloc(h, &h->ticket, 4));
+  AMG_TRY(dalloc(h, &h->partials, (size_t)kMaxParts * 2));
   AMG_TRY(dalloc(h, &h->scal, 1));
   AMG_TRY(dalloc(h, &h->zero_flag, 4));
-  AMG_HIP(hipMemsetAsync(h->ticket, 0, sizeof(unsigned) * 4, s));
   AMG_HIP(hipMemsetAsync(h->zero_flag, 0, sizeof(int32_t) * 4, s));
   AMG_HIP(hipMemsetAsync(h->scal, 0, sizeof(PcgScal), s));
   if (!h->scal_host) AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->scal_host), sizeof(PcgScal)));
@@ -705,24 +685,56 @@ amg_status vcycle(amg_hierarchy *h, const double *r, double *z, bool fuse_dot,
 
 namespace {
 
-// one CG iteration (after the first preconditioning)
-void cg_iteration(amg_hierarchy *h, double *x) {
+// One CG iteration after the first preconditioning. Touches only hierarchy
+// buffers (x is the internal copy), so it can be captured once and replayed.
+void cg_iteration(amg_hierarchy *h) {
   hipStream_t s = h->stream;
   Level &L0 = h->lv[0];
   const int32_t n = L0.n;
   const int32_t *done = &h->scal->done;
   const Geom g = geom(n, true);
   k_spmv_dot<<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, h->p, h->q,
-                                       h->partials, h->ticket, h->scal, done);
-  k_update_xr<<<g.grid, kBlock, 0, s>>>(n, g.chunk, x, h->r, h->p, h->q, h->partials,
-                                        h->ticket + 1, h->scal, done);
+                                       h->partials, done);
+  finalize(h, kFinPQ, g.grid, done);
+  k_update_xr<<<g.grid, kBlock, 0, s>>>(n, g.chunk, h->x, h->r, h->p, h->q, h->partials, h->scal,
+                                        done);
+  finalize(h, kFinRR, g.grid, done);
   vcycle(h, h->r, h->z, true, done);
   k_xpay<<<grid1(n), kBlock, 0, s>>>(n, h->z, h->p, h->scal, done);
 }
 
+// Captures one CG iteration into a hipGraph (once per hierarchy).
+amg_status ensure_iteration_graph(amg_hierarchy *h) {
+  if (h->iter_exec || h->graph_failed || (h->params.flags & AMG_FLAG_NO_GRAPH)) return AMG_OK;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    h->graph_failed = true;
+    return AMG_OK;
+  }
+  cg_iteration(h);
+  hipError_t e = hipStreamEndCapture(h->stream, &g);
+  if (e != hipSuccess || !g) {
+    (void)hipGetLastError();
+    h->graph_failed = true;
+    return AMG_OK;
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipGraphDestroy(g);
+    h->graph_failed = true;
+    return AMG_OK;
+  }
+  h->iter_graph = g;
+  h->iter_exec = ex;
+  return AMG_OK;
+}
+
 }  // namespace
 
-amg_status pcg(amg_hierarchy *h, const double *b, double *x, double rtol, int32_t maxit,
+amg_status pcg(amg_hierarchy *h, const double *b, double *x_user, double rtol, int32_t maxit,
                amg_solve_info *info) {
   const double t0 = now_ms();
   hipStream_t s = h->stream;
@@ -730,10 +742,13 @@ amg_status pcg(amg_hierarchy *h, const double *b, double *x, double rtol, int32_
   const int32_t n = L0.n;
   const int32_t *done = &h->scal->done;
   const Geom g = geom(n, true);
+  AMG_TRY(ensure_iteration_graph(h));
+  AMG_HIP(hipMemcpyAsync(h->x, x_user, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   k_scal_init<<<1, 1, 0, s>>>(h->scal, rtol, maxit);
-  k_init_residual<<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, b, x,
-                                            h->r, h->partials, h->ticket, h->scal);
-  k_zero_if_zero_rhs<<<grid1(n), kBlock, 0, s>>>(n, x, h->scal);
+  k_init_residual<<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, b, h->x,
+                                            h->r, h->partials);
+  finalize(h, kFinInit, g.grid, nullptr);
+  k_zero_if_zero_rhs<<<grid1(n), kBlock, 0, s>>>(n, h->x, h->scal);
   AMG_TRY(vcycle(h, h->r, h->z, true, done));
   k_copy<<<grid1(n), kBlock, 0, s>>>(n, h->z, h->p, done);
   // iterations in chunks; the chunk length follows the observed convergence
@@ -745,7 +760,7 @@ amg_status pcg(amg_hierarchy *h, const double *b, double *x, double rtol, int32_
     AMG_HIP(hipStreamSynchronize(s));
     const PcgScal sc = *h->scal_host;
     if (sc.done) break;
-    if (queued >= maxit) break;  // cannot happen: the maxit test sets done
+    if (queued >= maxit) break;  // not reached: the maxit test sets done
     if (rr_prev > 0.0 && sc.iter > it_prev && sc.rr > 0.0 && sc.rr < rr_prev) {
       const double rate = std::pow(sc.rr / rr_prev, 1.0 / (sc.iter - it_prev));
       const double need = std::log(sc.tol2 / sc.rr) / std::log(rate);
@@ -754,12 +769,17 @@ amg_status pcg(amg_hierarchy *h, const double *b, double *x, double rtol, int32_
     rr_prev = sc.rr;
     it_prev = sc.iter;
     const int32_t c = std::min(chunk, maxit - queued);
-    for (int32_t k = 0; k < c; ++k) cg_iteration(h, x);
+    for (int32_t k = 0; k < c; ++k) {
+      if (h->iter_exec) AMG_HIP(hipGraphLaunch(h->iter_exec, s));
+      else cg_iteration(h);
+    }
     AMG_HIP(hipGetLastError());
     queued += c;
   }
-  k_true_residual<<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, b, x,
-                                            h->partials, h->ticket, h->scal);
+  k_true_residual<<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, b, h->x,
+                                            h->partials);
+  finalize(h, kFinTrue, g.grid, nullptr);
+  AMG_HIP(hipMemcpyAsync(x_user, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   AMG_HIP(hipMemcpyAsync(h->scal_host, h->scal, sizeof(PcgScal), hipMemcpyDeviceToHost, s));
   AMG_HIP(hipStreamSynchronize(s));
   const PcgScal sc = *h->scal_host;
@@ -792,7 +812,6 @@ amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t 
   AMG_HIP(hipEventCreate(&e1));
   auto launch = [&]() {
     const Geom g = geom(L.n, false);
-    const Geom gr = geom(L.n, true);
     switch (kernel) {
       case 0:
         if (fp32) {
@@ -813,18 +832,22 @@ amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t 
       case 1:
         if (fp32) {
           if (level == 0)
-            k_post<float, double, double, false><<<g.grid, kBlock, 0, s>>>(
+            k_post<float, double, double, true><<<g.grid, kBlock, 0, s>>>(
                 L.n, g.chunk, L.S.sptr, L.S.col, L.S.v32, L.minv32, h->r, (const float *)L.z,
-                h->z, nullptr, nullptr, nullptr, done);
+                h->z, h->partials, done);
           else
             k_post<float, float, float, false><<<g.grid, kBlock, 0, s>>>(
                 L.n, g.chunk, L.S.sptr, L.S.col, L.S.v32, L.minv32, (const float *)L.r,
-                (const float *)L.z, (float *)L.y, nullptr, nullptr, nullptr, done);
+                (const float *)L.z, (float *)L.y, nullptr, done);
         } else {
-          k_post<double, double, double, false><<<g.grid, kBlock, 0, s>>>(
-              L.n, g.chunk, L.S.sptr, L.S.col, L.S.v64, L.minv64,
-              level == 0 ? h->r : (const double *)L.r, (const double *)L.z,
-              level == 0 ? h->z : (double *)L.y, nullptr, nullptr, nullptr, done);
+          if (level == 0)
+            k_post<double, double, double, true><<<g.grid, kBlock, 0, s>>>(
+                L.n, g.chunk, L.S.sptr, L.S.col, L.S.v64, L.minv64, h->r, (const double *)L.z,
+                h->z, h->partials, done);
+          else
+            k_post<double, double, double, false><<<g.grid, kBlock, 0, s>>>(
+                L.n, g.chunk, L.S.sptr, L.S.col, L.S.v64, L.minv64, (const double *)L.r,
+                (const double *)L.z, (double *)L.y, nullptr, done);
         }
         break;
       case 2:
@@ -848,8 +871,8 @@ amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t 
                                                           (double *)L.z, done);
         break;
       default:
-        k_spmv_dot<<<gr.grid, kBlock, 0, s>>>(L.n, gr.chunk, L.S.sptr, L.S.col, L.S.v64, h->p,
-                                              h->q, h->partials, h->ticket, h->scal, done);
+        k_spmv_dot<<<g.grid, kBlock, 0, s>>>(L.n, g.chunk, L.S.sptr, L.S.col, L.S.v64, h->p,
+                                             h->q, h->partials, done);
         break;
     }
   };
