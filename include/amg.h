@@ -138,6 +138,11 @@ amg_status amg_pcg_solve_batch(amg_hierarchy *h, int32_t k, const double *B, dou
  * r, z: device, n. */
 amg_status amg_vcycle_apply(amg_hierarchy *h, const double *r, double *z);
 
+/* Rebinds the hierarchy to another caller stream (hipStream_t, NULL = the
+ * device's default stream): later calls are ordered after the work queued
+ * on it. Lets a serving loop reuse a cached hierarchy from any slot. */
+amg_status amg_set_stream(amg_hierarchy *h, void *stream);
+
 /* Releases the hierarchy and all its device memory. NULL is a no-op. */
 void amg_free(amg_hierarchy *h);
 

@@ -28,7 +28,7 @@ MAX_DENSE = 4096
 
 EXPORTED_SYMBOLS = (
     "amg_params_default", "amg_setup", "amg_pcg_solve", "amg_pcg_solve_batch",
-    "amg_vcycle_apply", "amg_free", "amg_num_levels", "amg_level_info", "amg_get_level_csr",
+    "amg_vcycle_apply", "amg_set_stream", "amg_free", "amg_num_levels", "amg_level_info", "amg_get_level_csr",
     "amg_get_transfer", "amg_get_l1diag", "amg_get_w", "amg_footprint_bytes",
     "amg_estimate_footprint", "amg_setup_times", "amg_matching_rounds", "amg_time_kernel",
     "amg_batch_tile", "amg_status_string",
@@ -99,6 +99,7 @@ def load_library():
         "amg_pcg_solve": (C.c_int, [V, V, V, D, I32, P(SolveInfo)]),
         "amg_pcg_solve_batch": (C.c_int, [V, I32, V, V, D, I32, P(SolveInfo)]),
         "amg_vcycle_apply": (C.c_int, [V, V, V]),
+        "amg_set_stream": (C.c_int, [V, V]),
         "amg_free": (None, [V]),
         "amg_num_levels": (C.c_int, [V, P(I32)]),
         "amg_level_info": (C.c_int, [V, I32, P(I64), P(I64)]),
@@ -237,6 +238,11 @@ class Hierarchy:
         w = np.empty(n)
         self._check(load_library().amg_get_w(self._h, l, w.ctypes.data), "amg_get_w")
         return w
+
+    def set_stream(self, stream):
+        """Orders later calls after `stream` (a torch stream or a raw handle)."""
+        raw = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        self._check(load_library().amg_set_stream(self._h, raw), "amg_set_stream")
 
     def footprint_bytes(self) -> int:
         return int(load_library().amg_footprint_bytes(self._h))

@@ -169,6 +169,12 @@ amg_status amg_vcycle_apply(amg_hierarchy *h, const double *r, double *z) {
   return AMG_OK;
 }
 
+amg_status amg_set_stream(amg_hierarchy *h, void *stream) {
+  if (!h) return AMG_ERR_ARG;
+  h->user_stream = reinterpret_cast<hipStream_t>(stream);
+  return AMG_OK;
+}
+
 void amg_free(amg_hierarchy *h) { destroy(h); }
 
 amg_status amg_num_levels(const amg_hierarchy *h, int32_t *nlev) {

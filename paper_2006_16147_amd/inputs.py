@@ -311,3 +311,53 @@ def random_spd_graph(n: int, avg_deg: float, seed: int, diag_shift: float = 0.5,
     np.add.at(row_ptr, rows + 1, 1)
     row_ptr = np.cumsum(row_ptr)
     return Csr(n, row_ptr, cols, vals)
+
+
+def constant_diffusion7_arrays(N: int, kx: float, ky: float, kz: float, xp, device=None):
+    """7-point operator with constant coefficients, built with array module
+    ``xp`` (numpy, or torch with ``device``): off-diagonals -k_d along axis d,
+    diagonal 2 (kx + ky + kz) (Dirichlet faces take the node's coefficient).
+    Returns (row_ptr int32, col int32, val float64) in the CSR conventions of
+    this module. Used by serving clients to build operators where they live.
+    """
+    n = N * N * N
+    if xp.__name__ == "torch":
+        import torch
+
+        ar = lambda m: torch.arange(m, dtype=torch.int64, device=device)  # noqa: E731
+        full = lambda v: torch.full((n,), v, dtype=torch.float64, device=device)  # noqa: E731
+        stack = lambda a: torch.stack(a, dim=1)  # noqa: E731
+        cumsum = lambda a: torch.cumsum(a, 0)  # noqa: E731
+        zero = torch.zeros(1, dtype=torch.int64, device=device)
+    else:
+        ar = lambda m: np.arange(m, dtype=np.int64)  # noqa: E731
+        full = lambda v: np.full(n, v, dtype=np.float64)  # noqa: E731
+        stack = lambda a: np.stack(a, axis=1)  # noqa: E731
+        cumsum = lambda a: np.cumsum(a)  # noqa: E731
+        zero = np.zeros(1, dtype=np.int64)
+    idx = ar(n)
+    coord = {"x": idx % N, "y": (idx // N) % N, "z": idx // (N * N)}
+    stride = {"x": 1, "y": N, "z": N * N}
+    kval = {"x": float(kx), "y": float(ky), "z": float(kz)}
+    cols, vals, masks = [], [], []
+    for ax, sg in zip(_AXES, _SIGNS):
+        if ax is None:
+            cols.append(idx)
+            vals.append(full(2.0 * (float(kx) + float(ky) + float(kz))))
+            masks.append(idx >= 0)
+            continue
+        c = coord[ax]
+        masks.append((c > 0) if sg < 0 else (c < N - 1))
+        cols.append(idx + sg * stride[ax])
+        vals.append(full(-kval[ax]))
+    M = stack(masks)
+    col = stack(cols)[M]
+    val = stack(vals)[M]
+    counts = M.sum(1)
+    if xp.__name__ == "torch":
+        import torch
+
+        row_ptr = torch.cat([zero, cumsum(counts)]).to(torch.int32)
+        return row_ptr.contiguous(), col.to(torch.int32).contiguous(), val.contiguous()
+    row_ptr = np.concatenate([zero, cumsum(counts)]).astype(np.int32)
+    return row_ptr, col.astype(np.int32), val
