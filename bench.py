@@ -32,8 +32,8 @@ if ROOT not in sys.path:
 
 METRIC = "AMG-PCG solve ms & V-cycle HBM GB/s (160^3 Poisson), FP32-prec vs FP64; p99"
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAMES = {0: "pre-smoothing + residual", 1: "post-smoothing", 2: "restriction",
-                3: "prolongation", 4: "outer-CG SpMV + dot"}
+KERNEL_NAMES = {0: "pre-smoothing + residual + restriction", 1: "post-smoothing + CG dot",
+                2: "level-1 post-smoothing + prolongation", 4: "outer-CG SpMV + dot"}
 
 
 def source_hash() -> str:
@@ -49,25 +49,31 @@ def source_hash() -> str:
 def vcycle_bytes(sizes, nnzs, V, nL):
     """Algorithmic HBM bytes of one V-cycle with this library's kernel set.
 
-    Per level l < L (n rows, z entries, nc coarse rows; Vr = 8 on level 0,
-    whose right-hand side and output are the FP64 CG vectors, else V):
-      pre-smoothing + residual  z (V + 4) + 4 (n + 1) + n (Vr + 3 V)
-      restriction               n (4 + 2 V) + 4 (nc + 1) + nc V
-      prolongation              n (4 + 3 V) + nc V
-      post-smoothing            z (V + 4) + 4 (n + 1) + n (2 Vr + 2 V)
-    each array read or written once (CSR values, int32 columns and int32
-    row offsets for the SpMVs); plus the coarsest solve, which reads the two
-    triangular factors of the inverse Cholesky factor and its vectors."""
-    total = 0.0
+    n_l rows, z_l entries per level; V value bytes; Vr = 8 on level 0, whose
+    right-hand side and output are the FP64 CG vectors. Every array is read
+    or written once per kernel (matrix values + int32 columns + int32 row
+    offsets per SpMV):
+      pre-smoothing + residual + restriction (l < L):
+          z_l (V + 4) + 4 (n_l + 1) + n_l (Vr + 3 V) + n_{l+1} (V + 4)
+      post-smoothing of level c (0 < c < L), fused with prolongation:
+          z_c (V + 4) + 4 (n_c + 1) + 3 V n_c
+      prolongation into level l (l < L):  n_l (3 V + 4)
+      coarsest solve (dense A_L^-1):      8 n_L^2 + V n_L
+      level-0 post-smoothing:             z_0 (V + 4) + 4 (n_0 + 1) + n_0 (16 + 2 V)
+    """
     L = len(sizes) - 1
+    if L == 0:
+        return 8.0 * nL * nL + 16.0 * nL
+    total = 0.0
     for l in range(L):
         n, z, nc = sizes[l], nnzs[l], sizes[l + 1]
         Vr = 8.0 if l == 0 else V
-        total += z * (V + 4) + 4 * (n + 1) + n * (Vr + 3 * V)
-        total += n * (4 + 2 * V) + 4 * (nc + 1) + nc * V
-        total += n * (4 + 3 * V) + nc * V
-        total += z * (V + 4) + 4 * (n + 1) + n * (2 * Vr + 2 * V)
-    total += 2 * 8.0 * nL * (nL + 1) / 2 + 2 * nL * (8.0 if L == 0 else V)
+        total += z * (V + 4) + 4 * (n + 1) + n * (Vr + 3 * V) + nc * (V + 4)
+        total += n * (3 * V + 4)
+    for c in range(1, L):
+        total += nnzs[c] * (V + 4) + 4 * (sizes[c] + 1) + 3 * V * sizes[c]
+    total += 8.0 * nL * nL + V * nL
+    total += nnzs[0] * (V + 4) + 4 * (sizes[0] + 1) + sizes[0] * (16 + 2 * V)
     return total
 
 

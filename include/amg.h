@@ -178,8 +178,11 @@ amg_status amg_matching_rounds(const amg_hierarchy *h, int32_t l, int32_t *round
 /* Times `reps` launches of one solve-phase kernel on level l with live data
  * between HIP events on the hierarchy's stream; *ms = mean per launch and
  * *bytes = the kernel's algorithmic HBM bytes per launch. kernel:
- * 0 = pre-smoothing + residual, 1 = post-smoothing, 2 = restriction,
- * 3 = prolongation, 4 = outer-CG SpMV with dot product. */
+ * 0 = pre-smoothing + residual + restriction to level l + 1,
+ * 1 = post-smoothing (on level 0 with the CG dot product),
+ * 2 = post-smoothing of level l + 1 fused with the prolongation into level l
+ *     (level l + 1 must not be the coarsest), 3 = same as 2,
+ * 4 = outer-CG SpMV with its dot product (level 0). */
 amg_status amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
                            double *ms, double *bytes);
 

@@ -79,8 +79,8 @@ __global__ void __launch_bounds__(kBlock) kb_pre_residual(
     TV acc = 0;
     for (int32_t e = 0; e < w; ++e) {
       const int32_t idx = base + e * kSlice;
-      const int32_t c = col[idx];
-      acc += val[idx] * ((TV)R[(int64_t)c * k + j] * minv[c]);
+      const int32_t c = ld_stream(&col[idx]);
+      acc += ld_stream(&val[idx]) * (TV)R[(int64_t)c * k + j];  // val holds A M^-1
     }
     const int64_t o = (int64_t)row * k + j;
     const TV ri = (TV)R[o];
@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(kBlock) kb_post(
       TV acc = 0;
       for (int32_t e = 0; e < w; ++e) {
         const int32_t idx = base + e * kSlice;
-        acc += val[idx] * Z[(int64_t)col[idx] * k + j];
+        acc += ld_stream(&val[idx]) * Z[(int64_t)ld_stream(&col[idx]) * k + j];
       }
       const int64_t o = (int64_t)row * k + j;
       const TR rr = R[o];
@@ -120,30 +120,43 @@ __global__ void __launch_bounds__(kBlock) kb_post(
   if (DOT) column_partial<KT>(d, valid, j, k, partials);
 }
 
+// R_c(J) = sum over the segment of J (aggregate-major positions), in order,
+// of p_m T(m)
 template <typename TV, int KT>
-__global__ void kb_restrict(int32_t nc, int32_t k, const int32_t *__restrict__ mptr,
-                            const int32_t *__restrict__ mem, const TV *__restrict__ pm,
-                            const TV *__restrict__ T, TV *__restrict__ Rc,
-                            const int32_t *__restrict__ stop) {
+__global__ void kb_restrict(int32_t nc, int32_t k, const int32_t *__restrict__ seg,
+                            const TV *__restrict__ pp, const TV *__restrict__ T,
+                            TV *__restrict__ Rc, const int32_t *__restrict__ stop) {
   if (*stop) return;
   const int32_t j = blockIdx.y * KT + threadIdx.x % KT;
   const int64_t I = (int64_t)blockIdx.x * (kBlock / KT) + threadIdx.x / KT;
   if (j >= k || I >= nc) return;
-  const int32_t b = mptr[I], e = mptr[I + 1];
+  const int32_t b = seg[I], e = seg[I + 1];
   TV s = 0;
-  for (int32_t m = b; m < e; ++m) s += pm[m] * T[(int64_t)mem[m] * k + j];
+  for (int32_t m = b; m < e; ++m) s += pp[m] * T[(int64_t)m * k + j];
   Rc[I * k + j] = s;
 }
 
 template <typename TV, int KT>
-__global__ void kb_prolong(int32_t n, int32_t k, const int32_t *__restrict__ agg,
-                           const TV *__restrict__ p, const TV *__restrict__ Zc,
+__global__ void kb_prolong(int32_t n, int32_t k, const int32_t *__restrict__ aggp,
+                           const TV *__restrict__ pp, const TV *__restrict__ Zc,
                            TV *__restrict__ Z, const int32_t *__restrict__ stop) {
   if (*stop) return;
   const int32_t j = blockIdx.y * KT + threadIdx.x % KT;
   const int64_t i = (int64_t)blockIdx.x * (kBlock / KT) + threadIdx.x / KT;
   if (j >= k || i >= n) return;
-  Z[i * k + j] += p[i] * Zc[(int64_t)agg[i] * k + j];
+  Z[i * k + j] += pp[i] * Zc[(int64_t)aggp[i] * k + j];
+}
+
+// row permutation of an n x k block: Dst(q) = Src(perm q) (IN) or
+// Dst(perm q) = Src(q) (OUT)
+template <bool IN>
+__global__ void kb_permute_rows(int32_t n, int32_t k, const int32_t *__restrict__ perm,
+                                const double *__restrict__ Src, double *__restrict__ Dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * k) return;
+  const int64_t q = e / k, j = e % k;
+  if (IN) Dst[e] = Src[(int64_t)perm[q] * k + j];
+  else Dst[(int64_t)perm[q] * k + j] = Src[e];
 }
 
 // Z = A_L^-1 R on the coarsest level, one thread per (row, column)
@@ -187,7 +200,7 @@ __global__ void __launch_bounds__(kBlock) kb_spmv(
       double acc = 0.0;
       for (int32_t e = 0; e < w; ++e) {
         const int32_t idx = base + e * kSlice;
-        acc += val[idx] * Xin[(int64_t)col[idx] * k + j];
+        acc += ld_stream(&val[idx]) * Xin[(int64_t)ld_stream(&col[idx]) * k + j];
       }
       const int64_t o = (int64_t)row * k + j;
       if (mode == 0) {
@@ -406,23 +419,23 @@ const double *vals<double>(const Level &L) { return L.S.v64; }
 template <>
 const float *vals<float>(const Level &L) { return L.S.v32; }
 template <typename TV>
+const TV *svals(const Level &L);
+template <>
+const double *svals<double>(const Level &L) { return L.S.s64; }
+template <>
+const float *svals<float>(const Level &L) { return L.S.s32; }
+template <typename TV>
 const TV *minv(const Level &L);
 template <>
-const double *minv<double>(const Level &L) { return L.minv64; }
+const double *minv<double>(const Level &L) { return L.sminv64; }
 template <>
-const float *minv<float>(const Level &L) { return L.minv32; }
+const float *minv<float>(const Level &L) { return L.sminv32; }
 template <typename TV>
-const TV *pvals(const Level &L);
+const TV *ppv(const Level &L);
 template <>
-const double *pvals<double>(const Level &L) { return L.p64; }
+const double *ppv<double>(const Level &L) { return L.pp64; }
 template <>
-const float *pvals<float>(const Level &L) { return L.p32; }
-template <typename TV>
-const TV *pmvals(const Level &L);
-template <>
-const double *pmvals<double>(const Level &L) { return L.pm64; }
-template <>
-const float *pmvals<float>(const Level &L) { return L.pm32; }
+const float *ppv<float>(const Level &L) { return L.pp32; }
 
 void bfinalize(amg_hierarchy *h, int32_t op, int32_t nparts, int32_t maxit, const int32_t *stop) {
   Batch &B = *h->batch;
@@ -455,15 +468,15 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
     const BGeom g = bgeom(F.n, k, KT);
     if (l == 0)
       kb_pre_residual<TV, double, KT><<<g.grid, kBlock, 0, s>>>(
-          F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, (TV *)B.z[0],
+          F.n, k, g.chunk, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), R0, (TV *)B.z[0],
           (TV *)B.t[0], stop);
     else
       kb_pre_residual<TV, TV, KT><<<g.grid, kBlock, 0, s>>>(
-          F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), (const TV *)B.r[l],
+          F.n, k, g.chunk, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), (const TV *)B.r[l],
           (TV *)B.z[l], (TV *)B.t[l], stop);
     const Level &C = h->lv[l + 1];
     kb_restrict<TV, KT><<<egrid(C.n, k, KT), kBlock, 0, s>>>(
-        C.n, k, F.mptr, F.mem, pmvals<TV>(F), (const TV *)B.t[l], (TV *)B.r[l + 1], stop);
+        C.n, k, F.seg, ppv<TV>(F), (const TV *)B.t[l], (TV *)B.r[l + 1], stop);
   }
   const int32_t nL = h->C.n;
   kb_coarse<TV, TV><<<ceil_div((int64_t)nL * k, kBlock), kBlock, 0, s>>>(
@@ -471,7 +484,7 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
   for (int32_t l = L - 1; l >= 0; --l) {
     Level &F = h->lv[l];
     kb_prolong<TV, KT><<<egrid(F.n, k, KT), kBlock, 0, s>>>(
-        F.n, k, F.agg, pvals<TV>(F), (const TV *)B.y[l + 1], (TV *)B.z[l], stop);
+        F.n, k, F.aggp, ppv<TV>(F), (const TV *)B.y[l + 1], (TV *)B.z[l], stop);
     const BGeom g = bgeom(F.n, k, KT);
     if (l > 0) {
       kb_post<TV, TV, TV, KT, false><<<g.grid, kBlock, 0, s>>>(
@@ -611,6 +624,7 @@ amg_status ensure_batch(amg_hierarchy *h, int32_t k) {
   }
   const size_t e0 = (size_t)h->lv[0].n * k * sizeof(double);
   AMG_TRY(balloc(h, (void **)&B.X, e0));
+  AMG_TRY(balloc(h, (void **)&B.Bp, e0));
   AMG_TRY(balloc(h, (void **)&B.R, e0));
   AMG_TRY(balloc(h, (void **)&B.Z, e0));
   AMG_TRY(balloc(h, (void **)&B.P, e0));
@@ -709,7 +723,6 @@ amg_status pcg_batch(amg_hierarchy *h, int32_t k, const double *Bu, double *Xu, 
   hipStream_t s = h->stream;
   const bool fp32 = h->params.precision == AMG_FP32;
   const int32_t n = h->lv[0].n;
-  const size_t e0 = (size_t)n * k * sizeof(double);
   AMG_TRY(ensure_batch(h, k));
   Batch &B = *h->batch;
   if (B.kt == 0) {
@@ -733,10 +746,13 @@ amg_status pcg_batch(amg_hierarchy *h, int32_t k, const double *Bu, double *Xu, 
     }
     (void)hipGetLastError();
   }
-  AMG_HIP(hipMemcpyAsync(B.X, Xu, e0, hipMemcpyDeviceToDevice, s));
+  const int32_t *perm0 = h->lv[0].perm;
+  const int32_t pgrid = ceil_div((int64_t)n * k, kBlock);
+  kb_permute_rows<true><<<pgrid, kBlock, 0, s>>>(n, k, perm0, Xu, B.X);
+  kb_permute_rows<true><<<pgrid, kBlock, 0, s>>>(n, k, perm0, Bu, B.Bp);
   kb_init_cols<<<ceil_div(k, 64), 64, 0, s>>>(k, rtol, maxit, B.col, B.iter, B.done, B.all_done);
   int32_t np = 0;
-  spmv_mode(h, B.X, Bu, B.R, 1, &np);
+  spmv_mode(h, B.X, B.Bp, B.R, 1, &np);
   bfinalize(h, bInit, np, maxit, nullptr);
   small_kernel(h, 0);  // zero the columns of zero right-hand sides
   kb_all_done<<<1, 64, 0, s>>>(k, B.done, B.all_done);
@@ -780,9 +796,9 @@ amg_status pcg_batch(amg_hierarchy *h, int32_t k, const double *Bu, double *Xu, 
   }
   // columns still running at maxit
   AMG_HIP(hipMemcpyAsync(B.iter_host, B.iter, sizeof(int32_t) * k, hipMemcpyDeviceToHost, s));
-  spmv_mode(h, B.X, Bu, nullptr, 2, &np);
+  spmv_mode(h, B.X, B.Bp, nullptr, 2, &np);
   bfinalize(h, bTrue, np, maxit, nullptr);
-  AMG_HIP(hipMemcpyAsync(Xu, B.X, e0, hipMemcpyDeviceToDevice, s));
+  kb_permute_rows<false><<<pgrid, kBlock, 0, s>>>(n, k, perm0, B.X, Xu);
   AMG_HIP(hipMemcpyAsync(B.col_host, B.col, sizeof(double) * kColFields * k,
                          hipMemcpyDeviceToHost, s));
   AMG_HIP(hipMemcpyAsync(B.done_host, B.done, sizeof(int32_t) * k, hipMemcpyDeviceToHost, s));

@@ -534,11 +534,6 @@ __global__ void k_member_merge(int32_t nc, const int32_t *lead, const int32_t *m
   }
 }
 
-__global__ void k_gather_p(int32_t n, const int32_t *mem, const double *p, double *pm) {
-  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) pm[k] = p[mem[k]];
-}
-
 // ---------------------------------------------------------------------------
 // l1-Jacobi diagonal, eq. (l1weights) with blocks of one row
 // ---------------------------------------------------------------------------
@@ -947,13 +942,11 @@ amg_status build_hierarchy(amg_hierarchy *h, const amg_csr *A) {
     AMG_TRY(dalloc(h, &F.p64, (size_t)n));
     AMG_TRY(dalloc(h, &F.mptr, (size_t)cur.n + 1));
     AMG_TRY(dalloc(h, &F.mem, (size_t)n));
-    AMG_TRY(dalloc(h, &F.pm64, (size_t)n));
     AMG_HIP(hipMemcpyAsync(F.agg, agg_c, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
     AMG_HIP(hipMemcpyAsync(F.p64, p_c, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     AMG_HIP(hipMemcpyAsync(F.mptr, mptr, sizeof(int32_t) * (cur.n + 1), hipMemcpyDeviceToDevice,
                            s));
     AMG_HIP(hipMemcpyAsync(F.mem, mem, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
-    k_gather_p<<<grid(n), kBlock, 0, s>>>(n, F.mem, F.p64, F.pm64);
     h->lv.emplace_back();
     AMG_TRY(adopt_level(h, cur, h->lv[l + 1]));
     AMG_HIP(hipStreamSynchronize(s));

@@ -1,26 +1,29 @@
-// Solve phase: V-cycle of eq. (amg) with l1-Jacobi smoothing (Section 3.3)
+// Solve phase: the V-cycle of eq. (amg) with l1-Jacobi smoothing (Section 3.3)
 // inside preconditioned CG (Section 5), on one gfx950 GPU.
 //
-// Every level is stored as sliced ELLPACK with 64-row slices (one slice per
-// wavefront, column-major inside the slice), so lane i of a wavefront loads
-// row i's k-th value and column index from consecutive addresses; the 7-point
-// rows waste about 0.5% to padding. The streaming kernels are HBM-bound:
-// each keeps one row per lane and touches every array once.
+// Layout. Every level is stored in an aggregate-major order (the unknowns of
+// an aggregate of P_l are one contiguous segment, segments ordered like the
+// coarse unknowns, recursively from the coarsest level), as sliced ELLPACK
+// with 64-row slices (one slice per wavefront, column-major inside a slice),
+// so lane i of a wavefront loads row i's k-th value and column index from
+// consecutive addresses. The matrix arrays are loaded with a nontemporal
+// hint: they stream once per SpMV while the gathered vector stays in L2.
 //
-// Kernels of one V-cycle level l < L (zero initial guess):
-//   pre_residual : z = M^-1 r ; t = r - A z        (one SpMV, z gathered as r/m)
-//   restrict     : r_c = P^T t                     (members in ascending order)
-//   ...            level l + 1 ...
-//   prolong      : z += P z_c
-//   post         : y = z + M^-1 (r - A z)          (one SpMV; on level 0 it
-//                                                   also forms (r, y) for CG)
-// and on level L a dense solve with the inverse Cholesky factor.
+// Kernels of a V-cycle (zero initial guess), per level l < L:
+//   down  pre_restrict : z = M^-1 r ; r_{l+1} = P^T (r - A z)
+//         (A M^-1 is stored, so one vector is gathered; a block owns whole
+//          aggregates and sums their members in LDS: the residual never
+//          goes to HBM)
+//   up    post_prolong : y = z + M^-1 (r - A z) on level l + 1, and at once
+//         z_l += P y for the segments of the block's coarse rows
+//   level L: coarse_prolong: z_L = A_L^-1 r_L and z_{L-1} += P z_L
+//   level 0: post with the (r, z) partial sums for CG
 //
-// CG scalars live on the device; reductions are two-stage and
-// deterministic: each block writes a partial, the last block to arrive sums
-// the partials in a fixed order and updates the scalars. Kernels of an
-// iteration read a device flag and return at once after convergence, so the
-// host can queue several iterations between checks.
+// CG scalars live on the device; reductions are two-stage and deterministic:
+// every block writes its partial sums, a one-block finalize kernel adds them
+// in block order and updates the scalars. Kernels test a device flag and
+// return at once after convergence, so the host queues several iterations
+// (captured in a hipGraph) between checks.
 
 #include <chrono>
 #include <cmath>
@@ -37,8 +40,11 @@ double now_ms() {
       .count();
 }
 
+inline int32_t grid1(int64_t n) { return ceil_div(n > 0 ? n : 1, kBlock); }
+
 // ---------------------------------------------------------------------------
-// launch geometry: each block handles a contiguous chunk of rows
+// launch geometry of the row-streaming kernels: one row per thread, each
+// block a contiguous chunk (more rows per thread only beyond kMaxParts blocks)
 // ---------------------------------------------------------------------------
 
 struct Geom {
@@ -46,8 +52,7 @@ struct Geom {
   int32_t chunk;  // rows per block, a multiple of kBlock
 };
 
-Geom geom(int64_t n, bool reduce) {
-  (void)reduce;
+Geom geom(int64_t n) {
   int64_t blocks = (n + kBlock - 1) / kBlock;
   if (blocks < 1) blocks = 1;
   if (blocks > kMaxParts) {
@@ -58,17 +63,23 @@ Geom geom(int64_t n, bool reduce) {
 }
 
 __device__ __forceinline__ void rows_of_block(int32_t n, int32_t chunk, int32_t *b, int32_t *e) {
-  const int32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t bb = (int64_t)lb * chunk;
+  const int64_t bb = (int64_t)blockIdx.x * chunk;
   *b = (int32_t)bb;
   *e = (int32_t)(bb + chunk < n ? bb + chunk : n);
 }
 
+__device__ __forceinline__ void sell_row(const int32_t *sptr, int32_t row, int32_t *base,
+                                         int32_t *w) {
+  const int32_t s = row / kSlice;
+  const int32_t b0 = sptr[s];
+  *base = b0 + (row % kSlice);
+  *w = (sptr[s + 1] - b0) / kSlice;
+}
+
 // ---------------------------------------------------------------------------
-// deterministic two-stage reductions: every block writes its partial sums;
-// a one-block finalize kernel adds them in block order and updates the CG
-// scalars. (No in-kernel cross-block handshake: on gfx950 a device-scope
-// fence per block writes back the XCD's L2 and costs more than a launch.)
+// deterministic two-stage reductions (no in-kernel cross-block handshake: on
+// gfx950 a device-scope fence per block writes back the XCD's L2 and costs
+// more than the extra launch)
 // ---------------------------------------------------------------------------
 
 template <int NV>
@@ -107,19 +118,19 @@ __global__ void __launch_bounds__(1024) k_finalize(int32_t op, int32_t nparts,
   __shared__ double sh[2][1024 / kWave];
   const int nv = op == kFinInit ? 2 : 1;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  double tot[2] = {0.0, 0.0};
   for (int q = 0; q < nv; ++q) {
     double a = 0.0;
-    for (int32_t b = threadIdx.x; b < nparts; b += blockDim.x) a += partials[(int64_t)q * kMaxParts + b];
+    for (int32_t b = threadIdx.x; b < nparts; b += blockDim.x)
+      a += partials[(int64_t)q * kMaxParts + b];
     for (int o = kWave / 2; o > 0; o >>= 1) a += __shfl_down(a, o, kWave);
     if (lane == 0) sh[q][wid] = a;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  const int nw = blockDim.x / kWave;
+  double tot[2] = {0.0, 0.0};
   for (int q = 0; q < nv; ++q) {
     double t = sh[q][0];
-    for (int k = 1; k < nw; ++k) t += sh[q][k];
+    for (int k = 1; k < (int)(blockDim.x / kWave); ++k) t += sh[q][k];
     tot[q] = t;
   }
   switch (op) {
@@ -162,33 +173,103 @@ __global__ void __launch_bounds__(1024) k_finalize(int32_t op, int32_t nparts,
 }
 
 // ---------------------------------------------------------------------------
-// SELL construction and precision demotion
+// aggregate-major order, SELL construction, precision demotion
 // ---------------------------------------------------------------------------
 
-__global__ void k_sell_width(int32_t n, int32_t ns, const int32_t *rp, int32_t *w64) {
+// number of members of the aggregate at each coarse position
+__global__ void k_seg_count(int32_t nc, const int32_t *perm_c, const int32_t *mptr,
+                            int32_t *cnt) {
+  const int32_t J = blockIdx.x * blockDim.x + threadIdx.x;
+  if (J >= nc) return;
+  const int32_t I = perm_c[J];
+  cnt[J] = mptr[I + 1] - mptr[I];
+}
+
+// positions of the members of each aggregate (in ascending original index)
+__global__ void k_order_fill(int32_t nc, const int32_t *perm_c, const int32_t *mptr,
+                             const int32_t *mem, const int32_t *seg, const double *p,
+                             int32_t *perm, int32_t *iperm, int32_t *aggp, double *pp) {
+  const int32_t J = blockIdx.x * blockDim.x + threadIdx.x;
+  if (J >= nc) return;
+  const int32_t I = perm_c[J];
+  const int32_t b = mptr[I], e = mptr[I + 1], k0 = seg[J];
+  for (int32_t m = b; m < e; ++m) {
+    const int32_t i = mem[m], k = k0 + (m - b);
+    perm[k] = i;
+    iperm[i] = k;
+    aggp[k] = J;
+    pp[k] = p[i];
+  }
+}
+
+__global__ void k_iota_i32(int32_t *a, int32_t n) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = i;
+}
+
+__global__ void k_gather_f64(int32_t n, const int32_t *perm, const double *src, double *dst) {
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[k] = src[perm[k]];
+}
+
+__global__ void k_sell_width(int32_t n, int32_t ns, const int32_t *rp, const int32_t *perm,
+                             int32_t *w64) {
   const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= ns) return;
   const int32_t r0 = s * kSlice, r1 = min(n, r0 + kSlice);
   int32_t w = 0;
-  for (int32_t r = r0; r < r1; ++r) w = max(w, rp[r + 1] - rp[r]);
+  for (int32_t k = r0; k < r1; ++k) {
+    const int32_t i = perm[k];
+    w = max(w, rp[i + 1] - rp[i]);
+  }
   w64[s] = w * kSlice;
 }
 
+// Row k of the permuted matrix is original row perm[k] with columns renumbered
+// by iperm and sorted (rows up to kSortCap entries); padding entries point at
+// the row itself with value 0.
+constexpr int kSortCap = 64;
 __global__ void k_sell_fill(int32_t n, int32_t ns, const int32_t *rp, const int32_t *ci,
-                            const double *val, const int32_t *sptr, int32_t *col, double *v64,
-                            float *v32) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= (int64_t)ns * kSlice) return;
-  const int32_t s = (int32_t)(r / kSlice), lane = (int32_t)(r % kSlice);
+                            const double *val, const int32_t *perm, const int32_t *iperm,
+                            const double *minv, const int32_t *sptr, int32_t *col, double *v64,
+                            float *v32, double *s64, float *s32) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (int64_t)ns * kSlice) return;
+  const int32_t s = (int32_t)(k / kSlice), lane = (int32_t)(k % kSlice);
   const int32_t base = sptr[s], w = (sptr[s + 1] - base) / kSlice;
-  const int32_t b = r < n ? rp[r] : 0, len = r < n ? rp[r + 1] - b : 0;
-  for (int32_t k = 0; k < w; ++k) {
-    const int64_t idx = base + (int64_t)k * kSlice + lane;
-    const bool real = k < len;
-    const double a = real ? val[b + k] : 0.0;
-    col[idx] = real ? ci[b + k] : (r < n ? (int32_t)r : 0);
-    if (v64) v64[idx] = a;
-    if (v32) v32[idx] = (float)a;
+  const int32_t i = k < n ? perm[k] : 0;
+  const int32_t b = k < n ? rp[i] : 0, len = k < n ? rp[i + 1] - b : 0;
+  int32_t order[kSortCap];
+  const bool sorted = len <= kSortCap;
+  if (sorted) {
+    for (int32_t e = 0; e < len; ++e) {
+      const int32_t c = iperm[ci[b + e]];
+      int32_t pos = e;
+      while (pos > 0 && iperm[ci[b + order[pos - 1]]] > c) {
+        order[pos] = order[pos - 1];
+        --pos;
+      }
+      order[pos] = e;
+    }
+  }
+  for (int32_t e = 0; e < w; ++e) {
+    const int64_t idx = base + (int64_t)e * kSlice + lane;
+    if (e < len) {
+      const int32_t src = b + (sorted ? order[e] : e);
+      const int32_t c = ci[src];
+      const double a = val[src];
+      col[idx] = iperm[c];
+      if (v64) v64[idx] = a;
+      if (v32) v32[idx] = (float)a;
+      if (s64) s64[idx] = a * minv[c];
+      if (s32) s32[idx] = (float)(a * minv[c]);
+    } else {
+      col[idx] = k < n ? (int32_t)k : 0;
+      if (v64) v64[idx] = 0.0;
+      if (v32) v32[idx] = 0.f;
+      if (s64) s64[idx] = 0.0;
+      if (s32) s32[idx] = 0.f;
+    }
   }
 }
 
@@ -197,39 +278,61 @@ __global__ void k_demote(int64_t n, const double *a, float *b) {
   if (i < n) b[i] = (float)a[i];
 }
 
-// ---------------------------------------------------------------------------
-// V-cycle kernels. TV: hierarchy precision; TR: type of the level's right-hand
-// side (double on level 0, TV below); TO: type of the level's output.
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ void sell_slice(const int32_t *sptr, int32_t row, int32_t *base,
-                                           int32_t *w) {
-  const int32_t s = row / kSlice;
-  *base = sptr[s] + (row % kSlice);
-  *w = (sptr[s + 1] - sptr[s]) / kSlice;
+__global__ void k_permute_in(int32_t n, const int32_t *__restrict__ perm,
+                             const double *__restrict__ src, double *__restrict__ dst) {
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[k] = src[perm[k]];
 }
 
-// z = M^-1 r ; t = r - A z  (z_j gathered as r_j m_j^-1)
-template <typename TV, typename TR>
-__global__ void __launch_bounds__(kBlock) k_pre_residual(
-    int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
-    const TV *__restrict__ val, const TV *__restrict__ minv, const TR *__restrict__ r,
-    TV *__restrict__ z, TV *__restrict__ t, const int32_t *__restrict__ done) {
+__global__ void k_permute_out(int32_t n, const int32_t *__restrict__ perm,
+                              const double *__restrict__ src, double *__restrict__ dst) {
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[perm[k]] = src[k];
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle kernels. TV: hierarchy precision; TR: type of the level's
+// right-hand side (double on level 0, TV below); TO: type of its output.
+// ---------------------------------------------------------------------------
+
+// Down step on level l for the coarse positions [J0, J0 + G) of this block:
+// z = M^-1 r (FROM_Z = false; the residual uses the stored A M^-1) or, after
+// extra pre-smoothing sweeps, the given z (FROM_Z = true, plain A); then
+// r_{l+1}(J) = sum over the segment of J, in order, of p_k (r - A z)_k.
+// The block's fine rows are the union of its segments (at most kBlock rows).
+template <typename TV, typename TR, bool FROM_Z>
+__global__ void __launch_bounds__(kBlock) k_pre_restrict(
+    int32_t nc, int32_t G, const int32_t *__restrict__ seg, const int32_t *__restrict__ sptr,
+    const int32_t *__restrict__ col, const TV *__restrict__ val, const TV *__restrict__ minv,
+    const TV *__restrict__ pp, const TR *__restrict__ r, TV *__restrict__ z,
+    TV *__restrict__ rc, const int32_t *__restrict__ done) {
+  __shared__ TV sh[kBlock];
   if (*done) return;
-  int32_t rb, re;
-  rows_of_block(n, chunk, &rb, &re);
-  for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
+  const int32_t J0 = blockIdx.x * G;
+  const int32_t J1 = min(nc, J0 + G);
+  const int32_t f0 = seg[J0], f1 = seg[J1];
+  const int32_t row = f0 + threadIdx.x;
+  if (row < f1) {
     int32_t base, w;
-    sell_slice(sptr, row, &base, &w);
+    sell_row(sptr, row, &base, &w);
     TV acc = 0;
     for (int32_t k = 0; k < w; ++k) {
       const int32_t idx = base + k * kSlice;
-      const int32_t j = col[idx];
-      acc += val[idx] * ((TV)r[j] * minv[j]);
+      const int32_t c = ld_stream(&col[idx]);
+      if (FROM_Z) acc += ld_stream(&val[idx]) * z[c];
+      else acc += ld_stream(&val[idx]) * (TV)r[c];
     }
     const TV ri = (TV)r[row];
-    z[row] = ri * minv[row];
-    t[row] = ri - acc;
+    if (!FROM_Z) z[row] = ri * minv[row];
+    sh[threadIdx.x] = pp[row] * (ri - acc);
+  }
+  __syncthreads();
+  const int32_t J = J0 + (int32_t)threadIdx.x;
+  if ((int32_t)threadIdx.x < G && J < J1) {
+    const int32_t b = seg[J] - f0, e = seg[J + 1] - f0;
+    TV s = 0;
+    for (int32_t m = b; m < e; ++m) s += sh[m];
+    rc[J] = s;
   }
 }
 
@@ -246,11 +349,11 @@ __global__ void __launch_bounds__(kBlock) k_post(
   double d[1] = {0.0};
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
-    sell_slice(sptr, row, &base, &w);
+    sell_row(sptr, row, &base, &w);
     TV acc = 0;
     for (int32_t k = 0; k < w; ++k) {
       const int32_t idx = base + k * kSlice;
-      acc += val[idx] * z[col[idx]];
+      acc += ld_stream(&val[idx]) * z[ld_stream(&col[idx])];
     }
     const TR rr = r[row];
     const TO yo = (TO)(z[row] + ((TV)rr - acc) * minv[row]);
@@ -260,64 +363,58 @@ __global__ void __launch_bounds__(kBlock) k_post(
   if (DOT) block_partial<1>(d, partials);
 }
 
-// z = M^-1 r (first of several pre-smoothing sweeps)
-template <typename TV, typename TR>
-__global__ void k_jacobi0(int32_t n, const TV *minv, const TR *r, TV *z, const int32_t *done) {
+// Up step: post-smoothing of the coarse level c for this block's kBlock
+// coarse rows, y = z_c + M^-1 (r_c - A_c z_c) (kept in LDS), then the
+// prolongation z_f += P y over the fine segments of those rows.
+template <typename TV>
+__global__ void __launch_bounds__(kBlock) k_post_prolong(
+    int32_t nc, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
+    const TV *__restrict__ val, const TV *__restrict__ minv, const TV *__restrict__ rcv,
+    const TV *__restrict__ zc, const int32_t *__restrict__ seg, const int32_t *__restrict__ aggp,
+    const TV *__restrict__ pp, TV *__restrict__ zf, const int32_t *__restrict__ done) {
+  __shared__ TV sh[kBlock];
   if (*done) return;
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) z[i] = (TV)r[i] * minv[i];
-}
-
-// t = r - A z
-template <typename TV, typename TR>
-__global__ void __launch_bounds__(kBlock) k_residual(
-    int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
-    const TV *__restrict__ val, const TR *__restrict__ r, const TV *__restrict__ z,
-    TV *__restrict__ t, const int32_t *__restrict__ done) {
-  if (*done) return;
-  int32_t rb, re;
-  rows_of_block(n, chunk, &rb, &re);
-  for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
+  const int32_t J0 = blockIdx.x * kBlock;
+  const int32_t J = J0 + threadIdx.x;
+  if (J < nc) {
     int32_t base, w;
-    sell_slice(sptr, row, &base, &w);
+    sell_row(sptr, J, &base, &w);
     TV acc = 0;
     for (int32_t k = 0; k < w; ++k) {
       const int32_t idx = base + k * kSlice;
-      acc += val[idx] * z[col[idx]];
+      acc += ld_stream(&val[idx]) * zc[ld_stream(&col[idx])];
     }
-    t[row] = (TV)r[row] - acc;
+    sh[threadIdx.x] = zc[J] + (rcv[J] - acc) * minv[J];
   }
+  __syncthreads();
+  const int32_t J1 = min(nc, J0 + kBlock);
+  const int32_t f0 = seg[J0], f1 = seg[J1];
+  for (int32_t k = f0 + threadIdx.x; k < f1; k += kBlock) zf[k] += pp[k] * sh[aggp[k] - J0];
 }
 
-// r_c(I) = sum over members i of I (ascending) of p_i t_i
+// Coarsest level with prolongation: z_L = A_L^-1 r_L (one wavefront per row,
+// rows kept in LDS), then z_f += P z_L over all fine positions. One block.
 template <typename TV>
-__global__ void k_restrict(int32_t nc, const int32_t *__restrict__ mptr,
-                           const int32_t *__restrict__ mem, const TV *__restrict__ pm,
-                           const TV *__restrict__ t, TV *__restrict__ rc,
-                           const int32_t *__restrict__ done) {
+__global__ void __launch_bounds__(1024) k_coarse_prolong(
+    int32_t nL, const double *__restrict__ Ainv, const TV *__restrict__ rL, int32_t nf,
+    const int32_t *__restrict__ aggp, const TV *__restrict__ pp, TV *__restrict__ zf,
+    const int32_t *__restrict__ done) {
+  extern __shared__ double zs[];
   if (*done) return;
-  const int32_t I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nc) return;
-  const int32_t b = mptr[I], e = mptr[I + 1];
-  TV s = 0;
-  for (int32_t k = b; k < e; ++k) s += pm[k] * t[mem[k]];
-  rc[I] = s;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int nw = blockDim.x / kWave;
+  for (int32_t i = threadIdx.x / kWave; i < nL; i += nw) {
+    const double *row = Ainv + (int64_t)i * nL;
+    double s = 0.0;
+    for (int32_t k = lane; k < nL; k += kWave) s += row[k] * (double)rL[k];
+    for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_down(s, o, kWave);
+    if (lane == 0) zs[i] = s;
+  }
+  __syncthreads();
+  for (int32_t k = threadIdx.x; k < nf; k += blockDim.x) zf[k] += pp[k] * (TV)zs[aggp[k]];
 }
 
-// z += P z_c
-template <typename TV>
-__global__ void k_prolong(int32_t n, const int32_t *__restrict__ agg, const TV *__restrict__ p,
-                          const TV *__restrict__ zc, TV *__restrict__ z,
-                          const int32_t *__restrict__ done) {
-  if (*done) return;
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) z[i] += p[i] * zc[agg[i]];
-}
-
-// Coarsest level: z = A_L^-1 r with A_L^-1 = L^-T L^-1 formed from the
-// Cholesky factor at setup (row-major, symmetric). One wavefront per row,
-// lanes stride the columns (coalesced), so every row's loads are in flight
-// together instead of two sequential triangular sweeps.
+// Single-level hierarchy: z = A_0^-1 r, one wavefront per row.
 constexpr int kCoarseWaves = 4;
 template <typename TI, typename TO>
 __global__ void __launch_bounds__(kWave *kCoarseWaves) k_coarse_solve(
@@ -334,6 +431,14 @@ __global__ void __launch_bounds__(kWave *kCoarseWaves) k_coarse_solve(
   if (lane == 0) z[i] = (TO)s;
 }
 
+// z = M^-1 r (first of several pre-smoothing sweeps)
+template <typename TV, typename TR>
+__global__ void k_jacobi0(int32_t n, const TV *minv, const TR *r, TV *z, const int32_t *done) {
+  if (*done) return;
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = (TV)r[i] * minv[i];
+}
+
 // partials of (r, z) when level 0 is itself the coarsest level
 __global__ void __launch_bounds__(kBlock) k_dot_rz(int32_t n, int32_t chunk, const double *r,
                                                    const double *z, double *partials,
@@ -347,7 +452,7 @@ __global__ void __launch_bounds__(kBlock) k_dot_rz(int32_t n, int32_t chunk, con
 }
 
 // ---------------------------------------------------------------------------
-// outer CG kernels (FP64)
+// outer CG kernels (FP64, aggregate-major order of level 0)
 // ---------------------------------------------------------------------------
 
 __global__ void k_scal_init(PcgScal *s, double rtol, int32_t maxit) {
@@ -366,51 +471,37 @@ __global__ void k_scal_init(PcgScal *s, double rtol, int32_t maxit) {
   s->phase = 0;
 }
 
-// r = b - A x ; partials of (b, b), (r, r)
-__global__ void __launch_bounds__(kBlock) k_init_residual(
+// MODE 0: r = b - A x and partials of (b, b), (r, r)
+// MODE 1: partials of ||b - A x||^2 only
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_residual_norms(
     int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
     const double *__restrict__ val, const double *__restrict__ b, const double *__restrict__ x,
     double *__restrict__ r, double *__restrict__ partials) {
+  constexpr int NV = MODE == 0 ? 2 : 1;
   int32_t rb, re;
   rows_of_block(n, chunk, &rb, &re);
-  double d[2] = {0.0, 0.0};
+  double d[NV];
+  for (int q = 0; q < NV; ++q) d[q] = 0.0;
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
-    sell_slice(sptr, row, &base, &w);
+    sell_row(sptr, row, &base, &w);
     double acc = 0.0;
     for (int32_t k = 0; k < w; ++k) {
       const int32_t idx = base + k * kSlice;
-      acc += val[idx] * x[col[idx]];
+      acc += ld_stream(&val[idx]) * x[ld_stream(&col[idx])];
     }
     const double bi = b[row];
     const double ri = bi - acc;
-    r[row] = ri;
-    d[0] += bi * bi;
-    d[1] += ri * ri;
-  }
-  block_partial<2>(d, partials);
-}
-
-// partials of ||b - A x||^2 at exit
-__global__ void __launch_bounds__(kBlock) k_true_residual(
-    int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
-    const double *__restrict__ val, const double *__restrict__ b, const double *__restrict__ x,
-    double *__restrict__ partials) {
-  int32_t rb, re;
-  rows_of_block(n, chunk, &rb, &re);
-  double d[1] = {0.0};
-  for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
-    int32_t base, w;
-    sell_slice(sptr, row, &base, &w);
-    double acc = 0.0;
-    for (int32_t k = 0; k < w; ++k) {
-      const int32_t idx = base + k * kSlice;
-      acc += val[idx] * x[col[idx]];
+    if (MODE == 0) {
+      r[row] = ri;
+      d[0] += bi * bi;
+      d[NV - 1] += ri * ri;
+    } else {
+      d[0] += ri * ri;
     }
-    const double ri = b[row] - acc;
-    d[0] += ri * ri;
   }
-  block_partial<1>(d, partials);
+  block_partial<NV>(d, partials);
 }
 
 __global__ void k_zero_if_zero_rhs(int32_t n, double *x, const PcgScal *scal) {
@@ -430,11 +521,11 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot(
   double d[1] = {0.0};
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
-    sell_slice(sptr, row, &base, &w);
+    sell_row(sptr, row, &base, &w);
     double acc = 0.0;
     for (int32_t k = 0; k < w; ++k) {
       const int32_t idx = base + k * kSlice;
-      acc += val[idx] * p[col[idx]];
+      acc += ld_stream(&val[idx]) * p[ld_stream(&col[idx])];
     }
     q[row] = acc;
     d[0] += p[row] * acc;
@@ -465,26 +556,18 @@ __global__ void __launch_bounds__(kBlock) k_update_xr(int32_t n, int32_t chunk,
   block_partial<1>(d, partials);
 }
 
-// p = z + beta p
+// p = z + beta p (copy: p = z)
 __global__ void k_xpay(int32_t n, const double *__restrict__ z, double *__restrict__ p,
-                       const PcgScal *__restrict__ scal, const int32_t *__restrict__ done) {
+                       const PcgScal *__restrict__ scal, int32_t copy,
+                       const int32_t *__restrict__ done) {
   if (*done) return;
   const double beta = scal->beta;
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = z[i] + beta * p[i];
+  if (i < n) p[i] = copy ? z[i] : z[i] + beta * p[i];
 }
-
-__global__ void k_copy(int32_t n, const double *__restrict__ z, double *__restrict__ p,
-                       const int32_t *__restrict__ done) {
-  if (*done) return;
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = z[i];
-}
-
-inline int32_t grid1(int64_t n) { return ceil_div(n > 0 ? n : 1, kBlock); }
 
 // ---------------------------------------------------------------------------
-// host: V-cycle for one hierarchy precision
+// host: the V-cycle for one hierarchy precision
 // ---------------------------------------------------------------------------
 
 template <typename TV>
@@ -494,116 +577,132 @@ const double *vals<double>(const Level &L) { return L.S.v64; }
 template <>
 const float *vals<float>(const Level &L) { return L.S.v32; }
 template <typename TV>
+const TV *svals(const Level &L);
+template <>
+const double *svals<double>(const Level &L) { return L.S.s64; }
+template <>
+const float *svals<float>(const Level &L) { return L.S.s32; }
+template <typename TV>
 const TV *minv(const Level &L);
 template <>
-const double *minv<double>(const Level &L) { return L.minv64; }
+const double *minv<double>(const Level &L) { return L.sminv64; }
 template <>
-const float *minv<float>(const Level &L) { return L.minv32; }
+const float *minv<float>(const Level &L) { return L.sminv32; }
 template <typename TV>
-const TV *pvals(const Level &L);
+const TV *ppv(const Level &L);
 template <>
-const double *pvals<double>(const Level &L) { return L.p64; }
+const double *ppv<double>(const Level &L) { return L.pp64; }
 template <>
-const float *pvals<float>(const Level &L) { return L.p32; }
-template <typename TV>
-const TV *pmvals(const Level &L);
-template <>
-const double *pmvals<double>(const Level &L) { return L.pm64; }
-template <>
-const float *pmvals<float>(const Level &L) { return L.pm32; }
+const float *ppv<float>(const Level &L) { return L.pp32; }
 
 void finalize(amg_hierarchy *h, int32_t op, int32_t nparts, const int32_t *done) {
   k_finalize<<<1, 1024, 0, h->stream>>>(op, nparts, h->partials, h->scal, done);
 }
 
-// Pre-smoothing (pre sweeps) and residual on level l from right-hand side r.
-// Leaves t_l = r - A z in L.t and returns the buffer that holds z.
+int32_t coarse_per_block(const amg_hierarchy *h) {
+  const int32_t g = kBlock / h->max_seg;
+  return g < 1 ? 1 : g;
+}
+
+// down step on level l: smoothing from zero, residual, restriction into
+// level l + 1's right-hand side; returns the buffer holding z_l
 template <typename TV, typename TR>
 TV *launch_down(amg_hierarchy *h, int32_t l, const TR *r, const int32_t *done) {
   hipStream_t s = h->stream;
-  Level &L = h->lv[l];
-  TV *z = (TV *)L.z, *tmp = (TV *)L.y, *t = (TV *)L.t;
-  const Geom g = geom(L.n, false);
-  const int32_t pre = h->params.pre;
-  if (pre == 1) {
-    k_pre_residual<TV, TR><<<g.grid, kBlock, 0, s>>>(L.n, g.chunk, L.S.sptr, L.S.col, vals<TV>(L),
-                                                   minv<TV>(L), r, z, t, done);
+  Level &F = h->lv[l];
+  Level &C = h->lv[l + 1];
+  TV *z = (TV *)F.z, *tmp = (TV *)F.y;
+  const int32_t G = coarse_per_block(h);
+  const int32_t grid = ceil_div(C.n, G);
+  if (h->params.pre == 1) {
+    k_pre_restrict<TV, TR, false><<<grid, kBlock, 0, s>>>(C.n, G, F.seg, F.S.sptr, F.S.col,
+                                                         svals<TV>(F), minv<TV>(F), ppv<TV>(F), r,
+                                                         z, (TV *)C.r, done);
     return z;
   }
-  k_jacobi0<TV, TR><<<grid1(L.n), kBlock, 0, s>>>(L.n, minv<TV>(L), r, z, done);
-  for (int32_t k = 1; k < pre; ++k) {
-    k_post<TV, TR, TV, false><<<g.grid, kBlock, 0, s>>>(L.n, g.chunk, L.S.sptr, L.S.col,
-                                                       vals<TV>(L), minv<TV>(L), r, z, tmp,
+  const Geom g = geom(F.n);
+  k_jacobi0<TV, TR><<<grid1(F.n), kBlock, 0, s>>>(F.n, minv<TV>(F), r, z, done);
+  for (int32_t k = 1; k < h->params.pre; ++k) {
+    k_post<TV, TR, TV, false><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
+                                                       vals<TV>(F), minv<TV>(F), r, z, tmp,
                                                        nullptr, done);
     std::swap(z, tmp);
   }
-  k_residual<TV, TR><<<g.grid, kBlock, 0, s>>>(L.n, g.chunk, L.S.sptr, L.S.col, vals<TV>(L), r, z,
-                                             t, done);
+  k_pre_restrict<TV, TR, true><<<grid, kBlock, 0, s>>>(C.n, G, F.seg, F.S.sptr, F.S.col,
+                                                      vals<TV>(F), minv<TV>(F), ppv<TV>(F), r, z,
+                                                      (TV *)C.r, done);
   return z;
 }
 
-// Prolongation into z and post-smoothing on level l; the last sweep writes
-// `out` (a buffer other than z and L.t), with the (r, out) partials if dot.
-template <typename TV, typename TR, typename TO>
-void launch_up(amg_hierarchy *h, int32_t l, const TR *r, TV *z, const TV *zc, TO *out, bool dot,
-               const int32_t *done) {
+// up step on coarse level c >= 1: extra post sweeps, then the last sweep
+// fused with the prolongation into the finer level's z (zf)
+template <typename TV>
+void launch_up(amg_hierarchy *h, int32_t c, TV *zc, TV *zf, const int32_t *done) {
   hipStream_t s = h->stream;
-  Level &L = h->lv[l];
-  TV *tmp = (TV *)L.t;  // free once the restriction has read it
-  k_prolong<TV><<<grid1(L.n), kBlock, 0, s>>>(L.n, L.agg, pvals<TV>(L), zc, z, done);
-  const Geom g = geom(L.n, dot);
-  const int32_t post = h->params.post;
-  for (int32_t k = 0; k + 1 < post; ++k) {
-    k_post<TV, TR, TV, false><<<g.grid, kBlock, 0, s>>>(L.n, g.chunk, L.S.sptr, L.S.col,
-                                                       vals<TV>(L), minv<TV>(L), r, z, tmp,
-                                                       nullptr, done);
-    std::swap(z, tmp);
+  Level &C = h->lv[c];
+  Level &F = h->lv[c - 1];
+  TV *tmp = (TV *)C.y;
+  if (tmp == zc) tmp = (TV *)C.z;
+  const Geom g = geom(C.n);
+  for (int32_t k = 1; k < h->params.post; ++k) {
+    k_post<TV, TV, TV, false><<<g.grid, kBlock, 0, s>>>(C.n, g.chunk, C.S.sptr, C.S.col,
+                                                       vals<TV>(C), minv<TV>(C), (const TV *)C.r,
+                                                       zc, tmp, nullptr, done);
+    std::swap(zc, tmp);
   }
-  if (dot) {
-    k_post<TV, TR, TO, true><<<g.grid, kBlock, 0, s>>>(L.n, g.chunk, L.S.sptr, L.S.col,
-                                                      vals<TV>(L), minv<TV>(L), r, z, out,
-                                                      h->partials, done);
-    finalize(h, kFinRZ, g.grid, done);
-  } else {
-    k_post<TV, TR, TO, false><<<g.grid, kBlock, 0, s>>>(L.n, g.chunk, L.S.sptr, L.S.col,
-                                                       vals<TV>(L), minv<TV>(L), r, z, out,
-                                                       nullptr, done);
-  }
+  k_post_prolong<TV><<<grid1(C.n), kBlock, 0, s>>>(C.n, C.S.sptr, C.S.col, vals<TV>(C),
+                                                   minv<TV>(C), (const TV *)C.r, zc, F.seg,
+                                                   F.aggp, ppv<TV>(F), zf, done);
 }
 
-template <typename TI, typename TO>
-void launch_coarse(amg_hierarchy *h, const TI *r, TO *z, const int32_t *done) {
-  const int32_t n = h->C.n;
-  k_coarse_solve<TI, TO><<<ceil_div(n, kCoarseWaves), kWave * kCoarseWaves, 0, h->stream>>>(
-      n, h->C.Ainv, r, z, done);
-}
-
+// V-cycle z0 = B r0 on the aggregate-major vectors of level 0
 template <typename TV>
 void vcycle_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const int32_t *done) {
+  hipStream_t s = h->stream;
   const int32_t L = (int32_t)h->lv.size() - 1;
   if (L == 0) {
-    launch_coarse<double, double>(h, r0, z0, done);
+    const int32_t n = h->C.n;
+    k_coarse_solve<double, double><<<ceil_div(n, kCoarseWaves), kWave * kCoarseWaves, 0, s>>>(
+        n, h->C.Ainv, r0, z0, done);
     if (dot) {
-      const Geom g = geom(h->lv[0].n, true);
-      k_dot_rz<<<g.grid, kBlock, 0, h->stream>>>(h->lv[0].n, g.chunk, r0, z0, h->partials, done);
+      const Geom g = geom(h->lv[0].n);
+      k_dot_rz<<<g.grid, kBlock, 0, s>>>(h->lv[0].n, g.chunk, r0, z0, h->partials, done);
       finalize(h, kFinRZ, g.grid, done);
     }
     return;
   }
-  std::vector<TV *> zbuf(L);
-  zbuf[0] = launch_down<TV, double>(h, 0, r0, done);
-  for (int32_t l = 0; l < L; ++l) {
-    Level &F = h->lv[l];
-    Level &C = h->lv[l + 1];
-    k_restrict<TV><<<grid1(C.n), kBlock, 0, h->stream>>>(C.n, F.mptr, F.mem, pmvals<TV>(F),
-                                                         (const TV *)F.t, (TV *)C.r, done);
-    if (l + 1 < L) zbuf[l + 1] = launch_down<TV, TV>(h, l + 1, (const TV *)C.r, done);
+  std::vector<TV *> zb(L);
+  zb[0] = launch_down<TV, double>(h, 0, r0, done);
+  for (int32_t l = 1; l < L; ++l)
+    zb[l] = launch_down<TV, TV>(h, l, (const TV *)h->lv[l].r, done);
+  {
+    Level &F = h->lv[L - 1];
+    const int32_t nL = h->C.n;
+    k_coarse_prolong<TV><<<1, 1024, sizeof(double) * nL, s>>>(
+        nL, h->C.Ainv, (const TV *)h->lv[L].r, F.n, F.aggp, ppv<TV>(F), zb[L - 1], done);
   }
-  launch_coarse<TV, TV>(h, (const TV *)h->lv[L].r, (TV *)h->lv[L].y, done);
-  for (int32_t l = L - 1; l >= 1; --l)
-    launch_up<TV, TV, TV>(h, l, (const TV *)h->lv[l].r, zbuf[l], (const TV *)h->lv[l + 1].y,
-                          (TV *)h->lv[l].y, false, done);
-  launch_up<TV, double, double>(h, 0, r0, zbuf[0], (const TV *)h->lv[1].y, z0, dot, done);
+  for (int32_t c = L - 1; c >= 1; --c) launch_up<TV>(h, c, zb[c], zb[c - 1], done);
+  // level 0: extra post sweeps, then the last with the (r, z) partials
+  Level &F = h->lv[0];
+  TV *z = zb[0], *tmp = (TV *)F.y;
+  if (tmp == z) tmp = (TV *)F.z;
+  const Geom g = geom(F.n);
+  for (int32_t k = 1; k < h->params.post; ++k) {
+    k_post<TV, double, TV, false><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
+                                                           vals<TV>(F), minv<TV>(F), r0, z, tmp,
+                                                           nullptr, done);
+    std::swap(z, tmp);
+  }
+  if (dot) {
+    k_post<TV, double, double, true><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
+                                                              vals<TV>(F), minv<TV>(F), r0, z, z0,
+                                                              h->partials, done);
+    finalize(h, kFinRZ, g.grid, done);
+  } else {
+    k_post<TV, double, double, false><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
+                                                               vals<TV>(F), minv<TV>(F), r0, z,
+                                                               z0, nullptr, done);
+  }
 }
 
 amg_status alloc_level_vectors(amg_hierarchy *h, Level &L, size_t vbytes) {
@@ -621,11 +720,37 @@ amg_status build_solve_formats(amg_hierarchy *h) {
   const bool fp32 = h->params.precision == AMG_FP32;
   const size_t vbytes = fp32 ? sizeof(float) : sizeof(double);
   const int32_t nlev = (int32_t)h->lv.size();
+  // aggregate-major order, from the coarsest level down
+  {
+    Level &C = h->lv[nlev - 1];
+    AMG_TRY(dalloc(h, &C.perm, (size_t)C.n));
+    AMG_TRY(dalloc(h, &C.iperm, (size_t)C.n));
+    k_iota_i32<<<grid1(C.n), kBlock, 0, s>>>(C.perm, C.n);
+    k_iota_i32<<<grid1(C.n), kBlock, 0, s>>>(C.iperm, C.n);
+  }
+  h->max_seg = 1;
+  for (int32_t l = nlev - 2; l >= 0; --l) {
+    Level &F = h->lv[l];
+    Level &C = h->lv[l + 1];
+    int32_t *cnt;
+    AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&cnt), sizeof(int32_t) * C.n + 16, s));
+    AMG_TRY(dalloc(h, &F.seg, (size_t)C.n + 1));
+    k_seg_count<<<grid1(C.n), kBlock, 0, s>>>(C.n, C.perm, F.mptr, cnt);
+    AMG_TRY(scan_exclusive_i32(cnt, F.seg, C.n, s));
+    AMG_HIP(hipFreeAsync(cnt, s));
+    AMG_TRY(dalloc(h, &F.perm, (size_t)F.n));
+    AMG_TRY(dalloc(h, &F.iperm, (size_t)F.n));
+    AMG_TRY(dalloc(h, &F.aggp, (size_t)F.n));
+    AMG_TRY(dalloc(h, &F.pp64, (size_t)F.n));
+    k_order_fill<<<grid1(C.n), kBlock, 0, s>>>(C.n, C.perm, F.mptr, F.mem, F.seg, F.p64, F.perm,
+                                              F.iperm, F.aggp, F.pp64);
+    h->max_seg = std::max(h->max_seg, 1 << F.sweeps);
+  }
   for (int32_t l = 0; l < nlev; ++l) {
     Level &L = h->lv[l];
     const bool coarsest = (l == nlev - 1);
-    // level 0 always needs the FP64 SELL for the outer CG; the V-cycle levels
-    // need the hierarchy precision; the coarsest uses its dense inverse only
+    // level 0 needs FP64 values for the outer CG; V-cycle levels need the
+    // hierarchy precision (plain and scaled); the coarsest uses A_L^-1 only
     const bool need64 = (l == 0) || (!coarsest && !fp32);
     const bool need32 = !coarsest && fp32;
     if (need64 || need32) {
@@ -635,7 +760,7 @@ amg_status build_solve_formats(amg_hierarchy *h) {
       int32_t *w64;
       AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&w64), sizeof(int32_t) * S.nslices + 16, s));
       AMG_TRY(dalloc(h, &S.sptr, (size_t)S.nslices + 1));
-      k_sell_width<<<grid1(S.nslices), kBlock, 0, s>>>(L.n, S.nslices, L.rp, w64);
+      k_sell_width<<<grid1(S.nslices), kBlock, 0, s>>>(L.n, S.nslices, L.rp, L.perm, w64);
       AMG_TRY(scan_exclusive_i32(w64, S.sptr, S.nslices, s));
       AMG_HIP(hipFreeAsync(w64, s));
       int32_t padded = 0;
@@ -646,22 +771,28 @@ amg_status build_solve_formats(amg_hierarchy *h) {
       AMG_TRY(dalloc(h, &S.col, (size_t)padded));
       if (need64) AMG_TRY(dalloc(h, &S.v64, (size_t)padded));
       if (need32) AMG_TRY(dalloc(h, &S.v32, (size_t)padded));
+      if (!coarsest && !fp32) AMG_TRY(dalloc(h, &S.s64, (size_t)padded));
+      if (need32) AMG_TRY(dalloc(h, &S.s32, (size_t)padded));
       k_sell_fill<<<ceil_div((int64_t)S.nslices * kSlice, kBlock), kBlock, 0, s>>>(
-          L.n, S.nslices, L.rp, L.ci, L.val, S.sptr, S.col, S.v64, S.v32);
+          L.n, S.nslices, L.rp, L.ci, L.val, L.perm, L.iperm, L.minv64, S.sptr, S.col, S.v64,
+          S.v32, S.s64, S.s32);
     }
-    if (!coarsest && fp32) {
-      AMG_TRY(dalloc(h, &L.minv32, (size_t)L.n));
-      AMG_TRY(dalloc(h, &L.p32, (size_t)L.n));
-      AMG_TRY(dalloc(h, &L.pm32, (size_t)L.n));
-      k_demote<<<grid1(L.n), kBlock, 0, s>>>(L.n, L.minv64, L.minv32);
-      k_demote<<<grid1(L.n), kBlock, 0, s>>>(L.n, L.p64, L.p32);
-      k_demote<<<grid1(L.n), kBlock, 0, s>>>(L.n, L.pm64, L.pm32);
+    if (!coarsest) {
+      AMG_TRY(dalloc(h, &L.sminv64, (size_t)L.n));
+      k_gather_f64<<<grid1(L.n), kBlock, 0, s>>>(L.n, L.perm, L.minv64, L.sminv64);
+      if (fp32) {
+        AMG_TRY(dalloc(h, &L.sminv32, (size_t)L.n));
+        AMG_TRY(dalloc(h, &L.pp32, (size_t)L.n));
+        k_demote<<<grid1(L.n), kBlock, 0, s>>>(L.n, L.sminv64, L.sminv32);
+        k_demote<<<grid1(L.n), kBlock, 0, s>>>(L.n, L.pp64, L.pp32);
+      }
     }
     AMG_TRY(alloc_level_vectors(h, L, vbytes));
   }
-  // outer CG vectors and scalars
+  // outer CG vectors and scalars (aggregate-major order of level 0)
   const int32_t n0 = h->lv[0].n;
   AMG_TRY(dalloc(h, &h->x, (size_t)n0));
+  AMG_TRY(dalloc(h, &h->b, (size_t)n0));
   AMG_TRY(dalloc(h, &h->r, (size_t)n0));
   AMG_TRY(dalloc(h, &h->z, (size_t)n0));
   AMG_TRY(dalloc(h, &h->p, (size_t)n0));
@@ -675,32 +806,46 @@ amg_status build_solve_formats(amg_hierarchy *h) {
   return AMG_OK;
 }
 
-amg_status vcycle(amg_hierarchy *h, const double *r, double *z, bool fuse_dot,
-                  const int32_t *done) {
+// Applies the V-cycle to vectors in the aggregate-major order of level 0.
+amg_status vcycle_perm(amg_hierarchy *h, const double *r, double *z, bool fuse_dot,
+                       const int32_t *done) {
   if (h->params.precision == AMG_FP32) vcycle_t<float>(h, r, z, fuse_dot, done);
   else vcycle_t<double>(h, r, z, fuse_dot, done);
   AMG_HIP(hipGetLastError());
   return AMG_OK;
 }
 
+// z = B r on vectors in the caller's numbering
+amg_status vcycle(amg_hierarchy *h, const double *r, double *z, bool fuse_dot,
+                  const int32_t *done) {
+  hipStream_t s = h->stream;
+  const int32_t n = h->lv[0].n;
+  k_permute_in<<<grid1(n), kBlock, 0, s>>>(n, h->lv[0].perm, r, h->r);
+  AMG_TRY(vcycle_perm(h, h->r, h->z, fuse_dot, done));
+  k_permute_out<<<grid1(n), kBlock, 0, s>>>(n, h->lv[0].perm, h->z, z);
+  AMG_HIP(hipGetLastError());
+  return AMG_OK;
+}
+
 namespace {
 
-// One CG iteration after the first preconditioning. Touches only hierarchy
-// buffers (x is the internal copy), so it can be captured once and replayed.
+// One CG iteration: q = A p, alpha, x and r updates with the stop test,
+// z = B r with (r, z) and beta, p = z + beta p. Touches only hierarchy
+// buffers, so it is captured once and replayed.
 void cg_iteration(amg_hierarchy *h) {
   hipStream_t s = h->stream;
   Level &L0 = h->lv[0];
   const int32_t n = L0.n;
   const int32_t *done = &h->scal->done;
-  const Geom g = geom(n, true);
+  const Geom g = geom(n);
   k_spmv_dot<<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, h->p, h->q,
                                        h->partials, done);
   finalize(h, kFinPQ, g.grid, done);
   k_update_xr<<<g.grid, kBlock, 0, s>>>(n, g.chunk, h->x, h->r, h->p, h->q, h->partials, h->scal,
                                         done);
   finalize(h, kFinRR, g.grid, done);
-  vcycle(h, h->r, h->z, true, done);
-  k_xpay<<<grid1(n), kBlock, 0, s>>>(n, h->z, h->p, h->scal, done);
+  vcycle_perm(h, h->r, h->z, true, done);
+  k_xpay<<<grid1(n), kBlock, 0, s>>>(n, h->z, h->p, h->scal, 0, done);
 }
 
 // Captures one CG iteration into a hipGraph (once per hierarchy).
@@ -734,23 +879,24 @@ amg_status ensure_iteration_graph(amg_hierarchy *h) {
 
 }  // namespace
 
-amg_status pcg(amg_hierarchy *h, const double *b, double *x_user, double rtol, int32_t maxit,
-               amg_solve_info *info) {
+amg_status pcg(amg_hierarchy *h, const double *b_user, double *x_user, double rtol,
+               int32_t maxit, amg_solve_info *info) {
   const double t0 = now_ms();
   hipStream_t s = h->stream;
   Level &L0 = h->lv[0];
   const int32_t n = L0.n;
   const int32_t *done = &h->scal->done;
-  const Geom g = geom(n, true);
+  const Geom g = geom(n);
   AMG_TRY(ensure_iteration_graph(h));
-  AMG_HIP(hipMemcpyAsync(h->x, x_user, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  k_permute_in<<<grid1(n), kBlock, 0, s>>>(n, L0.perm, b_user, h->b);
+  k_permute_in<<<grid1(n), kBlock, 0, s>>>(n, L0.perm, x_user, h->x);
   k_scal_init<<<1, 1, 0, s>>>(h->scal, rtol, maxit);
-  k_init_residual<<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, b, h->x,
-                                            h->r, h->partials);
+  k_residual_norms<0><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, h->b,
+                                               h->x, h->r, h->partials);
   finalize(h, kFinInit, g.grid, nullptr);
   k_zero_if_zero_rhs<<<grid1(n), kBlock, 0, s>>>(n, h->x, h->scal);
-  AMG_TRY(vcycle(h, h->r, h->z, true, done));
-  k_copy<<<grid1(n), kBlock, 0, s>>>(n, h->z, h->p, done);
+  AMG_TRY(vcycle_perm(h, h->r, h->z, true, done));
+  k_xpay<<<grid1(n), kBlock, 0, s>>>(n, h->z, h->p, h->scal, 1, done);
   // iterations in chunks; the chunk length follows the observed convergence
   int32_t queued = 0, chunk = 4;
   double rr_prev = -1.0;
@@ -776,10 +922,10 @@ amg_status pcg(amg_hierarchy *h, const double *b, double *x_user, double rtol, i
     AMG_HIP(hipGetLastError());
     queued += c;
   }
-  k_true_residual<<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, b, h->x,
-                                            h->partials);
+  k_residual_norms<1><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, h->b,
+                                               h->x, nullptr, h->partials);
   finalize(h, kFinTrue, g.grid, nullptr);
-  AMG_HIP(hipMemcpyAsync(x_user, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  k_permute_out<<<grid1(n), kBlock, 0, s>>>(n, L0.perm, h->x, x_user);
   AMG_HIP(hipMemcpyAsync(h->scal_host, h->scal, sizeof(PcgScal), hipMemcpyDeviceToHost, s));
   AMG_HIP(hipStreamSynchronize(s));
   const PcgScal sc = *h->scal_host;
@@ -798,84 +944,79 @@ amg_status pcg(amg_hierarchy *h, const double *b, double *x_user, double rtol, i
 
 amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
                        double *ms, double *bytes) {
-  if (level < 0 || level >= (int32_t)h->lv.size() - 1 || reps < 1) return AMG_ERR_ARG;
+  const int32_t L = (int32_t)h->lv.size() - 1;
+  if (level < 0 || level >= L || reps < 1 || kernel < 0 || kernel > 4) return AMG_ERR_ARG;
+  if (kernel == 4 && level != 0) return AMG_ERR_ARG;
+  if ((kernel == 2 || kernel == 3) && level + 1 >= L) return AMG_ERR_ARG;
   hipStream_t s = h->stream;
-  Level &L = h->lv[level];
+  Level &F = h->lv[level];
+  Level &C = h->lv[level + 1];
   const bool fp32 = h->params.precision == AMG_FP32;
   const double V = fp32 ? 4.0 : 8.0;
-  const double n = L.n, nnz = (double)L.nnz, nc = h->lv[level + 1].n;
+  const double n = F.n, nnz = (double)F.nnz, nc = C.n, nnzc = (double)C.nnz;
   const double Vr = level == 0 ? 8.0 : V;  // level 0 reads/writes the FP64 CG vectors
   const int32_t *done = h->zero_flag;
-  if (kernel == 4 && level != 0) return AMG_ERR_ARG;
-  hipEvent_t e0, e1;
-  AMG_HIP(hipEventCreate(&e0));
-  AMG_HIP(hipEventCreate(&e1));
+  const int32_t G = coarse_per_block(h);
   auto launch = [&]() {
-    const Geom g = geom(L.n, false);
+    const Geom g = geom(F.n);
     switch (kernel) {
-      case 0:
+      case 0:  // pre-smoothing + residual + restriction on `level`
         if (fp32) {
           if (level == 0)
-            k_pre_residual<float, double><<<g.grid, kBlock, 0, s>>>(
-                L.n, g.chunk, L.S.sptr, L.S.col, L.S.v32, L.minv32, h->r, (float *)L.z,
-                (float *)L.t, done);
+            k_pre_restrict<float, double, false><<<ceil_div(C.n, G), kBlock, 0, s>>>(
+                C.n, G, F.seg, F.S.sptr, F.S.col, F.S.s32, F.sminv32, F.pp32, h->r, (float *)F.z,
+                (float *)C.r, done);
           else
-            k_pre_residual<float, float><<<g.grid, kBlock, 0, s>>>(
-                L.n, g.chunk, L.S.sptr, L.S.col, L.S.v32, L.minv32, (const float *)L.r,
-                (float *)L.z, (float *)L.t, done);
+            k_pre_restrict<float, float, false><<<ceil_div(C.n, G), kBlock, 0, s>>>(
+                C.n, G, F.seg, F.S.sptr, F.S.col, F.S.s32, F.sminv32, F.pp32, (const float *)F.r,
+                (float *)F.z, (float *)C.r, done);
         } else {
-          k_pre_residual<double, double><<<g.grid, kBlock, 0, s>>>(
-              L.n, g.chunk, L.S.sptr, L.S.col, L.S.v64, L.minv64,
-              level == 0 ? h->r : (const double *)L.r, (double *)L.z, (double *)L.t, done);
+          k_pre_restrict<double, double, false><<<ceil_div(C.n, G), kBlock, 0, s>>>(
+              C.n, G, F.seg, F.S.sptr, F.S.col, F.S.s64, F.sminv64, F.pp64,
+              level == 0 ? h->r : (const double *)F.r, (double *)F.z, (double *)C.r, done);
         }
         break;
-      case 1:
+      case 1:  // post-smoothing on `level` (level 0: with the CG dot product)
         if (fp32) {
           if (level == 0)
             k_post<float, double, double, true><<<g.grid, kBlock, 0, s>>>(
-                L.n, g.chunk, L.S.sptr, L.S.col, L.S.v32, L.minv32, h->r, (const float *)L.z,
+                F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, F.sminv32, h->r, (const float *)F.z,
                 h->z, h->partials, done);
           else
             k_post<float, float, float, false><<<g.grid, kBlock, 0, s>>>(
-                L.n, g.chunk, L.S.sptr, L.S.col, L.S.v32, L.minv32, (const float *)L.r,
-                (const float *)L.z, (float *)L.y, nullptr, done);
+                F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, F.sminv32, (const float *)F.r,
+                (const float *)F.z, (float *)F.y, nullptr, done);
         } else {
           if (level == 0)
             k_post<double, double, double, true><<<g.grid, kBlock, 0, s>>>(
-                L.n, g.chunk, L.S.sptr, L.S.col, L.S.v64, L.minv64, h->r, (const double *)L.z,
+                F.n, g.chunk, F.S.sptr, F.S.col, F.S.v64, F.sminv64, h->r, (const double *)F.z,
                 h->z, h->partials, done);
           else
             k_post<double, double, double, false><<<g.grid, kBlock, 0, s>>>(
-                L.n, g.chunk, L.S.sptr, L.S.col, L.S.v64, L.minv64, (const double *)L.r,
-                (const double *)L.z, (double *)L.y, nullptr, done);
+                F.n, g.chunk, F.S.sptr, F.S.col, F.S.v64, F.sminv64, (const double *)F.r,
+                (const double *)F.z, (double *)F.y, nullptr, done);
         }
         break;
-      case 2:
-        if (fp32)
-          k_restrict<float><<<grid1(nc), kBlock, 0, s>>>((int32_t)nc, L.mptr, L.mem, L.pm32,
-                                                         (const float *)L.t,
-                                                         (float *)h->lv[level + 1].r, done);
-        else
-          k_restrict<double><<<grid1(nc), kBlock, 0, s>>>((int32_t)nc, L.mptr, L.mem, L.pm64,
-                                                          (const double *)L.t,
-                                                          (double *)h->lv[level + 1].r, done);
-        break;
+      case 2:  // post-smoothing on level + 1 fused with prolongation into level
       case 3:
         if (fp32)
-          k_prolong<float><<<grid1(L.n), kBlock, 0, s>>>(L.n, L.agg, L.p32,
-                                                         (const float *)h->lv[level + 1].y,
-                                                         (float *)L.z, done);
+          k_post_prolong<float><<<grid1(C.n), kBlock, 0, s>>>(
+              C.n, C.S.sptr, C.S.col, C.S.v32, C.sminv32, (const float *)C.r,
+              (const float *)C.z, F.seg, F.aggp, F.pp32, (float *)F.t, done);
         else
-          k_prolong<double><<<grid1(L.n), kBlock, 0, s>>>(L.n, L.agg, L.p64,
-                                                          (const double *)h->lv[level + 1].y,
-                                                          (double *)L.z, done);
+          k_post_prolong<double><<<grid1(C.n), kBlock, 0, s>>>(
+              C.n, C.S.sptr, C.S.col, C.S.v64, C.sminv64, (const double *)C.r,
+              (const double *)C.z, F.seg, F.aggp, F.pp64, (double *)F.t, done);
         break;
       default:
-        k_spmv_dot<<<g.grid, kBlock, 0, s>>>(L.n, g.chunk, L.S.sptr, L.S.col, L.S.v64, h->p,
+        k_spmv_dot<<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col, F.S.v64, h->p,
                                              h->q, h->partials, done);
         break;
     }
   };
+  hipEvent_t e0, e1;
+  AMG_HIP(hipEventCreate(&e0));
+  AMG_HIP(hipEventCreate(&e1));
   launch();  // warm
   AMG_HIP(hipEventRecord(e0, s));
   for (int32_t k = 0; k < reps; ++k) launch();
@@ -886,14 +1027,22 @@ amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *ms = (double)t / reps;
-  // algorithmic bytes: CSR values + int32 columns + int32 row offsets, each
-  // vector once
+  // algorithmic bytes: CSR values + int32 columns + int32 row offsets once per
+  // SpMV, every vector entry once
   switch (kernel) {
-    case 0: *bytes = nnz * (V + 4) + 4 * (n + 1) + n * (Vr + V + V + V); break;
-    case 1: *bytes = nnz * (V + 4) + 4 * (n + 1) + n * (Vr + V + V + Vr); break;
-    case 2: *bytes = n * (4 + V + V) + 4 * (nc + 1) + nc * V; break;
-    case 3: *bytes = n * (4 + V + V + V) + nc * V; break;
-    default: *bytes = nnz * 12 + 4 * (n + 1) + n * 16; break;
+    case 0:  // A M^-1, r, minv, p read; z, r_c written; segment offsets
+      *bytes = nnz * (V + 4) + 4 * (n + 1) + n * (Vr + 3 * V) + nc * (V + 4);
+      break;
+    case 1:  // A, r, z, minv read; y written
+      *bytes = nnz * (V + 4) + 4 * (n + 1) + n * (Vr + V + V + Vr);
+      break;
+    case 2:
+    case 3:  // coarse A, r_c, z_c, minv_c; fine z read + written, p, positions
+      *bytes = nnzc * (V + 4) + 4 * (nc + 1) + nc * (3 * V + 4) + n * (3 * V + 4);
+      break;
+    default:  // A, p read; q written
+      *bytes = nnz * 12 + 4 * (n + 1) + n * 16;
+      break;
   }
   return AMG_OK;
 }
