@@ -100,6 +100,77 @@ def load_traffic(kernel_key):
     return float(k["bytes_per_launch"])
 
 
+CALIB_BYTES = 512 << 20  # plain device copy used to scale the HBM counters
+TRAFFIC_KERNELS = {  # (kernel-name fragment, level-0 grid in threads) -> key
+    "fp64_level0_0": "k_pre_restrict<double, double, false>",
+    "fp64_level0_1": "k_post<double, double, double, true>",
+    "fp64_level0_4": "k_spmv_dot",
+}
+
+
+def profile_pass(N=160):
+    """Short run for counter collection: one FP64 setup, two solves, and a
+    plain device copy of CALIB_BYTES (read and written once)."""
+    import torch
+
+    from paper_2006_16147_amd import amg, inputs
+
+    dev = torch.device("cuda:0")
+    case = inputs.headline_case(N, seed=1)
+    A = case["A"]
+    h = amg.amg_setup(torch.from_numpy(A.row_ptr).to(dev), torch.from_numpy(A.col).to(dev),
+                      torch.from_numpy(A.val).to(dev))
+    b = torch.from_numpy(case["b"]).to(dev)
+    for _ in range(2):
+        x = torch.zeros_like(b)
+        amg.amg_pcg_solve(h, b, x, rtol=case["rtol"], maxit=1000)
+    src = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    h.close()
+    print(json.dumps({"profile_pass": "done", "n": A.n}), flush=True)
+
+
+def _counter_rows(path):
+    import csv
+
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def ingest_pmc(fetch_csv, write_csv, n=160 ** 3):
+    """Writes profiles/traffic.json from rocprofv3 FETCH_SIZE and WRITE_SIZE
+    counter CSVs of the profile pass: per-dispatch KiB averaged per kernel,
+    scaled by the same counter's reading for the calibration copy."""
+    out = {"source_hash": source_hash(), "calibration_bytes": CALIB_BYTES, "kernels": {}}
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = [r for r in _counter_rows(path) if r.get("Counter_Name") == counter]
+        # the calibration copy is the largest device copy of the pass
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        if not copies:
+            raise SystemExit("no calibration copy dispatch found for %s" % counter)
+        kib_copy = max(copies)
+        scale = kib_copy * 1024.0 / CALIB_BYTES  # counter bytes per real byte moved
+        out["%s_scale" % counter] = scale
+        for key, frag in TRAFFIC_KERNELS.items():
+            vals = [float(r["Counter_Value"]) * 1024.0 / scale for r in rows
+                    if frag in r["Kernel_Name"] and int(r.get("Grid_Size", 0)) == n]
+            if vals:
+                per.setdefault(key, {})[counter] = sum(vals) / len(vals)
+                per[key]["dispatches"] = len(vals)
+    for key, d in per.items():
+        if "FETCH_SIZE" in d and "WRITE_SIZE" in d:
+            out["kernels"][key] = {"fetch_bytes": d["FETCH_SIZE"], "write_bytes": d["WRITE_SIZE"],
+                                   "bytes_per_launch": d["FETCH_SIZE"] + d["WRITE_SIZE"],
+                                   "dispatches": d["dispatches"]}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def cpu_baseline(case, gpu_iters):
     import oracle
 
@@ -131,7 +202,17 @@ def main():
     ap.add_argument("--N", type=int, default=160)
     ap.add_argument("--vcycles", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="short run for rocprofv3 counter collection")
+    ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two counter runs")
     args = ap.parse_args()
+    if args.ingest_pmc:
+        ingest_pmc(*args.ingest_pmc, n=args.N ** 3)
+        return
+    if args.profile_pass:
+        profile_pass(args.N)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)

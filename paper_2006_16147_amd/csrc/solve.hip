@@ -392,23 +392,23 @@ __global__ void __launch_bounds__(kBlock) k_post_prolong(
   for (int32_t k = f0 + threadIdx.x; k < f1; k += kBlock) zf[k] += pp[k] * sh[aggp[k] - J0];
 }
 
-// Coarsest level with prolongation: z_L = A_L^-1 r_L (one wavefront per row,
-// rows kept in LDS), then z_f += P z_L over all fine positions. One block.
+// Coarsest level with prolongation: z_L = A_L^-1 r_L, then z_f += P z_L over
+// all fine positions; one block. A_L^-1 is symmetric, so thread i reads
+// column i (coalesced across threads) against r_L staged in LDS.
 template <typename TV>
 __global__ void __launch_bounds__(1024) k_coarse_prolong(
     int32_t nL, const double *__restrict__ Ainv, const TV *__restrict__ rL, int32_t nf,
     const int32_t *__restrict__ aggp, const TV *__restrict__ pp, TV *__restrict__ zf,
     const int32_t *__restrict__ done) {
-  extern __shared__ double zs[];
+  extern __shared__ double sm[];
   if (*done) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int nw = blockDim.x / kWave;
-  for (int32_t i = threadIdx.x / kWave; i < nL; i += nw) {
-    const double *row = Ainv + (int64_t)i * nL;
+  double *rs = sm, *zs = sm + nL;
+  for (int32_t k = threadIdx.x; k < nL; k += blockDim.x) rs[k] = (double)rL[k];
+  __syncthreads();
+  for (int32_t i = threadIdx.x; i < nL; i += blockDim.x) {
     double s = 0.0;
-    for (int32_t k = lane; k < nL; k += kWave) s += row[k] * (double)rL[k];
-    for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_down(s, o, kWave);
-    if (lane == 0) zs[i] = s;
+    for (int32_t k = 0; k < nL; ++k) s += Ainv[(int64_t)k * nL + i] * rs[k];
+    zs[i] = s;
   }
   __syncthreads();
   for (int32_t k = threadIdx.x; k < nf; k += blockDim.x) zf[k] += pp[k] * (TV)zs[aggp[k]];
@@ -678,7 +678,7 @@ void vcycle_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const in
   {
     Level &F = h->lv[L - 1];
     const int32_t nL = h->C.n;
-    k_coarse_prolong<TV><<<1, 1024, sizeof(double) * nL, s>>>(
+    k_coarse_prolong<TV><<<1, 1024, 2 * sizeof(double) * nL, s>>>(
         nL, h->C.Ainv, (const TV *)h->lv[L].r, F.n, F.aggp, ppv<TV>(F), zb[L - 1], done);
   }
   for (int32_t c = L - 1; c >= 1; --c) launch_up<TV>(h, c, zb[c], zb[c - 1], done);

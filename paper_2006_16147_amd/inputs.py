@@ -361,3 +361,66 @@ def constant_diffusion7_arrays(N: int, kx: float, ky: float, kz: float, xp, devi
         return row_ptr.contiguous(), col.to(torch.int32).contiguous(), val.contiguous()
     row_ptr = np.concatenate([zero, cumsum(counts)]).astype(np.int32)
     return row_ptr, col.astype(np.int32), val
+
+
+def diffusion7_torch(N: int, kx, ky, kz, device):
+    """diffusion7 built with torch on ``device`` (same operations, same bits).
+
+    ``kx, ky, kz`` are scalars or (N^3,) float64 tensors/arrays. Returns
+    (row_ptr int32, col int32, val float64) tensors in this module's CSR
+    conventions.
+    """
+    import torch
+
+    n = N * N * N
+
+    def coef(v):
+        t = torch.as_tensor(v, dtype=torch.float64, device=device)
+        return t.expand(n).clone() if t.dim() == 0 else t.clone()
+
+    k = {"x": coef(kx), "y": coef(ky), "z": coef(kz)}
+    idx = torch.arange(n, dtype=torch.int64, device=device)
+    coord = {"x": idx % N, "y": (idx // N) % N, "z": idx // (N * N)}
+    stride = {"x": 1, "y": N, "z": N * N}
+    face = {}
+    for ax in ("x", "y", "z"):
+        kk = k[ax]
+        c = coord[ax]
+        plus = kk.clone()
+        inner = c < N - 1
+        ki = kk[inner]
+        kj = kk[idx[inner] + stride[ax]]
+        plus[inner] = (2.0 * ki * kj) / (ki + kj)
+        minus = kk.clone()
+        has_minus = c > 0
+        minus[has_minus] = plus[idx[has_minus] - stride[ax]]
+        face[ax] = (minus, plus)
+    diag = (face["x"][0] + face["x"][1] + face["y"][0] + face["y"][1] + face["z"][0]
+            + face["z"][1])
+    cols, vals, masks = [], [], []
+    for ax, sg in zip(_AXES, _SIGNS):
+        if ax is None:
+            cols.append(idx)
+            vals.append(diag)
+            masks.append(torch.ones(n, dtype=torch.bool, device=device))
+            continue
+        c = coord[ax]
+        masks.append((c > 0) if sg < 0 else (c < N - 1))
+        cols.append(idx + sg * stride[ax])
+        vals.append(-(face[ax][0] if sg < 0 else face[ax][1]))
+    M = torch.stack(masks, dim=1)
+    col = torch.stack(cols, dim=1)[M].to(torch.int32).contiguous()
+    val = torch.stack(vals, dim=1)[M].contiguous()
+    counts = M.sum(1)
+    row_ptr = torch.cat([torch.zeros(1, dtype=torch.int64, device=device),
+                         torch.cumsum(counts, 0)]).to(torch.int32).contiguous()
+    return row_ptr, col, val
+
+
+def aniso_blocks_coefficients(N: int = 256, block: int = 16, seed: int = 2):
+    """(eps_x, eps_y) per node and the right-hand side of aniso_blocks_case,
+    drawn in the same order from the same generator (no operator assembly)."""
+    rng = np.random.default_rng(seed)
+    ex, ey = block_log_uniform_eps(N, block, rng)
+    b = rng.uniform(-1.0, 1.0, N ** 3)
+    return ex, ey, b
