@@ -171,6 +171,106 @@ def ingest_pmc(fetch_csv, write_csv, n=160 ** 3):
     print(json.dumps(out))
 
 
+def bench_aniso(args):
+    """256^3 block-anisotropic diffusion: FP64 vs FP32 hierarchy (outer CG FP64)."""
+    import torch
+
+    from paper_2006_16147_amd import amg, inputs
+
+    dev = torch.device("cuda:0")
+    N = args.N if args.N != 160 else 256
+    ex, ey, bh = inputs.aniso_blocks_coefficients(N, 16, seed=2)
+    rp, ci, va = inputs.diffusion7_torch(N, torch.from_numpy(ex).to(dev),
+                                         torch.from_numpy(ey).to(dev), 1.0, dev)
+    b = torch.from_numpy(bh).to(dev)
+    out = {"mode": "aniso", "workload": "aniso7_%d^3_blocks16_seed2_rtol1e-8" % N,
+           "n": int(rp.numel() - 1), "nnz": int(ci.numel())}
+    xs = {}
+    for prec, name in ((amg.FP64, "fp64"), (amg.FP32, "fp32_prec")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = amg.amg_setup(rp, ci, va, precision=prec)
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        x = torch.zeros_like(b)
+        times = []
+        for k in range(args.warmup + args.steps):
+            x.zero_()
+            t0 = time.perf_counter()
+            st, info = amg.amg_pcg_solve(h, b, x, rtol=1e-8, maxit=1000)
+            if k >= args.warmup:
+                times.append((time.perf_counter() - t0) * 1e3)
+        xs[name] = x.cpu().numpy()
+        out[name] = {"setup_ms": round(setup_ms, 1), "levels": h.sizes(), "opc": round(h.opc(), 4),
+                     "p50_ms": round(percentile(times, 50), 3),
+                     "p99_ms": round(percentile(times, 99), 3),
+                     "iterations": info["iterations"], "rel_res_true": info["rel_res_true"]}
+        h.close()
+    out["fp32_vs_fp64_rel_diff"] = float(np.linalg.norm(xs["fp32_prec"] - xs["fp64"])
+                                         / np.linalg.norm(xs["fp64"]))
+    out["fp32_prec_speedup_p50"] = round(out["fp64"]["p50_ms"] / out["fp32_prec"]["p50_ms"], 3)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """128^3 Poisson with k = 32 right-hand sides: one batched solve (block
+    V-cycle, FP32 hierarchy, per-column FP64 CG) vs k single solves."""
+    import torch
+
+    from paper_2006_16147_amd import amg, inputs
+
+    dev = torch.device("cuda:0")
+    N = args.N if args.N != 160 else 128
+    k = 32
+    A = inputs.laplacian7(N)
+    B = np.random.default_rng(3).uniform(-1.0, 1.0, (A.n, k))
+    Bd = torch.from_numpy(B).to(dev)
+    h = amg.amg_setup(torch.from_numpy(A.row_ptr).to(dev), torch.from_numpy(A.col).to(dev),
+                      torch.from_numpy(A.val).to(dev), precision=amg.FP32)
+    X = torch.zeros_like(Bd)
+    for _ in range(max(1, args.warmup)):
+        X.zero_()
+        amg.amg_pcg_solve_batch(h, Bd, X, rtol=1e-8, maxit=1000)
+    times = []
+    for _ in range(args.steps):
+        X.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, infos = amg.amg_pcg_solve_batch(h, Bd, X, rtol=1e-8, maxit=1000)
+        times.append((time.perf_counter() - t0) * 1e3)
+    its = [i["iterations"] for i in infos]
+    # the same 32 right-hand sides one at a time
+    single = 0.0
+    x = torch.zeros(A.n, dtype=torch.float64, device=dev)
+    cols = [Bd[:, j].contiguous() for j in range(k)]
+    amg.amg_pcg_solve(h, cols[0], x, rtol=1e-8, maxit=1000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(k):
+        x.zero_()
+        amg.amg_pcg_solve(h, cols[j], x, rtol=1e-8, maxit=1000)
+    torch.cuda.synchronize()
+    single = (time.perf_counter() - t0) * 1e3
+    out = {"mode": "batch", "workload": "poisson7_%d^3_k%d_seed3_rtol1e-8_fp32prec" % (N, k),
+           "n": A.n, "k": k, "status": st, "tile": h.batch_tile(),
+           "batch_p50_ms": round(percentile(times, 50), 3),
+           "batch_p99_ms": round(percentile(times, 99), 3),
+           "ms_per_rhs": round(percentile(times, 50) / k, 3),
+           "single_solves_ms": round(single, 3), "ms_per_rhs_single": round(single / k, 3),
+           "batch_speedup": round(single / percentile(times, 50), 3),
+           "iterations_min_max": [min(its), max(its)],
+           "max_rel_res_true": max(i["rel_res_true"] for i in infos)}
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    from paper_2006_16147_amd import serve
+
+    serve.main(["--rates", args.rates, "--count", str(args.count), "--warmup",
+                str(max(0, args.count // 10)), "--slots", str(args.slots)])
+
+
 def cpu_baseline(case, gpu_iters):
     import oracle
 
@@ -202,6 +302,12 @@ def main():
     ap.add_argument("--N", type=int, default=160)
     ap.add_argument("--vcycles", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="headline", choices=["headline", "aniso", "batch", "serve"],
+                    help="headline (default): the 160^3 benchmark line; the others print "
+                         "their own JSON lines")
+    ap.add_argument("--rates", default="10,50,200,500", help="serve mode: arrival rates /s")
+    ap.add_argument("--count", type=int, default=200, help="serve mode: requests per rate")
+    ap.add_argument("--slots", type=int, default=4, help="serve mode: concurrent slots")
     ap.add_argument("--profile-pass", action="store_true",
                     help="short run for rocprofv3 counter collection")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -212,6 +318,12 @@ def main():
         return
     if args.profile_pass:
         profile_pass(args.N)
+        return
+    if args.mode != "headline":
+        import torch
+
+        torch.cuda.set_device(0)
+        {"aniso": bench_aniso, "batch": bench_batch, "serve": bench_serve}[args.mode](args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

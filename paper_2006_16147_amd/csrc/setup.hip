@@ -279,6 +279,55 @@ __global__ void k_match_accept(int32_t n, int32_t *mate, const int32_t *cand) {
   if (u >= 0 && cand[u] == v) mate[v] = u;
 }
 
+// x is no longer free after this round: matched or a singleton before it
+// (mate), or matched in it (mutual proposals in `cur`, which nobody writes in
+// this round). A stale read of mate[x] can only show a vertex that becomes a
+// singleton in this round as free; a proposal to it is then repeated next
+// round, while no free vertex is ever taken for matched.
+__device__ __forceinline__ bool taken(int32_t x, const int32_t *mate, const int32_t *cur) {
+  if (mate[x] != kFree) return true;
+  const int32_t c = cur[x];
+  return c >= 0 && cur[c] == x;
+}
+
+// One round: accept the mutual proposals of `cur` and, for vertices that stay
+// free, write their next proposal into `nxt` (kept while its target stays
+// free, else the best free neighbour under the strict key; none: singleton).
+__global__ void k_match_round(int32_t n, const int32_t *rp, const int32_t *ci, const double *c,
+                              int32_t *mate, const int32_t *cur, int32_t *nxt,
+                              int32_t *active) {
+  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  bool live = false;
+  if (v < n && mate[v] == kFree) {
+    const int32_t u = cur[v];
+    if (u >= 0 && cur[u] == v) {
+      mate[v] = u;
+      nxt[v] = u;
+    } else if (u >= 0 && !taken(u, mate, cur)) {
+      nxt[v] = u;
+      live = true;
+    } else {
+      int32_t best = -1, blo = 0, bhi = 0;
+      double bc = 0.0;
+      for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
+        const int32_t j = ci[k];
+        if (j == v || taken(j, mate, cur)) continue;
+        const int32_t lo = min(v, j), hi = max(v, j);
+        const double cc = c[k];
+        if (best < 0 || better(cc, lo, hi, bc, blo, bhi)) {
+          best = j;
+          bc = cc;
+          blo = lo;
+          bhi = hi;
+        }
+      }
+      nxt[v] = best;
+      if (best < 0) mate[v] = kDead; else live = true;
+    }
+  }
+  if (__syncthreads_or(live) && threadIdx.x == 0) *active = 1;
+}
+
 // ---------------------------------------------------------------------------
 // 3. numbering, 4. eq. (prolongator), restriction of w
 // ---------------------------------------------------------------------------
@@ -699,12 +748,13 @@ amg_status pairwise_sweep(amg_hierarchy *h, Tmp &tmp, const Mat &A, SweepOut &o,
   hipStream_t s = h->stream;
   const int32_t n = A.n;
   double t0 = now_ms();
-  int32_t *dpos, *mate, *cand, *counters;
+  int32_t *dpos, *mate, *cand, *cand2, *counters;
   double *c;
   AMG_TRY(tmp.get(&dpos, n));
   AMG_TRY(tmp.get(&c, A.nnz));
   AMG_TRY(tmp.get(&mate, n));
   AMG_TRY(tmp.get(&cand, n));
+  AMG_TRY(tmp.get(&cand2, n));
   constexpr int kMaxBatch = 64;
   AMG_TRY(tmp.get(&counters, kMaxBatch));
   k_diag_pos<<<grid(n), kBlock, 0, s>>>(n, A.rp, A.ci, dpos);
@@ -713,13 +763,18 @@ amg_status pairwise_sweep(amg_hierarchy *h, Tmp &tmp, const Mat &A, SweepOut &o,
   k_fill<int32_t><<<grid(n), kBlock, 0, s>>>(cand, -1, n);
   // matching rounds in batches; the host reads the per-round counters after
   // each batch (rounds past the last live one do nothing)
+  // first proposals, then one fused accept-and-propose kernel per round with
+  // the proposals double-buffered; the last round's accept is applied after
   int32_t rounds = 0, batch = 4;
   int32_t hc[kMaxBatch];
+  int32_t *cur = cand, *nxt = cand2;
+  k_fill<int32_t><<<1, kMaxBatch, 0, s>>>(counters, 0, kMaxBatch);
+  k_match_propose<<<grid(n), kBlock, 0, s>>>(n, A.rp, A.ci, c, mate, cur, counters);
   for (;;) {
     k_fill<int32_t><<<1, kMaxBatch, 0, s>>>(counters, 0, kMaxBatch);
     for (int32_t r = 0; r < batch; ++r) {
-      k_match_propose<<<grid(n), kBlock, 0, s>>>(n, A.rp, A.ci, c, mate, cand, counters + r);
-      k_match_accept<<<grid(n), kBlock, 0, s>>>(n, mate, cand);
+      k_match_round<<<grid(n), kBlock, 0, s>>>(n, A.rp, A.ci, c, mate, cur, nxt, counters + r);
+      std::swap(cur, nxt);
     }
     AMG_HIP(hipMemcpyAsync(hc, counters, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, s));
     AMG_HIP(hipStreamSynchronize(s));
@@ -730,8 +785,11 @@ amg_status pairwise_sweep(amg_hierarchy *h, Tmp &tmp, const Mat &A, SweepOut &o,
     if (rounds > n + 2) return AMG_ERR_HIP;  // cannot happen: one edge per round at least
     batch = batch * 2 > kMaxBatch ? kMaxBatch : batch * 2;
   }
+  // the proposals of the last live round may still hold mutual pairs
+  k_match_accept<<<grid(n), kBlock, 0, s>>>(n, mate, cur);
   o.rounds = rounds;
   o.mate = mate;
+  tmp.drop(cand2);
   tmp.drop(cand);
   tmp.drop(c);
   double t1 = now_ms();

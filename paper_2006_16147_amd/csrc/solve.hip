@@ -393,8 +393,10 @@ __global__ void __launch_bounds__(kBlock) k_post_prolong(
 }
 
 // Coarsest level with prolongation: z_L = A_L^-1 r_L, then z_f += P z_L over
-// all fine positions; one block. A_L^-1 is symmetric, so thread i reads
-// column i (coalesced across threads) against r_L staged in LDS.
+// all fine positions; one block of 1024 threads. Eight consecutive threads
+// share a row (coalesced 64-byte pieces of it), each summing every eighth
+// entry against r_L staged in LDS, so 128 rows are in flight per pass.
+constexpr int kCoarseSplit = 8;
 template <typename TV>
 __global__ void __launch_bounds__(1024) k_coarse_prolong(
     int32_t nL, const double *__restrict__ Ainv, const TV *__restrict__ rL, int32_t nf,
@@ -405,13 +407,86 @@ __global__ void __launch_bounds__(1024) k_coarse_prolong(
   double *rs = sm, *zs = sm + nL;
   for (int32_t k = threadIdx.x; k < nL; k += blockDim.x) rs[k] = (double)rL[k];
   __syncthreads();
-  for (int32_t i = threadIdx.x; i < nL; i += blockDim.x) {
+  const int32_t part = threadIdx.x % kCoarseSplit;
+  const int32_t rows_per_pass = blockDim.x / kCoarseSplit;
+  for (int32_t i0 = 0; i0 < nL; i0 += rows_per_pass) {
+    const int32_t i = i0 + (int32_t)threadIdx.x / kCoarseSplit;
     double s = 0.0;
-    for (int32_t k = 0; k < nL; ++k) s += Ainv[(int64_t)k * nL + i] * rs[k];
-    zs[i] = s;
+    if (i < nL) {
+      const double *row = Ainv + (int64_t)i * nL;
+#pragma unroll 8
+      for (int32_t k = part; k < nL; k += kCoarseSplit) s += row[k] * rs[k];
+    }
+    for (int o = kCoarseSplit / 2; o > 0; o >>= 1) s += __shfl_down(s, o, kCoarseSplit);
+    if (i < nL && part == 0) zs[i] = s;
   }
   __syncthreads();
   for (int32_t k = threadIdx.x; k < nf; k += blockDim.x) zf[k] += pp[k] * (TV)zs[aggp[k]];
+}
+
+// Tail of the V-cycle in one block, for a level t = L - 1 small enough for
+// LDS (t >= 1, one pre- and one post-sweep): starting from r_t it does the
+// down step on t, the coarsest solve, the up step on t, and the
+// prolongation into level t - 1 (zf += P_{t-1} y_t), with level t's vectors
+// in LDS. Replaces the three latency-bound kernels of the last two levels.
+constexpr int kTailMax = 2048;  // largest level t handled in LDS
+constexpr int kTailCoarseMax = 512;
+template <typename TV>
+__global__ void __launch_bounds__(1024) k_tail(
+    int32_t nt, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
+    const TV *__restrict__ sval, const TV *__restrict__ val, const TV *__restrict__ minv,
+    const TV *__restrict__ rt, const int32_t *__restrict__ seg, const int32_t *__restrict__ aggp,
+    const TV *__restrict__ pp, int32_t nL, const double *__restrict__ Ainv, int32_t nf,
+    const int32_t *__restrict__ aggp_f, const TV *__restrict__ pp_f, TV *__restrict__ zf,
+    const int32_t *__restrict__ done) {
+  __shared__ TV rs[kTailMax], zs[kTailMax], ys[kTailMax];
+  __shared__ double rl[kTailCoarseMax], zl[kTailCoarseMax];
+  if (*done) return;
+  const int32_t tid = threadIdx.x, nth = blockDim.x;
+  for (int32_t k = tid; k < nt; k += nth) {
+    const TV r = rt[k];
+    rs[k] = r;
+    zs[k] = r * minv[k];
+  }
+  __syncthreads();
+  // t = p (r - A M^-1 r), kept in ys
+  for (int32_t k = tid; k < nt; k += nth) {
+    const int32_t s = k / kSlice, base = sptr[s] + k % kSlice, w = (sptr[s + 1] - sptr[s]) / kSlice;
+    TV acc = 0;
+    for (int32_t e = 0; e < w; ++e) acc += sval[base + e * kSlice] * rs[col[base + e * kSlice]];
+    ys[k] = pp[k] * (rs[k] - acc);
+  }
+  __syncthreads();
+  for (int32_t J = tid; J < nL; J += nth) {
+    TV a = 0;
+    for (int32_t m = seg[J]; m < seg[J + 1]; ++m) a += ys[m];
+    rl[J] = (double)a;
+  }
+  __syncthreads();
+  // coarsest: eight threads per row of A_L^-1
+  const int32_t part = tid % kCoarseSplit;
+  for (int32_t i0 = 0; i0 < nL; i0 += nth / kCoarseSplit) {
+    const int32_t i = i0 + tid / kCoarseSplit;
+    double a = 0.0;
+    if (i < nL) {
+      const double *row = Ainv + (int64_t)i * nL;
+      for (int32_t k = part; k < nL; k += kCoarseSplit) a += row[k] * rl[k];
+    }
+    for (int o = kCoarseSplit / 2; o > 0; o >>= 1) a += __shfl_down(a, o, kCoarseSplit);
+    if (i < nL && part == 0) zl[i] = a;
+  }
+  __syncthreads();
+  for (int32_t k = tid; k < nt; k += nth) zs[k] += pp[k] * (TV)zl[aggp[k]];
+  __syncthreads();
+  // post-smoothing on level t
+  for (int32_t k = tid; k < nt; k += nth) {
+    const int32_t s = k / kSlice, base = sptr[s] + k % kSlice, w = (sptr[s + 1] - sptr[s]) / kSlice;
+    TV acc = 0;
+    for (int32_t e = 0; e < w; ++e) acc += val[base + e * kSlice] * zs[col[base + e * kSlice]];
+    ys[k] = zs[k] + (rs[k] - acc) * minv[k];
+  }
+  __syncthreads();
+  for (int32_t k = tid; k < nf; k += nth) zf[k] += pp_f[k] * ys[aggp_f[k]];
 }
 
 // Single-level hierarchy: z = A_0^-1 r, one wavefront per row.
@@ -672,16 +747,26 @@ void vcycle_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const in
     return;
   }
   std::vector<TV *> zb(L);
+  const bool tail = L >= 2 && h->params.pre == 1 && h->params.post == 1 &&
+                    h->lv[L - 1].n <= kTailMax && h->C.n <= kTailCoarseMax;
+  const int32_t down_end = tail ? L - 1 : L;  // levels [0, down_end) take the down step
   zb[0] = launch_down<TV, double>(h, 0, r0, done);
-  for (int32_t l = 1; l < L; ++l)
+  for (int32_t l = 1; l < down_end; ++l)
     zb[l] = launch_down<TV, TV>(h, l, (const TV *)h->lv[l].r, done);
-  {
+  if (tail) {
+    Level &T = h->lv[L - 1];
+    Level &F = h->lv[L - 2];
+    k_tail<TV><<<1, 1024, 0, s>>>(T.n, T.S.sptr, T.S.col, svals<TV>(T), vals<TV>(T), minv<TV>(T),
+                                  (const TV *)T.r, T.seg, T.aggp, ppv<TV>(T), h->C.n, h->C.Ainv,
+                                  F.n, F.aggp, ppv<TV>(F), zb[L - 2], done);
+    for (int32_t c = L - 2; c >= 1; --c) launch_up<TV>(h, c, zb[c], zb[c - 1], done);
+  } else {
     Level &F = h->lv[L - 1];
     const int32_t nL = h->C.n;
     k_coarse_prolong<TV><<<1, 1024, 2 * sizeof(double) * nL, s>>>(
         nL, h->C.Ainv, (const TV *)h->lv[L].r, F.n, F.aggp, ppv<TV>(F), zb[L - 1], done);
+    for (int32_t c = L - 1; c >= 1; --c) launch_up<TV>(h, c, zb[c], zb[c - 1], done);
   }
-  for (int32_t c = L - 1; c >= 1; --c) launch_up<TV>(h, c, zb[c], zb[c - 1], done);
   // level 0: extra post sweeps, then the last with the (r, z) partials
   Level &F = h->lv[0];
   TV *z = zb[0], *tmp = (TV *)F.y;
