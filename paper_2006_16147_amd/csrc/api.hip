@@ -51,6 +51,8 @@ void destroy(amg_hierarchy *h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   if (h->iter_exec) (void)hipGraphExecDestroy(h->iter_exec);
   if (h->iter_graph) (void)hipGraphDestroy(h->iter_graph);
+  if (h->iter_exec4) (void)hipGraphExecDestroy(h->iter_exec4);
+  if (h->iter_graph4) (void)hipGraphDestroy(h->iter_graph4);
   for (void *p : h->allocs)
     if (p) (void)hipFree(p);
   if (h->batch) free_batch(h->batch);

@@ -151,8 +151,10 @@ struct amg_hierarchy {
   amg::Batch *batch = nullptr;
   size_t batch_bytes = 0;
   // graph of one CG iteration
-  hipGraphExec_t iter_exec = nullptr;
+  hipGraphExec_t iter_exec = nullptr;  // one CG iteration
   hipGraph_t iter_graph = nullptr;
+  hipGraphExec_t iter_exec4 = nullptr;  // kIterGroup CG iterations
+  hipGraph_t iter_graph4 = nullptr;
   bool graph_failed = false;
   // bookkeeping
   std::vector<void *> allocs;

@@ -76,6 +76,66 @@ __device__ __forceinline__ void sell_row(const int32_t *sptr, int32_t row, int32
   *w = (sptr[s + 1] - b0) / kSlice;
 }
 
+// sum_k val[k] * x(col[k]) over one SELL row, in entry order. The slice
+// width w is the same for the 64 rows of a wavefront, so the guards are
+// uniform; each group of up to eight entries issues all its index and value
+// loads, then all its gathers, before the first product, which keeps eight
+// gathers per lane in flight instead of one.
+constexpr int kRowBatch = 8;
+template <typename TV, typename X>
+__device__ __forceinline__ TV sell_dot(const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                       int32_t base, int32_t w, X x) {
+  TV acc = 0;
+  for (int32_t k0 = 0; k0 < w; k0 += kRowBatch) {
+    int32_t c[kRowBatch];
+    TV v[kRowBatch], g[kRowBatch];
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      c[u] = 0;
+      v[u] = 0;
+      if (k0 + u < w) {
+        const int32_t idx = base + (k0 + u) * kSlice;
+        c[u] = ld_stream(&col[idx]);
+        v[u] = ld_stream(&val[idx]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) g[u] = k0 + u < w ? x(c[u]) : TV(0);
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u)
+      if (k0 + u < w) acc += v[u] * g[u];
+  }
+  return acc;
+}
+
+// zf[k] += pp[k] * y(aggp[k]) for k = k0 + t, k0 + t + nth, ... < k1: each
+// thread issues the loads of four of its positions before their use.
+template <typename TV, typename Y>
+__device__ __forceinline__ void prolong_add(int32_t k0, int32_t k1, int32_t t, int32_t nth,
+                                            const int32_t *__restrict__ aggp,
+                                            const TV *__restrict__ pp, TV *__restrict__ zf, Y y) {
+  for (int32_t kb = k0 + t; kb < k1; kb += 4 * nth) {
+    int32_t a[4];
+    TV pv[4], zv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t k = kb + u * nth;
+      a[u] = 0;
+      pv[u] = zv[u] = 0;
+      if (k < k1) {
+        a[u] = aggp[k];
+        pv[u] = pp[k];
+        zv[u] = zf[k];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t k = kb + u * nth;
+      if (k < k1) zf[k] = zv[u] + pv[u] * y(a[u]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // deterministic two-stage reductions (no in-kernel cross-block handshake: on
 // gfx950 a device-scope fence per block writes back the XCD's L2 and costs
@@ -119,9 +179,20 @@ __global__ void __launch_bounds__(1024) k_finalize(int32_t op, int32_t nparts,
   const int nv = op == kFinInit ? 2 : 1;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   for (int q = 0; q < nv; ++q) {
+    // this thread's partials in index order, sixteen loads at a time
+    const double *src = partials + (int64_t)q * kMaxParts;
     double a = 0.0;
-    for (int32_t b = threadIdx.x; b < nparts; b += blockDim.x)
-      a += partials[(int64_t)q * kMaxParts + b];
+    for (int32_t b0 = threadIdx.x; b0 < nparts; b0 += 16 * blockDim.x) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int32_t b = b0 + u * (int32_t)blockDim.x;
+        v[u] = b < nparts ? src[b] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (b0 + u * (int32_t)blockDim.x < nparts) a += v[u];
+    }
     for (int o = kWave / 2; o > 0; o >>= 1) a += __shfl_down(a, o, kWave);
     if (lane == 0) sh[q][wid] = a;
   }
@@ -315,13 +386,8 @@ __global__ void __launch_bounds__(kBlock) k_pre_restrict(
   if (row < f1) {
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
-    TV acc = 0;
-    for (int32_t k = 0; k < w; ++k) {
-      const int32_t idx = base + k * kSlice;
-      const int32_t c = ld_stream(&col[idx]);
-      if (FROM_Z) acc += ld_stream(&val[idx]) * z[c];
-      else acc += ld_stream(&val[idx]) * (TV)r[c];
-    }
+    const TV acc = FROM_Z ? sell_dot(col, val, base, w, [&](int32_t c) { return z[c]; })
+                          : sell_dot(col, val, base, w, [&](int32_t c) { return (TV)r[c]; });
     const TV ri = (TV)r[row];
     if (!FROM_Z) z[row] = ri * minv[row];
     sh[threadIdx.x] = pp[row] * (ri - acc);
@@ -350,11 +416,7 @@ __global__ void __launch_bounds__(kBlock) k_post(
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
-    TV acc = 0;
-    for (int32_t k = 0; k < w; ++k) {
-      const int32_t idx = base + k * kSlice;
-      acc += ld_stream(&val[idx]) * z[ld_stream(&col[idx])];
-    }
+    const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return z[c]; });
     const TR rr = r[row];
     const TO yo = (TO)(z[row] + ((TV)rr - acc) * minv[row]);
     y[row] = yo;
@@ -379,17 +441,14 @@ __global__ void __launch_bounds__(kBlock) k_post_prolong(
   if (J < nc) {
     int32_t base, w;
     sell_row(sptr, J, &base, &w);
-    TV acc = 0;
-    for (int32_t k = 0; k < w; ++k) {
-      const int32_t idx = base + k * kSlice;
-      acc += ld_stream(&val[idx]) * zc[ld_stream(&col[idx])];
-    }
+    const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return zc[c]; });
     sh[threadIdx.x] = zc[J] + (rcv[J] - acc) * minv[J];
   }
   __syncthreads();
   const int32_t J1 = min(nc, J0 + kBlock);
   const int32_t f0 = seg[J0], f1 = seg[J1];
-  for (int32_t k = f0 + threadIdx.x; k < f1; k += kBlock) zf[k] += pp[k] * sh[aggp[k] - J0];
+  prolong_add(f0, f1, (int32_t)threadIdx.x, kBlock, aggp, pp, zf,
+              [&](int32_t a) { return sh[a - J0]; });
 }
 
 // Coarsest level with prolongation: z_L = A_L^-1 r_L, then z_f += P z_L over
@@ -421,7 +480,8 @@ __global__ void __launch_bounds__(1024) k_coarse_prolong(
     if (i < nL && part == 0) zs[i] = s;
   }
   __syncthreads();
-  for (int32_t k = threadIdx.x; k < nf; k += blockDim.x) zf[k] += pp[k] * (TV)zs[aggp[k]];
+  prolong_add(0, nf, (int32_t)threadIdx.x, (int32_t)blockDim.x, aggp, pp, zf,
+              [&](int32_t a) { return (TV)zs[a]; });
 }
 
 // Tail of the V-cycle in one block, for a level t = L - 1 small enough for
@@ -452,8 +512,7 @@ __global__ void __launch_bounds__(1024) k_tail(
   // t = p (r - A M^-1 r), kept in ys
   for (int32_t k = tid; k < nt; k += nth) {
     const int32_t s = k / kSlice, base = sptr[s] + k % kSlice, w = (sptr[s + 1] - sptr[s]) / kSlice;
-    TV acc = 0;
-    for (int32_t e = 0; e < w; ++e) acc += sval[base + e * kSlice] * rs[col[base + e * kSlice]];
+    const TV acc = sell_dot(col, sval, base, w, [&](int32_t c) { return rs[c]; });
     ys[k] = pp[k] * (rs[k] - acc);
   }
   __syncthreads();
@@ -470,6 +529,7 @@ __global__ void __launch_bounds__(1024) k_tail(
     double a = 0.0;
     if (i < nL) {
       const double *row = Ainv + (int64_t)i * nL;
+#pragma unroll 8
       for (int32_t k = part; k < nL; k += kCoarseSplit) a += row[k] * rl[k];
     }
     for (int o = kCoarseSplit / 2; o > 0; o >>= 1) a += __shfl_down(a, o, kCoarseSplit);
@@ -481,12 +541,11 @@ __global__ void __launch_bounds__(1024) k_tail(
   // post-smoothing on level t
   for (int32_t k = tid; k < nt; k += nth) {
     const int32_t s = k / kSlice, base = sptr[s] + k % kSlice, w = (sptr[s + 1] - sptr[s]) / kSlice;
-    TV acc = 0;
-    for (int32_t e = 0; e < w; ++e) acc += val[base + e * kSlice] * zs[col[base + e * kSlice]];
+    const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return zs[c]; });
     ys[k] = zs[k] + (rs[k] - acc) * minv[k];
   }
   __syncthreads();
-  for (int32_t k = tid; k < nf; k += nth) zf[k] += pp_f[k] * ys[aggp_f[k]];
+  prolong_add(0, nf, tid, nth, aggp_f, pp_f, zf, [&](int32_t a) { return ys[a]; });
 }
 
 // Single-level hierarchy: z = A_0^-1 r, one wavefront per row.
@@ -561,11 +620,7 @@ __global__ void __launch_bounds__(kBlock) k_residual_norms(
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
-    double acc = 0.0;
-    for (int32_t k = 0; k < w; ++k) {
-      const int32_t idx = base + k * kSlice;
-      acc += ld_stream(&val[idx]) * x[ld_stream(&col[idx])];
-    }
+    const double acc = sell_dot(col, val, base, w, [&](int32_t c) { return x[c]; });
     const double bi = b[row];
     const double ri = bi - acc;
     if (MODE == 0) {
@@ -597,11 +652,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot(
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
-    double acc = 0.0;
-    for (int32_t k = 0; k < w; ++k) {
-      const int32_t idx = base + k * kSlice;
-      acc += ld_stream(&val[idx]) * p[ld_stream(&col[idx])];
-    }
+    const double acc = sell_dot(col, val, base, w, [&](int32_t c) { return p[c]; });
     q[row] = acc;
     d[0] += p[row] * acc;
   }
@@ -933,32 +984,44 @@ void cg_iteration(amg_hierarchy *h) {
   k_xpay<<<grid1(n), kBlock, 0, s>>>(n, h->z, h->p, h->scal, 0, done);
 }
 
-// Captures one CG iteration into a hipGraph (once per hierarchy).
-amg_status ensure_iteration_graph(amg_hierarchy *h) {
-  if (h->iter_exec || h->graph_failed || (h->params.flags & AMG_FLAG_NO_GRAPH)) return AMG_OK;
+// Captures `count` CG iterations into one instantiated hipGraph.
+bool capture_iterations(amg_hierarchy *h, int32_t count, hipGraph_t *graph, hipGraphExec_t *exec) {
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipGetLastError();
-    h->graph_failed = true;
-    return AMG_OK;
+    return false;
   }
-  cg_iteration(h);
+  for (int32_t k = 0; k < count; ++k) cg_iteration(h);
   hipError_t e = hipStreamEndCapture(h->stream, &g);
   if (e != hipSuccess || !g) {
     (void)hipGetLastError();
-    h->graph_failed = true;
-    return AMG_OK;
+    return false;
   }
   hipGraphExec_t ex = nullptr;
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     (void)hipGraphDestroy(g);
+    return false;
+  }
+  *graph = g;
+  *exec = ex;
+  return true;
+}
+
+// Graphs of one and of kIterGroup CG iterations (once per hierarchy): a
+// group replay saves the launch gap between consecutive graphs.
+constexpr int32_t kIterGroup = 4;
+amg_status ensure_iteration_graph(amg_hierarchy *h) {
+  if (h->iter_exec || h->graph_failed || (h->params.flags & AMG_FLAG_NO_GRAPH)) return AMG_OK;
+  if (!capture_iterations(h, 1, &h->iter_graph, &h->iter_exec)) {
     h->graph_failed = true;
     return AMG_OK;
   }
-  h->iter_graph = g;
-  h->iter_exec = ex;
+  if (!capture_iterations(h, kIterGroup, &h->iter_graph4, &h->iter_exec4)) {
+    h->iter_graph4 = nullptr;
+    h->iter_exec4 = nullptr;
+  }
   return AMG_OK;
 }
 
@@ -1000,7 +1063,10 @@ amg_status pcg(amg_hierarchy *h, const double *b_user, double *x_user, double rt
     rr_prev = sc.rr;
     it_prev = sc.iter;
     const int32_t c = std::min(chunk, maxit - queued);
-    for (int32_t k = 0; k < c; ++k) {
+    int32_t k = 0;
+    if (h->iter_exec4)
+      for (; k + kIterGroup <= c; k += kIterGroup) AMG_HIP(hipGraphLaunch(h->iter_exec4, s));
+    for (; k < c; ++k) {
       if (h->iter_exec) AMG_HIP(hipGraphLaunch(h->iter_exec, s));
       else cg_iteration(h);
     }
