@@ -70,12 +70,16 @@ _F64P = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 
 
 def load():
+    """Loads liboracle.so (building it if absent). ORACLE_LIB names another
+    build of oracle.c to load instead (the mutation tests use it to check
+    that the pins reject a planted mistake)."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
+    path = os.environ.get("ORACLE_LIB") or _LIB_PATH
+    if path == _LIB_PATH and not os.path.exists(_LIB_PATH):
         build_oracle()
-    lib = C.CDLL(_LIB_PATH)
+    lib = C.CDLL(path)
     P = C.POINTER(_Csr)
     sig = {
         "orc_spmv": (None, [P, _F64P, _F64P]),

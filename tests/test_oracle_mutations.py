@@ -1,0 +1,130 @@
+"""The oracle's pins reject plausible mistakes.
+
+Each case plants one mistake in a copy of oracle/oracle.c (a dropped factor,
+a wrong sign or index, a transposed operand, a wrong tie-break order, a
+missing normalisation), builds that copy with gcc into a temporary library
+and runs the pin test that must reject it, in a child process that loads the
+copy through ORACLE_LIB. The case passes when that pin test fails. Nothing
+here touches the GPU path.
+"""
+
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+INV = "tests/test_oracle_invariants.py::"
+PIN = "tests/test_oracle_paper_pins.py::"
+
+# (mistake, text in oracle.c, replacement, pin test that must reject it)
+MUTATIONS = [
+    ("eq. (weights): factor 2 dropped",
+     "double num = ((2.0 * a) * w[i]) * w[j];", "double num = ((1.0 * a) * w[i]) * w[j];",
+     INV + "test_weights_isotropic_closed_form"),
+    ("eq. (weights): w_i for w_j in the denominator",
+     "double den = (aii * w[i]) * w[i] + (ajj * w[j]) * w[j];",
+     "double den = (aii * w[i]) * w[i] + (ajj * w[i]) * w[j];",
+     INV + "test_weights_invariants"),
+    ("eq. (weights): sign of the coupling term",
+     "c[e] = 1.0 - num / den;", "c[e] = 1.0 + num / den;",
+     PIN + "test_table1_gauss_seidel"),
+    ("matching: lightest edges first",
+     "if (a->c > b->c) return -1;\n  if (a->c < b->c) return 1;",
+     "if (a->c < b->c) return -1;\n  if (a->c > b->c) return 1;",
+     PIN + "test_table1_gauss_seidel"),
+    ("matching: second tie-break reversed",
+     "if (a->hi != b->hi) return a->hi < b->hi ? -1 : 1;\n  return 0;\n}\n\nint64_t",
+     "if (a->hi != b->hi) return a->hi > b->hi ? -1 : 1;\n  return 0;\n}\n\nint64_t",
+     INV + "test_matching_equals_locally_dominant"),
+    ("matching: first tie-break reversed",
+     "if (a->lo != b->lo) return a->lo < b->lo ? -1 : 1;\n  if (a->hi != b->hi) return a->hi < b->hi ? -1 : 1;\n  return 0;\n}\n\nint64_t",
+     "if (a->lo != b->lo) return a->lo > b->lo ? -1 : 1;\n  if (a->hi != b->hi) return a->hi < b->hi ? -1 : 1;\n  return 0;\n}\n\nint64_t",
+     INV + "test_tiny_exhaustive_matchings_on_path_graphs"),
+    ("eq. (prolongator): norm without square root",
+     "p[v] = w[v] / sqrt(s);", "p[v] = w[v] / s;",
+     INV + "test_numbering_and_prolongator"),
+    ("eq. (prolongator): singleton entry not normalised",
+     "p[v] = w[v] / fabs(w[v]);", "p[v] = 1.0;",
+     INV + "test_numbering_and_prolongator"),
+    ("Galerkin product: p_lo for p_hi",
+     "buf[cnt].t = (p[lo] * a) * p[hi];", "buf[cnt].t = (p[lo] * a) * p[lo];",
+     INV + "test_galerkin_matches_dense_product"),
+    ("restriction of w: prolongator weights dropped",
+     "double t = p[i] * v[i];", "double t = v[i];",
+     INV + "test_numbering_and_prolongator"),
+    ("l1-Jacobi: absolute value dropped",
+     "s = s + fabs(A->val[k]);", "s = s + A->val[k];",
+     PIN + "test_table1_l1_jacobi"),
+    ("l1-Jacobi: plain diagonal",
+     "m[i] = aii + s;", "m[i] = aii;",
+     PIN + "test_table1_l1_jacobi"),
+    ("eq. (amg): post-smoothing sign",
+     "for (int32_t i = 0; i < n; ++i) z[i] = z[i] + (r[i] - t[i]) / m[i];\n  }\n  free(t);",
+     "for (int32_t i = 0; i < n; ++i) z[i] = z[i] - (r[i] - t[i]) / m[i];\n  }\n  free(t);",
+     INV + "test_vcycle_two_level_equals_error_propagation_product"),
+    ("eq. (amg): prolongation without P's values",
+     "z[i] = z[i] + h->p[l][i] * zc[h->agg[l][i]];", "z[i] = z[i] + zc[h->agg[l][i]];",
+     INV + "test_vcycle_two_level_equals_error_propagation_product"),
+    ("eq. (amg): residual sign",
+     "for (int32_t i = 0; i < n; ++i) t[i] = r[i] - t[i];",
+     "for (int32_t i = 0; i < n; ++i) t[i] = r[i] + t[i];",
+     INV + "test_vcycle_two_level_equals_error_propagation_product"),
+    ("CG: beta inverted",
+     "double beta = rz / rho;", "double beta = rho / rz;",
+     INV + "test_pcg_small_case_against_dst_exact"),
+    ("Cholesky: back substitution with L for its transpose",
+     "for (int32_t k = i + 1; k < n; ++k) t = t - L[(int64_t)k * n + i] * z[k];",
+     "for (int32_t k = i + 1; k < n; ++k) t = t - L[(int64_t)i * n + k] * z[k];",
+     INV + "test_cholesky_against_lapack"),
+    ("sweep composition: earlier prolongator dropped",
+     "p_c[i] = p_c[i] * pk[a];", "p_c[i] = pk[a];",
+     INV + "test_isotropic_hierarchy_closed_form"),
+    ("numbering: partner of a pair left unnumbered",
+     "if (mate[v] >= 0) agg[mate[v]] = next;", "if (mate[v] >= 0 && 0) agg[mate[v]] = next;",
+     PIN + "test_table1_gauss_seidel"),
+]
+
+
+def _run_mutant(case, workdir):
+    name, old, new, pin = case
+    src = open(SRC).read()
+    if src.count(old) != 1:
+        return "oracle.c no longer holds the text this case mutates"
+    os.makedirs(workdir, exist_ok=True)
+    mutant = os.path.join(workdir, "oracle.c")
+    with open(mutant, "w") as f:
+        f.write(src.replace(old, new, 1))
+    lib = os.path.join(workdir, "liboracle.so")
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+                    "-I", os.path.dirname(SRC), "-o", lib, mutant, "-lm"],
+                   check=True, capture_output=True)
+    env = dict(os.environ, ORACLE_LIB=lib, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
+               MKL_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", pin],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    if r.returncode == 1:
+        return None
+    return "pin %s did not reject it (exit %d):\n%s" % (pin, r.returncode, r.stdout[-2000:])
+
+
+@pytest.fixture(scope="module")
+def outcomes(tmp_path_factory):
+    """Every mutant built and checked once, four child processes at a time."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    base = tmp_path_factory.mktemp("mutants")
+    workers = max(1, min(4, (os.cpu_count() or 1) // 2))
+    with ThreadPoolExecutor(workers) as ex:
+        res = list(ex.map(lambda kc: _run_mutant(kc[1], str(base / str(kc[0]))),
+                          enumerate(MUTATIONS)))
+    return {m[0]: r for m, r in zip(MUTATIONS, res)}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", [m[0] for m in MUTATIONS])
+def test_pin_rejects_planted_mistake(outcomes, name):
+    assert outcomes[name] is None, outcomes[name]
