@@ -4,16 +4,72 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "internal.h"
 
 namespace amg {
 
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_pool_mu;
+hipMemPool_t g_pool[kMaxDevices] = {};
+bool g_pool_tried[kMaxDevices] = {};
+
+// The library's pool on `device`, created on first use; null if the device
+// or runtime has no stream-ordered allocator.
+hipMemPool_t lib_pool(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  if (!g_pool_tried[device]) {
+    g_pool_tried[device] = true;
+    int supported = 0;
+    if (hipDeviceGetAttribute(&supported, hipDeviceAttributeMemoryPoolsSupported, device) !=
+            hipSuccess ||
+        !supported) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    hipMemPoolProps props;
+    std::memset(&props, 0, sizeof(props));
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = device;
+    hipMemPool_t pool = nullptr;
+    if (hipMemPoolCreate(&pool, &props) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    uint64_t keep = kPoolKeepBytes;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    g_pool[device] = pool;
+  }
+  return g_pool[device];
+}
+
+}  // namespace
+
+amg_status stream_alloc(int device, hipStream_t s, void **p, size_t bytes) {
+  *p = nullptr;
+  hipMemPool_t pool = lib_pool(device);
+  if (pool) AMG_HIP(hipMallocFromPoolAsync(p, bytes, pool, s));
+  else AMG_HIP(hipMalloc(p, bytes));
+  return AMG_OK;
+}
+
+void stream_free(int device, hipStream_t s, void *p) {
+  if (!p) return;
+  if (lib_pool(device)) (void)hipFreeAsync(p, s);
+  else (void)hipFree(p);
+}
+
 amg_status dev_alloc(amg_hierarchy *h, void **p, size_t bytes) {
   *p = nullptr;
   void *q = nullptr;
-  AMG_HIP(hipMalloc(&q, bytes));
+  AMG_TRY(stream_alloc(h->device, h->stream, &q, bytes));
   h->allocs.push_back(q);
   h->bytes += bytes;
   *p = q;
@@ -29,7 +85,7 @@ amg_status join_user_stream(amg_hierarchy *h) {
 void dev_release(amg_hierarchy *h, void *p) {
   for (auto &q : h->allocs)
     if (q == p) {
-      (void)hipFree(q);
+      stream_free(h->device, h->stream, q);
       q = nullptr;
     }
 }
@@ -53,9 +109,9 @@ void destroy(amg_hierarchy *h) {
   if (h->iter_graph) (void)hipGraphDestroy(h->iter_graph);
   if (h->iter_exec4) (void)hipGraphExecDestroy(h->iter_exec4);
   if (h->iter_graph4) (void)hipGraphDestroy(h->iter_graph4);
-  for (void *p : h->allocs)
-    if (p) (void)hipFree(p);
-  if (h->batch) free_batch(h->batch);
+  if (h->batch) free_batch(h->batch, h->device, h->stream);
+  for (void *p : h->allocs) stream_free(h->device, h->stream, p);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
   if (h->scal_host) (void)hipHostFree(h->scal_host);
   if (h->join_event) (void)hipEventDestroy(h->join_event);
   if (h->stream) (void)hipStreamDestroy(h->stream);
@@ -192,35 +248,44 @@ amg_status amg_level_info(const amg_hierarchy *h, int32_t l, int64_t *n, int64_t
   return AMG_OK;
 }
 
+namespace {
+// device-to-host copy ordered after all of the hierarchy's queued work
+amg_status d2h(const amg_hierarchy *h, void *dst, const void *src, size_t bytes) {
+  AMG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
+  AMG_HIP(hipStreamSynchronize(h->stream));
+  return AMG_OK;
+}
+}  // namespace
+
 amg_status amg_get_level_csr(const amg_hierarchy *h, int32_t l, int32_t *rp, int32_t *ci,
                              double *val) {
   if (!h || l < 0 || l >= (int32_t)h->lv.size()) return AMG_ERR_ARG;
   const Level &L = h->lv[l];
-  if (rp) AMG_HIP(hipMemcpy(rp, L.rp, sizeof(int32_t) * (L.n + 1), hipMemcpyDeviceToHost));
-  if (ci) AMG_HIP(hipMemcpy(ci, L.ci, sizeof(int32_t) * L.nnz, hipMemcpyDeviceToHost));
-  if (val) AMG_HIP(hipMemcpy(val, L.val, sizeof(double) * L.nnz, hipMemcpyDeviceToHost));
+  if (rp) AMG_TRY(d2h(h, rp, L.rp, sizeof(int32_t) * (L.n + 1)));
+  if (ci) AMG_TRY(d2h(h, ci, L.ci, sizeof(int32_t) * L.nnz));
+  if (val) AMG_TRY(d2h(h, val, L.val, sizeof(double) * L.nnz));
   return AMG_OK;
 }
 
 amg_status amg_get_transfer(const amg_hierarchy *h, int32_t l, int32_t *agg, double *p) {
   if (!h || l < 0 || l + 1 >= (int32_t)h->lv.size()) return AMG_ERR_ARG;
   const Level &L = h->lv[l];
-  if (agg) AMG_HIP(hipMemcpy(agg, L.agg, sizeof(int32_t) * L.n, hipMemcpyDeviceToHost));
-  if (p) AMG_HIP(hipMemcpy(p, L.p64, sizeof(double) * L.n, hipMemcpyDeviceToHost));
+  if (agg) AMG_TRY(d2h(h, agg, L.agg, sizeof(int32_t) * L.n));
+  if (p) AMG_TRY(d2h(h, p, L.p64, sizeof(double) * L.n));
   return AMG_OK;
 }
 
 amg_status amg_get_l1diag(const amg_hierarchy *h, int32_t l, double *m) {
   if (!h || !m || l < 0 || l + 1 >= (int32_t)h->lv.size()) return AMG_ERR_ARG;
   const Level &L = h->lv[l];
-  AMG_HIP(hipMemcpy(m, L.m, sizeof(double) * L.n, hipMemcpyDeviceToHost));
+  AMG_TRY(d2h(h, m, L.m, sizeof(double) * L.n));
   return AMG_OK;
 }
 
 amg_status amg_get_w(const amg_hierarchy *h, int32_t l, double *w) {
   if (!h || !w || l < 0 || l >= (int32_t)h->lv.size()) return AMG_ERR_ARG;
   const Level &L = h->lv[l];
-  AMG_HIP(hipMemcpy(w, L.w, sizeof(double) * L.n, hipMemcpyDeviceToHost));
+  AMG_TRY(d2h(h, w, L.w, sizeof(double) * L.n));
   return AMG_OK;
 }
 

@@ -76,12 +76,8 @@ __global__ void __launch_bounds__(kBlock) kb_pre_residual(
   for (int32_t row = rb + threadIdx.x / KT; row < re; row += kBlock / KT) {
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
-    TV acc = 0;
-    for (int32_t e = 0; e < w; ++e) {
-      const int32_t idx = base + e * kSlice;
-      const int32_t c = ld_stream(&col[idx]);
-      acc += ld_stream(&val[idx]) * (TV)R[(int64_t)c * k + j];  // val holds A M^-1
-    }
+    // val holds A M^-1
+    const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return (TV)R[(int64_t)c * k + j]; });
     const int64_t o = (int64_t)row * k + j;
     const TV ri = (TV)R[o];
     Z[o] = ri * minv[row];
@@ -105,11 +101,7 @@ __global__ void __launch_bounds__(kBlock) kb_post(
     for (int32_t row = rb + threadIdx.x / KT; row < re; row += kBlock / KT) {
       int32_t base, w;
       sell_row(sptr, row, &base, &w);
-      TV acc = 0;
-      for (int32_t e = 0; e < w; ++e) {
-        const int32_t idx = base + e * kSlice;
-        acc += ld_stream(&val[idx]) * Z[(int64_t)ld_stream(&col[idx]) * k + j];
-      }
+      const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return Z[(int64_t)c * k + j]; });
       const int64_t o = (int64_t)row * k + j;
       const TR rr = R[o];
       const TO yo = (TO)(Z[o] + ((TV)rr - acc) * minv[row]);
@@ -132,7 +124,20 @@ __global__ void kb_restrict(int32_t nc, int32_t k, const int32_t *__restrict__ s
   if (j >= k || I >= nc) return;
   const int32_t b = seg[I], e = seg[I + 1];
   TV s = 0;
-  for (int32_t m = b; m < e; ++m) s += pp[m] * T[(int64_t)m * k + j];
+  for (int32_t m0 = b; m0 < e; m0 += 8) {  // loads of eight members before their use
+    TV pv[8], tv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      pv[u] = tv[u] = 0;
+      if (m0 + u < e) {
+        pv[u] = pp[m0 + u];
+        tv[u] = T[(int64_t)(m0 + u) * k + j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (m0 + u < e) s += pv[u] * tv[u];
+  }
   Rc[I * k + j] = s;
 }
 
@@ -170,7 +175,20 @@ __global__ void kb_coarse(int32_t nL, int32_t k, const double *__restrict__ Ainv
   const int32_t i = (int32_t)(e / k), j = (int32_t)(e % k);
   const double *row = Ainv + (int64_t)i * nL;
   double s = 0.0;
-  for (int32_t m = 0; m < nL; ++m) s += row[m] * (double)R[(int64_t)m * k + j];
+  for (int32_t m0 = 0; m0 < nL; m0 += 8) {  // loads of eight terms before their use
+    double av[8], rv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      av[u] = rv[u] = 0.0;
+      if (m0 + u < nL) {
+        av[u] = row[m0 + u];
+        rv[u] = (double)R[(int64_t)(m0 + u) * k + j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (m0 + u < nL) s += av[u] * rv[u];
+  }
   Z[e] = (TO)s;
 }
 
@@ -197,11 +215,8 @@ __global__ void __launch_bounds__(kBlock) kb_spmv(
     for (int32_t row = rb + threadIdx.x / KT; row < re; row += kBlock / KT) {
       int32_t base, w;
       sell_row(sptr, row, &base, &w);
-      double acc = 0.0;
-      for (int32_t e = 0; e < w; ++e) {
-        const int32_t idx = base + e * kSlice;
-        acc += ld_stream(&val[idx]) * Xin[(int64_t)ld_stream(&col[idx]) * k + j];
-      }
+      const double acc =
+          sell_dot(col, val, base, w, [&](int32_t c) { return Xin[(int64_t)c * k + j]; });
       const int64_t o = (int64_t)row * k + j;
       if (mode == 0) {
         Out[o] = acc;
@@ -592,7 +607,7 @@ void small_kernel(amg_hierarchy *h, int32_t which) {
 
 amg_status balloc(amg_hierarchy *h, void **p, size_t bytes) {
   Batch &B = *h->batch;
-  AMG_HIP(hipMalloc(p, bytes + 16));
+  AMG_TRY(stream_alloc(h->device, h->stream, p, bytes + 16));
   B.allocs.push_back(*p);
   B.bytes += bytes + 16;
   return AMG_OK;
@@ -601,7 +616,7 @@ amg_status balloc(amg_hierarchy *h, void **p, size_t bytes) {
 amg_status ensure_batch(amg_hierarchy *h, int32_t k) {
   if (h->batch && h->batch->k == k) return AMG_OK;
   if (h->batch) {
-    free_batch(h->batch);
+    free_batch(h->batch, h->device, h->stream);
     h->batch = nullptr;
     h->batch_bytes = 0;
   }
@@ -701,11 +716,11 @@ amg_status autotune(amg_hierarchy *h) {
 
 }  // namespace
 
-void free_batch(Batch *b) {
+void free_batch(Batch *b, int device, hipStream_t s) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  for (void *p : b->allocs) (void)hipFree(p);
+  for (void *p : b->allocs) stream_free(device, s, p);
   if (b->col_host) (void)hipHostFree(b->col_host);
   if (b->iter_host) (void)hipHostFree(b->iter_host);
   if (b->done_host) (void)hipHostFree(b->done_host);

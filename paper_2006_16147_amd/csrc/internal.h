@@ -127,7 +127,7 @@ struct Batch {
   size_t bytes = 0;
 };
 
-void free_batch(Batch *b);
+void free_batch(Batch *b, int device, hipStream_t s);  // releases on stream s
 
 }  // namespace amg
 
@@ -165,6 +165,13 @@ struct amg_hierarchy {
 namespace amg {
 
 // allocation owned by the hierarchy (freed in amg_free)
+// Device memory of the library comes from one stream-ordered pool per device
+// (allocation and release are ordered on the given stream and never wait for
+// the whole device, unlike hipFree); freed memory up to kPoolKeepBytes stays
+// reserved in the pool for reuse. Without pool support: hipMalloc / hipFree.
+constexpr uint64_t kPoolKeepBytes = 8ull << 30;
+amg_status stream_alloc(int device, hipStream_t s, void **p, size_t bytes);
+void stream_free(int device, hipStream_t s, void *p);
 amg_status dev_alloc(amg_hierarchy *h, void **p, size_t bytes);
 template <typename T>
 inline amg_status dalloc(amg_hierarchy *h, T **p, size_t count) {
@@ -199,6 +206,38 @@ amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t 
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T *p) {
   return __builtin_nontemporal_load(p);
+}
+
+// sum_k val[k] * x(col[k]) over one SELL row, in entry order. The slice
+// width w is the same for the 64 rows of a wavefront, so the guards are
+// uniform; each group of up to eight entries issues all its index and value
+// loads, then all its gathers, before the first product, which keeps eight
+// gathers per lane in flight instead of one.
+constexpr int kRowBatch = 8;
+template <typename TV, typename X>
+__device__ __forceinline__ TV sell_dot(const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                       int32_t base, int32_t w, X x) {
+  TV acc = 0;
+  for (int32_t k0 = 0; k0 < w; k0 += kRowBatch) {
+    int32_t c[kRowBatch];
+    TV v[kRowBatch], g[kRowBatch];
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      c[u] = 0;
+      v[u] = 0;
+      if (k0 + u < w) {
+        const int32_t idx = base + (k0 + u) * kSlice;
+        c[u] = ld_stream(&col[idx]);
+        v[u] = ld_stream(&val[idx]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) g[u] = k0 + u < w ? x(c[u]) : TV(0);
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u)
+      if (k0 + u < w) acc += v[u] * g[u];
+  }
+  return acc;
 }
 
 // grid helpers

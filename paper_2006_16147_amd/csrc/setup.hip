@@ -687,15 +687,21 @@ __global__ void k_inverse_from_factor(int32_t n, const double *X, double *Ainv) 
 inline int32_t grid(int64_t n) { return ceil_div(n > 0 ? n : 1, kBlock); }
 
 // temporaries of one setup call (not owned by the hierarchy)
+// (released in stream order on the setup stream when dropped or destroyed)
 struct Tmp {
+  int device;
+  hipStream_t s;
   std::vector<void *> ptrs;
+  explicit Tmp(const amg_hierarchy *h) : device(h->device), s(h->stream) {}
+  Tmp(const Tmp &) = delete;
+  Tmp &operator=(const Tmp &) = delete;
   ~Tmp() {
-    for (void *p : ptrs) (void)hipFree(p);
+    for (void *p : ptrs) stream_free(device, s, p);
   }
   template <typename T>
   amg_status get(T **p, size_t count) {
     void *q = nullptr;
-    AMG_HIP(hipMalloc(&q, count * sizeof(T) + 16));
+    AMG_TRY(stream_alloc(device, s, &q, count * sizeof(T) + 16));
     ptrs.push_back(q);
     *p = reinterpret_cast<T *>(q);
     return AMG_OK;
@@ -703,7 +709,7 @@ struct Tmp {
   void drop(void *p) {
     for (auto &q : ptrs)
       if (q == p) {
-        (void)hipFree(q);
+        stream_free(device, s, q);
         q = nullptr;
       }
   }
@@ -899,7 +905,7 @@ amg_status build_hierarchy(amg_hierarchy *h, const amg_csr *A) {
   const int32_t n0 = (int32_t)A->n;
   double T[8] = {0};
   double t_start = now_ms();
-  Tmp tmp;
+  Tmp tmp(h);
 
   // validation
   int32_t *err;
@@ -939,7 +945,7 @@ amg_status build_hierarchy(amg_hierarchy *h, const amg_csr *A) {
     const int32_t n = h->lv[l].n;
     if (n <= P.max_coarse || l == P.max_levels - 1) break;
     Mat cur{h->lv[l].n, h->lv[l].nnz, h->lv[l].rp, h->lv[l].ci, h->lv[l].val, h->lv[l].w};
-    Tmp sweep_tmp;  // intermediate sweep matrices
+    Tmp sweep_tmp(h);  // intermediate sweep matrices
     int32_t *agg_c = nullptr, *mptr = nullptr, *mem = nullptr;
     double *p_c = nullptr;
     AMG_TRY(sweep_tmp.get(&agg_c, n));
@@ -952,7 +958,7 @@ amg_status build_hierarchy(amg_hierarchy *h, const amg_csr *A) {
     std::vector<Tmp *> owners;
     Tmp *prev_owner = nullptr;
     for (int32_t k = 0; k < P.sweeps; ++k) {
-      Tmp *own = new Tmp();
+      Tmp *own = new Tmp(h);
       SweepOut o;
       amg_status st = pairwise_sweep(h, *own, cur, o, &t_match, &t_number, &t_rap);
       if (st != AMG_OK) {

@@ -76,38 +76,6 @@ __device__ __forceinline__ void sell_row(const int32_t *sptr, int32_t row, int32
   *w = (sptr[s + 1] - b0) / kSlice;
 }
 
-// sum_k val[k] * x(col[k]) over one SELL row, in entry order. The slice
-// width w is the same for the 64 rows of a wavefront, so the guards are
-// uniform; each group of up to eight entries issues all its index and value
-// loads, then all its gathers, before the first product, which keeps eight
-// gathers per lane in flight instead of one.
-constexpr int kRowBatch = 8;
-template <typename TV, typename X>
-__device__ __forceinline__ TV sell_dot(const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                       int32_t base, int32_t w, X x) {
-  TV acc = 0;
-  for (int32_t k0 = 0; k0 < w; k0 += kRowBatch) {
-    int32_t c[kRowBatch];
-    TV v[kRowBatch], g[kRowBatch];
-#pragma unroll
-    for (int u = 0; u < kRowBatch; ++u) {
-      c[u] = 0;
-      v[u] = 0;
-      if (k0 + u < w) {
-        const int32_t idx = base + (k0 + u) * kSlice;
-        c[u] = ld_stream(&col[idx]);
-        v[u] = ld_stream(&val[idx]);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kRowBatch; ++u) g[u] = k0 + u < w ? x(c[u]) : TV(0);
-#pragma unroll
-    for (int u = 0; u < kRowBatch; ++u)
-      if (k0 + u < w) acc += v[u] * g[u];
-  }
-  return acc;
-}
-
 // zf[k] += pp[k] * y(aggp[k]) for k = k0 + t, k0 + t + nth, ... < k1: each
 // thread issues the loads of four of its positions before their use.
 template <typename TV, typename Y>
