@@ -298,16 +298,20 @@ size_t amg_estimate_footprint(int64_t n, int64_t nnz, const amg_params *params) 
   if (params) P = *params;
   else amg_params_default(&P);
   const double V = P.precision == AMG_FP32 ? 4.0 : 8.0;
+  const double X = P.precision == AMG_FP32 ? 4.0 : 0.0;  // FP32 copies kept beside FP64
   // geometric bound of the level sizes (coarsening by >= 2 per sweep)
   const double shrink = 1.0 / (1 << (P.sweeps < 1 ? 1 : P.sweeps));
   const double sn = n / (1.0 - shrink), sz = nnz / (1.0 - shrink);
+  // SELL padding: ~1 % on the stencil rows of level 0, up to 30 % on Galerkin levels
+  const double pad = 1.02 * nnz + 1.3 * (sz - nnz);
   double b = 0;
-  b += sz * (4 + 8) + sn * 4 * 2;          // FP64 CSR of every level
-  b += 8 * sn * 2;                          // w, m
-  b += 1.01 * sz * (4 + V) + 8.0 * nnz;     // SELL (+ FP64 values of level 0)
-  b += sn * (V + 4 + V + 4 + V);            // minv, agg, p, mptr/mem, pm
-  b += 4 * V * sn;                          // V-cycle vectors
-  b += 4 * 8.0 * n;                         // CG vectors
+  b += sz * (4 + 8) + sn * 4;                   // FP64 CSR of every level
+  b += sn * (3 * 8 + 4 + 8 + 4 + 4);            // w, m, 1/m, agg, p, mptr, mem
+  b += sn * (4 * 4 + 8) + sn * 2 * X;           // perm, iperm, seg, aggp, pp (+ FP32 pp, 1/m)
+  b += pad * (4 + 2 * 8 + 2 * X);               // SELL: columns, A, A M^-1 (+ FP32 copies)
+  b += 4 * V * sn;                              // V-cycle vectors
+  b += 6 * 8.0 * n;                             // CG vectors (x, r, z, p, q, b)
+  b += 2 * 65536 * 8.0;                         // block partials
   // peak of the setup temporaries (weights, Galerkin staging, sweep matrices)
   b += 8.0 * nnz + 12.0 * nnz + 2 * (12.0 * nnz + 16.0 * n);
   const double nL = P.max_coarse;

@@ -234,3 +234,50 @@ def test_fp32_hierarchy_reaches_fp64_residual(orc):
     xo, _ = orc.Hierarchy(A).pcg(b, rtol=1e-12)
     err = np.linalg.norm(x32 - xo) / np.linalg.norm(xo)
     assert err < 1e-6, err
+
+
+# V-cycle shapes: the one-block tail (prolonging into level 0 or a deeper
+# level), the separate coarsest kernel (coarsest above 512 rows, or the level
+# above it above 2048 rows), and extra smoothing sweeps
+VCYCLE_CASES = {
+    "tail_into_level1": (40, {}, 1, 1),
+    "coarse_above_512": (40, {"max_coarse": 1000}, 1, 1),
+    "last_level_above_2048": (32, {"max_coarse": 600}, 1, 1),
+    "pre2_post2": (20, {}, 2, 2),
+    "pre3_post1": (24, {}, 3, 1),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", sorted(VCYCLE_CASES))
+def test_vcycle_shapes_match_oracle(orc, case, precision):
+    import torch
+
+    from paper_2006_16147_amd import amg
+
+    N, hp, pre, post = VCYCLE_CASES[case]
+    A = inputs.laplacian7(N)
+    prec = amg.FP32 if precision == "fp32" else amg.FP64
+    h = setup(A, pre=pre, post=post, precision=prec, **hp)
+    ho = orc.Hierarchy(A, **hp)
+    assert h.sizes() == [ho.level_n(l) for l in range(ho.num_levels)]
+    r = np.random.default_rng(7).uniform(-1, 1, A.n)
+    z = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    amg.amg_vcycle_apply(h, to_dev(r), z)
+    zo = ho.vcycle(r, pre=pre, post=post)
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=0, atol=tol * np.abs(zo).max())
+
+
+@pytest.mark.parametrize("pre,post", [(2, 2), (1, 3)])
+def test_pcg_extra_sweeps_match_oracle(orc, pre, post):
+    c = inputs.small_case(20, seed=0)
+    A, b = c["A"], c["b"]
+    h = setup(A, pre=pre, post=post)
+    ho = orc.Hierarchy(A)
+    st, info, x = solve(h, b, rtol=1e-8, maxit=200)
+    assert st == 0 and info["converged"]
+    _, io = ho.pcg(b, rtol=1e-8, maxit=200, pre=pre, post=post)
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    xo, _ = ho.pcg(b, rtol=0.0, maxit=info["iterations"], pre=pre, post=post)
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8

@@ -53,3 +53,22 @@ def test_gpu_serving_eviction_under_small_budget(backend):
     srv.close()
     assert summarize(res)["completed"] == len(reqs)
     assert srv.peak_used <= srv.budget
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_footprint_estimate_bounds_the_hierarchy(backend, precision):
+    """Admission reserves amg_estimate_footprint: it must cover what a
+    hierarchy keeps, for isotropic and anisotropic operators of the stream."""
+    import torch
+
+    from paper_2006_16147_amd import amg
+
+    prec = amg.FP32 if precision == "fp32" else amg.FP64
+    params = amg.amg_params_default(precision=prec)
+    for N, eps in ((32, (1.0, 1.0)), (48, (1e-3, 1.0)), (64, (0.05, 0.3))):
+        rp, ci, va = inputs.constant_diffusion7_arrays(N, eps[0], eps[1], 1.0, torch,
+                                                       device="cuda")
+        h = amg.amg_setup(rp, ci, va, precision=prec)
+        est = amg.amg_estimate_footprint(N ** 3, int(va.numel()), params)
+        assert h.footprint_bytes() <= est, (N, eps, h.footprint_bytes(), est)
+        h.close()
