@@ -142,7 +142,10 @@ __device__ __forceinline__ bool converged(double rr, double bb, double rtol) {
 __global__ void __launch_bounds__(1024) k_finalize(int32_t op, int32_t nparts,
                                                    const double *__restrict__ partials,
                                                    PcgScal *scal, const int32_t *done) {
-  if (done && *done) return;
+  // the stop flag and the scalars are loaded with the partials, not before
+  const int32_t stop = done ? *done : 0;
+  PcgScal sc;
+  if (threadIdx.x == 0) sc = *scal;
   __shared__ double sh[2][1024 / kWave];
   const int nv = op == kFinInit ? 2 : 1;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -165,7 +168,7 @@ __global__ void __launch_bounds__(1024) k_finalize(int32_t op, int32_t nparts,
     if (lane == 0) sh[q][wid] = a;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0 || stop) return;
   double tot[2] = {0.0, 0.0};
   for (int q = 0; q < nv; ++q) {
     double t = sh[q][0];
@@ -174,34 +177,34 @@ __global__ void __launch_bounds__(1024) k_finalize(int32_t op, int32_t nparts,
   }
   switch (op) {
     case kFinInit: {
-      const double rtol = scal->rtol;
+      const double rtol = sc.rtol;
       scal->bb = tot[0];
       scal->rr = tot[1];
       scal->tol2 = rtol * rtol * tot[0];
       if (tot[0] == 0.0) scal->done = 4;
       else if (converged(tot[1], tot[0], rtol)) scal->done = 1;
-      else if (scal->maxit <= 0) scal->done = 2;
+      else if (sc.maxit <= 0) scal->done = 2;
       break;
     }
     case kFinPQ:
       scal->pq = tot[0];
       if (!(tot[0] > 0.0)) scal->done = 3;
-      else scal->alpha = scal->rho / tot[0];
+      else scal->alpha = sc.rho / tot[0];
       break;
     case kFinRR:
       scal->rr = tot[0];
-      scal->iter += 1;
-      if (converged(tot[0], scal->bb, scal->rtol)) scal->done = 1;
-      else if (scal->iter >= scal->maxit) scal->done = 2;
+      scal->iter = sc.iter + 1;
+      if (converged(tot[0], sc.bb, sc.rtol)) scal->done = 1;
+      else if (sc.iter + 1 >= sc.maxit) scal->done = 2;
       break;
     case kFinRZ:
       if (!(tot[0] > 0.0)) {
         scal->done = 3;
-      } else if (scal->phase == 0) {
+      } else if (sc.phase == 0) {
         scal->rho = tot[0];
         scal->phase = 1;
       } else {
-        scal->beta = tot[0] / scal->rho;
+        scal->beta = tot[0] / sc.rho;
         scal->rho = tot[0];
       }
       break;
@@ -459,6 +462,9 @@ __global__ void __launch_bounds__(1024) k_coarse_prolong(
 // in LDS. Replaces the three latency-bound kernels of the last two levels.
 constexpr int kTailMax = 2048;  // largest level t handled in LDS
 constexpr int kTailCoarseMax = 512;
+constexpr int kTailPro = 8;    // prolongation positions per thread loaded up front (FP32;
+                               // half as many in FP64, within the register budget)
+constexpr int kTailRow = 16;   // A_L^-1 entries per thread loaded up front (n_L <= 128)
 template <typename TV>
 __global__ void __launch_bounds__(1024) k_tail(
     int32_t nt, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
@@ -471,6 +477,30 @@ __global__ void __launch_bounds__(1024) k_tail(
   __shared__ double rl[kTailCoarseMax], zl[kTailCoarseMax];
   if (*done) return;
   const int32_t tid = threadIdx.x, nth = blockDim.x;
+  // The operands of the last two phases do not depend on the first ones:
+  // load them now so their latency overlaps the phases before.
+  constexpr int kPro = sizeof(TV) == 8 ? kTailPro / 2 : kTailPro;
+  int32_t fa[kPro];  // prolongation: this thread's first kPro positions
+  TV fp[kPro], fz[kPro];
+#pragma unroll
+  for (int u = 0; u < kPro; ++u) {
+    const int32_t k = tid + u * nth;
+    fa[u] = 0;
+    fp[u] = fz[u] = 0;
+    if (k < nf) {
+      fa[u] = aggp_f[k];
+      fp[u] = pp_f[k];
+      fz[u] = zf[k];
+    }
+  }
+  const int32_t part = tid % kCoarseSplit, irow = tid / kCoarseSplit;
+  const bool one_pass = nL <= nth / kCoarseSplit && nL <= kCoarseSplit * kTailRow;
+  double av[kTailRow];  // this thread's entries of its A_L^-1 row (one pass)
+#pragma unroll
+  for (int m = 0; m < kTailRow; ++m) {
+    const int32_t k = part + m * kCoarseSplit;
+    av[m] = one_pass && irow < nL && k < nL ? Ainv[(int64_t)irow * nL + k] : 0.0;
+  }
   for (int32_t k = tid; k < nt; k += nth) {
     const TV r = rt[k];
     rs[k] = r;
@@ -491,17 +521,25 @@ __global__ void __launch_bounds__(1024) k_tail(
   }
   __syncthreads();
   // coarsest: eight threads per row of A_L^-1
-  const int32_t part = tid % kCoarseSplit;
-  for (int32_t i0 = 0; i0 < nL; i0 += nth / kCoarseSplit) {
-    const int32_t i = i0 + tid / kCoarseSplit;
+  if (one_pass) {
     double a = 0.0;
-    if (i < nL) {
-      const double *row = Ainv + (int64_t)i * nL;
-#pragma unroll 8
-      for (int32_t k = part; k < nL; k += kCoarseSplit) a += row[k] * rl[k];
-    }
+#pragma unroll
+    for (int m = 0; m < kTailRow; ++m)
+      if (part + m * kCoarseSplit < nL) a += av[m] * rl[part + m * kCoarseSplit];
     for (int o = kCoarseSplit / 2; o > 0; o >>= 1) a += __shfl_down(a, o, kCoarseSplit);
-    if (i < nL && part == 0) zl[i] = a;
+    if (irow < nL && part == 0) zl[irow] = a;
+  } else {
+    for (int32_t i0 = 0; i0 < nL; i0 += nth / kCoarseSplit) {
+      const int32_t i = i0 + irow;
+      double a = 0.0;
+      if (i < nL) {
+        const double *row = Ainv + (int64_t)i * nL;
+#pragma unroll 8
+        for (int32_t k = part; k < nL; k += kCoarseSplit) a += row[k] * rl[k];
+      }
+      for (int o = kCoarseSplit / 2; o > 0; o >>= 1) a += __shfl_down(a, o, kCoarseSplit);
+      if (i < nL && part == 0) zl[i] = a;
+    }
   }
   __syncthreads();
   for (int32_t k = tid; k < nt; k += nth) zs[k] += pp[k] * (TV)zl[aggp[k]];
@@ -513,7 +551,12 @@ __global__ void __launch_bounds__(1024) k_tail(
     ys[k] = zs[k] + (rs[k] - acc) * minv[k];
   }
   __syncthreads();
-  prolong_add(0, nf, tid, nth, aggp_f, pp_f, zf, [&](int32_t a) { return ys[a]; });
+#pragma unroll
+  for (int u = 0; u < kPro; ++u) {
+    const int32_t k = tid + u * nth;
+    if (k < nf) zf[k] = fz[u] + fp[u] * ys[fa[u]];
+  }
+  prolong_add(kPro * nth, nf, tid, nth, aggp_f, pp_f, zf, [&](int32_t a) { return ys[a]; });
 }
 
 // Single-level hierarchy: z = A_0^-1 r, one wavefront per row.
