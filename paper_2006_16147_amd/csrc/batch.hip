@@ -58,6 +58,45 @@ __device__ void column_partial(double d, bool valid, int32_t j, int32_t k, doubl
   }
 }
 
+// Register tiling over columns: the sparse-product kernels give each thread
+// kCpt columns of its row (j, j + KT, ...), so one load of a row's column
+// indices and values feeds kCpt gathers, and each lane keeps kCpt times as
+// many gathers in flight.
+constexpr int kCpt = 2;
+
+// acc[q] = sum_e val[e] * x(col[e], q) over one SELL row, entries in order,
+// loads issued in batches of kRowBatch entries
+template <typename TV, typename X>
+__device__ __forceinline__ void sell_dot_cols(const int32_t *__restrict__ col,
+                                              const TV *__restrict__ val, int32_t base,
+                                              int32_t w, X x, TV (&acc)[kCpt]) {
+#pragma unroll
+  for (int q = 0; q < kCpt; ++q) acc[q] = 0;
+  for (int32_t k0 = 0; k0 < w; k0 += kRowBatch) {
+    int32_t c[kRowBatch];
+    TV v[kRowBatch], g[kRowBatch][kCpt];
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      c[u] = 0;
+      v[u] = 0;
+      if (k0 + u < w) {
+        const int32_t idx = base + (k0 + u) * kSlice;
+        c[u] = ld_stream(&col[idx]);
+        v[u] = ld_stream(&val[idx]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u)
+#pragma unroll
+      for (int q = 0; q < kCpt; ++q) g[u][q] = k0 + u < w ? x(c[u], q) : TV(0);
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u)
+      if (k0 + u < w)
+#pragma unroll
+        for (int q = 0; q < kCpt; ++q) acc[q] += v[u] * g[u][q];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // V-cycle kernels on n x k blocks
 // ---------------------------------------------------------------------------
@@ -69,19 +108,33 @@ __global__ void __launch_bounds__(kBlock) kb_pre_residual(
     const TR *__restrict__ R, TV *__restrict__ Z, TV *__restrict__ T,
     const int32_t *__restrict__ stop) {
   if (*stop) return;
-  const int32_t j = blockIdx.y * KT + threadIdx.x % KT;
-  if (j >= k) return;
+  const int32_t j0 = blockIdx.y * (KT * kCpt) + threadIdx.x % KT;
+  if (j0 >= k) return;
+  int32_t jc[kCpt];
+  bool ok[kCpt];
+#pragma unroll
+  for (int q = 0; q < kCpt; ++q) {
+    jc[q] = j0 + q * KT;
+    ok[q] = jc[q] < k;
+  }
   int32_t rb, re;
   block_rows(n, chunk, &rb, &re);
   for (int32_t row = rb + threadIdx.x / KT; row < re; row += kBlock / KT) {
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
-    // val holds A M^-1
-    const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return (TV)R[(int64_t)c * k + j]; });
-    const int64_t o = (int64_t)row * k + j;
-    const TV ri = (TV)R[o];
-    Z[o] = ri * minv[row];
-    T[o] = ri - acc;
+    TV acc[kCpt];  // val holds A M^-1
+    sell_dot_cols(col, val, base, w,
+                  [&](int32_t c, int q) { return ok[q] ? (TV)R[(int64_t)c * k + jc[q]] : TV(0); },
+                  acc);
+    const TV mi = minv[row];
+#pragma unroll
+    for (int q = 0; q < kCpt; ++q) {
+      if (!ok[q]) continue;
+      const int64_t o = (int64_t)row * k + jc[q];
+      const TV ri = (TV)R[o];
+      Z[o] = ri * mi;
+      T[o] = ri - acc[q];
+    }
   }
 }
 
@@ -92,24 +145,80 @@ __global__ void __launch_bounds__(kBlock) kb_post(
     const TR *__restrict__ R, const TV *__restrict__ Z, TO *__restrict__ Y,
     double *__restrict__ partials, const int32_t *__restrict__ stop) {
   if (*stop) return;
-  const int32_t j = blockIdx.y * KT + threadIdx.x % KT;
-  const bool valid = j < k;
+  const int32_t j0 = blockIdx.y * (KT * kCpt) + threadIdx.x % KT;
+  int32_t jc[kCpt];
+  bool ok[kCpt];
+#pragma unroll
+  for (int q = 0; q < kCpt; ++q) {
+    jc[q] = j0 + q * KT;
+    ok[q] = jc[q] < k;
+  }
   int32_t rb, re;
   block_rows(n, chunk, &rb, &re);
-  double d = 0.0;
-  if (valid) {
+  double d[kCpt];
+#pragma unroll
+  for (int q = 0; q < kCpt; ++q) d[q] = 0.0;
+  if (ok[0]) {
     for (int32_t row = rb + threadIdx.x / KT; row < re; row += kBlock / KT) {
       int32_t base, w;
       sell_row(sptr, row, &base, &w);
-      const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return Z[(int64_t)c * k + j]; });
-      const int64_t o = (int64_t)row * k + j;
-      const TR rr = R[o];
-      const TO yo = (TO)(Z[o] + ((TV)rr - acc) * minv[row]);
-      Y[o] = yo;
-      if (DOT) d += (double)rr * (double)yo;
+      TV acc[kCpt];
+      sell_dot_cols(col, val, base, w,
+                    [&](int32_t c, int q) { return ok[q] ? Z[(int64_t)c * k + jc[q]] : TV(0); },
+                    acc);
+      const TV mi = minv[row];
+#pragma unroll
+      for (int q = 0; q < kCpt; ++q) {
+        if (!ok[q]) continue;
+        const int64_t o = (int64_t)row * k + jc[q];
+        const TR rr = R[o];
+        const TO yo = (TO)(Z[o] + ((TV)rr - acc[q]) * mi);
+        Y[o] = yo;
+        if (DOT) d[q] += (double)rr * (double)yo;
+      }
     }
   }
-  if (DOT) column_partial<KT>(d, valid, j, k, partials);
+  if (DOT) {
+#pragma unroll
+    for (int q = 0; q < kCpt; ++q) {
+      if (q) __syncthreads();
+      column_partial<KT>(d[q], ok[q], jc[q], k, partials);
+    }
+  }
+}
+
+// T = R - A Z (the residual after extra pre-smoothing sweeps)
+template <typename TV, typename TR, int KT>
+__global__ void __launch_bounds__(kBlock) kb_resid(
+    int32_t n, int32_t k, int32_t chunk, const int32_t *__restrict__ sptr,
+    const int32_t *__restrict__ col, const TV *__restrict__ val, const TR *__restrict__ R,
+    const TV *__restrict__ Z, TV *__restrict__ T, const int32_t *__restrict__ stop) {
+  if (*stop) return;
+  const int32_t j0 = blockIdx.y * (KT * kCpt) + threadIdx.x % KT;
+  if (j0 >= k) return;
+  int32_t jc[kCpt];
+  bool ok[kCpt];
+#pragma unroll
+  for (int q = 0; q < kCpt; ++q) {
+    jc[q] = j0 + q * KT;
+    ok[q] = jc[q] < k;
+  }
+  int32_t rb, re;
+  block_rows(n, chunk, &rb, &re);
+  for (int32_t row = rb + threadIdx.x / KT; row < re; row += kBlock / KT) {
+    int32_t base, w;
+    sell_row(sptr, row, &base, &w);
+    TV acc[kCpt];
+    sell_dot_cols(col, val, base, w,
+                  [&](int32_t c, int q) { return ok[q] ? Z[(int64_t)c * k + jc[q]] : TV(0); },
+                  acc);
+#pragma unroll
+    for (int q = 0; q < kCpt; ++q) {
+      if (!ok[q]) continue;
+      const int64_t o = (int64_t)row * k + jc[q];
+      T[o] = (TV)R[o] - acc[q];
+    }
+  }
 }
 
 // R_c(J) = sum over the segment of J (aggregate-major positions), in order,
@@ -206,38 +315,56 @@ __global__ void __launch_bounds__(kBlock) kb_spmv(
   // mode 1: Out = B - A Xin, partials (B, B), (Out, Out)   (initial residual)
   // mode 2: partials (B - A Xin)^2 only               (true residual)
   if (stop && *stop) return;
-  const int32_t j = blockIdx.y * KT + threadIdx.x % KT;
-  const bool valid = j < k;
+  const int32_t j0 = blockIdx.y * (KT * kCpt) + threadIdx.x % KT;
+  int32_t jc[kCpt];
+  bool ok[kCpt];
+#pragma unroll
+  for (int q = 0; q < kCpt; ++q) {
+    jc[q] = j0 + q * KT;
+    ok[q] = jc[q] < k;
+  }
   int32_t rb, re;
   block_rows(n, chunk, &rb, &re);
-  double d0 = 0.0, d1 = 0.0;
-  if (valid) {
+  double d0[kCpt], d1[kCpt];
+#pragma unroll
+  for (int q = 0; q < kCpt; ++q) d0[q] = d1[q] = 0.0;
+  if (ok[0]) {
     for (int32_t row = rb + threadIdx.x / KT; row < re; row += kBlock / KT) {
       int32_t base, w;
       sell_row(sptr, row, &base, &w);
-      const double acc =
-          sell_dot(col, val, base, w, [&](int32_t c) { return Xin[(int64_t)c * k + j]; });
-      const int64_t o = (int64_t)row * k + j;
-      if (mode == 0) {
-        Out[o] = acc;
-        d0 += Xin[o] * acc;
-      } else {
-        const double bi = B[o], ri = bi - acc;
-        if (mode == 1) {
-          Out[o] = ri;
-          d0 += bi * bi;
-          d1 += ri * ri;
+      double acc[kCpt];
+      sell_dot_cols(
+          col, val, base, w,
+          [&](int32_t c, int q) { return ok[q] ? Xin[(int64_t)c * k + jc[q]] : 0.0; }, acc);
+#pragma unroll
+      for (int q = 0; q < kCpt; ++q) {
+        if (!ok[q]) continue;
+        const int64_t o = (int64_t)row * k + jc[q];
+        if (mode == 0) {
+          Out[o] = acc[q];
+          d0[q] += Xin[o] * acc[q];
         } else {
-          d0 += ri * ri;
+          const double bi = B[o], ri = bi - acc[q];
+          if (mode == 1) {
+            Out[o] = ri;
+            d0[q] += bi * bi;
+            d1[q] += ri * ri;
+          } else {
+            d0[q] += ri * ri;
+          }
         }
       }
     }
   }
   const int64_t plane = (int64_t)kBatchBlocks * k;
-  column_partial<KT>(d0, valid, j, k, partials);
-  if (mode == 1) {
-    __syncthreads();
-    column_partial<KT>(d1, valid, j, k, partials + plane);
+#pragma unroll
+  for (int q = 0; q < kCpt; ++q) {
+    if (q) __syncthreads();
+    column_partial<KT>(d0[q], ok[q], jc[q], k, partials);
+    if (mode == 1) {
+      __syncthreads();
+      column_partial<KT>(d1[q], ok[q], jc[q], k, partials + plane);
+    }
   }
 }
 
@@ -422,6 +549,11 @@ BGeom bgeom(int64_t n, int32_t k, int kt) {
   return {dim3((unsigned)bx, (unsigned)((k + kt - 1) / kt)), (int32_t)chunk};
 }
 
+// grid of the column-tiled sparse-product kernels (kCpt columns per thread)
+dim3 tgrid(const BGeom &g, int32_t k, int kt) {
+  return dim3(g.grid.x, (unsigned)((k + kt * kCpt - 1) / (kt * kCpt)));
+}
+
 dim3 egrid(int64_t n, int32_t k, int kt) {  // one thread per element
   const int64_t rpb = kBlock / kt;
   return dim3((unsigned)((n + rpb - 1) / rpb), (unsigned)((k + kt - 1) / kt));
@@ -478,42 +610,90 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
     }
     return;
   }
+  // Down: the first pre-sweep from zero with the residual through A M^-1,
+  // further sweeps alternating z and y, then the residual of the last one;
+  // restriction of the residual t. zc[l] is the buffer holding z_l.
+  const int32_t pre = h->params.pre, post = h->params.post;
+  std::vector<TV *> zc(L), yout(L + 1);
   for (int32_t l = 0; l < L; ++l) {
     Level &F = h->lv[l];
     const BGeom g = bgeom(F.n, k, KT);
+    TV *z = (TV *)B.z[l], *y = (TV *)B.y[l], *t = (TV *)B.t[l];
     if (l == 0)
-      kb_pre_residual<TV, double, KT><<<g.grid, kBlock, 0, s>>>(
-          F.n, k, g.chunk, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), R0, (TV *)B.z[0],
-          (TV *)B.t[0], stop);
+      kb_pre_residual<TV, double, KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+          F.n, k, g.chunk, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), R0, z, t, stop);
     else
-      kb_pre_residual<TV, TV, KT><<<g.grid, kBlock, 0, s>>>(
-          F.n, k, g.chunk, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), (const TV *)B.r[l],
-          (TV *)B.z[l], (TV *)B.t[l], stop);
+      kb_pre_residual<TV, TV, KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+          F.n, k, g.chunk, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), (const TV *)B.r[l], z,
+          t, stop);
+    for (int32_t sw = 1; sw < pre; ++sw) {
+      if (l == 0)
+        kb_post<TV, double, TV, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, y, nullptr,
+            stop);
+      else
+        kb_post<TV, TV, TV, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), (const TV *)B.r[l], z,
+            y, nullptr, stop);
+      std::swap(z, y);
+    }
+    if (pre > 1) {
+      if (l == 0)
+        kb_resid<TV, double, KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), R0, z, t, stop);
+      else
+        kb_resid<TV, TV, KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), (const TV *)B.r[l], z, t, stop);
+    }
+    zc[l] = z;
     const Level &C = h->lv[l + 1];
-    kb_restrict<TV, KT><<<egrid(C.n, k, KT), kBlock, 0, s>>>(
-        C.n, k, F.seg, ppv<TV>(F), (const TV *)B.t[l], (TV *)B.r[l + 1], stop);
+    kb_restrict<TV, KT><<<egrid(C.n, k, KT), kBlock, 0, s>>>(C.n, k, F.seg, ppv<TV>(F), t,
+                                                            (TV *)B.r[l + 1], stop);
   }
   const int32_t nL = h->C.n;
+  yout[L] = (TV *)B.y[L];
   kb_coarse<TV, TV><<<ceil_div((int64_t)nL * k, kBlock), kBlock, 0, s>>>(
-      nL, k, h->C.Ainv, (const TV *)B.r[L], (TV *)B.y[L], stop);
+      nL, k, h->C.Ainv, (const TV *)B.r[L], yout[L], stop);
+  // Up: prolongation of the coarser level's result into z_l, then the post
+  // sweeps; each writes a buffer of the level other than its input, and
+  // yout[l] records where the last one (l > 0) left y_l.
   for (int32_t l = L - 1; l >= 0; --l) {
     Level &F = h->lv[l];
-    kb_prolong<TV, KT><<<egrid(F.n, k, KT), kBlock, 0, s>>>(
-        F.n, k, F.aggp, ppv<TV>(F), (const TV *)B.y[l + 1], (TV *)B.z[l], stop);
+    kb_prolong<TV, KT><<<egrid(F.n, k, KT), kBlock, 0, s>>>(F.n, k, F.aggp, ppv<TV>(F),
+                                                           yout[l + 1], zc[l], stop);
     const BGeom g = bgeom(F.n, k, KT);
-    if (l > 0) {
-      kb_post<TV, TV, TV, KT, false><<<g.grid, kBlock, 0, s>>>(
-          F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), (const TV *)B.r[l],
-          (const TV *)B.z[l], (TV *)B.y[l], nullptr, stop);
-    } else if (rz_op >= 0) {
-      kb_post<TV, double, double, KT, true><<<g.grid, kBlock, 0, s>>>(
-          F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, (const TV *)B.z[0],
-          Z0, B.partials, stop);
-      bfinalize(h, rz_op, (int32_t)g.grid.x, maxit, stop);
-    } else {
-      kb_post<TV, double, double, KT, false><<<g.grid, kBlock, 0, s>>>(
-          F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, (const TV *)B.z[0],
-          Z0, nullptr, stop);
+    TV *bufs[3] = {(TV *)B.y[l], (TV *)B.z[l], (TV *)B.t[l]};
+    TV *z = zc[l];
+    auto other = [&](const TV *in) {
+      for (TV *b : bufs)
+        if (b != in) return b;
+      return bufs[0];
+    };
+    for (int32_t sw = 0; sw < post; ++sw) {
+      const bool last = sw + 1 == post;
+      if (l > 0) {
+        TV *out = other(z);
+        kb_post<TV, TV, TV, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), (const TV *)B.r[l], z,
+            out, nullptr, stop);
+        z = out;
+        if (last) yout[l] = out;
+      } else if (!last) {
+        TV *out = other(z);
+        kb_post<TV, double, TV, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, out, nullptr,
+            stop);
+        z = out;
+      } else if (rz_op >= 0) {
+        kb_post<TV, double, double, KT, true><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, Z0, B.partials,
+            stop);
+        bfinalize(h, rz_op, (int32_t)g.grid.x, maxit, stop);
+      } else {
+        kb_post<TV, double, double, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, Z0, nullptr,
+            stop);
+      }
     }
   }
 }
@@ -527,7 +707,7 @@ void iteration_b(amg_hierarchy *h, int32_t maxit) {
   const int32_t n = L0.n;
   const int32_t *stop = B.all_done;
   const BGeom g = bgeom(n, k, KT);
-  kb_spmv<KT><<<g.grid, kBlock, 0, s>>>(n, k, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, B.P,
+  kb_spmv<KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(n, k, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, B.P,
                                         nullptr, B.Q, B.partials, 0, stop);
   bfinalize(h, bPq, (int32_t)g.grid.x, maxit, stop);
   kb_update<KT><<<g.grid, kBlock, 0, s>>>(n, k, g.chunk, B.X, B.R, B.P, B.Q, B.col, B.done,
@@ -567,7 +747,7 @@ void launch_spmv_mode(amg_hierarchy *h, const double *Xin, const double *Bv, dou
   Batch &B = *h->batch;
   Level &L0 = h->lv[0];
   const BGeom g = bgeom(L0.n, B.k, KT);
-  kb_spmv<KT><<<g.grid, kBlock, 0, h->stream>>>(L0.n, B.k, g.chunk, L0.S.sptr, L0.S.col,
+  kb_spmv<KT><<<tgrid(g, B.k, KT), kBlock, 0, h->stream>>>(L0.n, B.k, g.chunk, L0.S.sptr, L0.S.col,
                                                 L0.S.v64, Xin, Bv, Out, B.partials, mode,
                                                 nullptr);
   *nparts = (int32_t)g.grid.x;
@@ -668,7 +848,7 @@ float time_post(amg_hierarchy *h) {
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   auto go = [&]() {
-    kb_post<TV, double, double, KT, true><<<g.grid, kBlock, 0, h->stream>>>(
+    kb_post<TV, double, double, KT, true><<<tgrid(g, B.k, KT), kBlock, 0, h->stream>>>(
         L0.n, B.k, g.chunk, L0.S.sptr, L0.S.col, vals<TV>(L0), minv<TV>(L0), B.R,
         (const TV *)B.z[0], B.Z, B.partials, h->zero_flag);
   };

@@ -129,3 +129,27 @@ def test_batch_deterministic():
     _, i2, X2 = _batch(h, B)
     assert [i["iterations"] for i in i1] == [i["iterations"] for i in i2]
     np.testing.assert_array_equal(X1.view(np.uint64), X2.view(np.uint64))
+
+
+@pytest.mark.parametrize("pre,post", [(2, 2), (3, 1), (1, 2)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_extra_sweeps_match_single_and_oracle(orc, pre, post, precision):
+    """The block V-cycle applies the hierarchy's pre/post sweep counts."""
+    from paper_2006_16147_amd import amg
+
+    A = inputs.laplacian7(20)
+    k = 6
+    B = np.random.default_rng(5).uniform(-1, 1, (A.n, k))
+    prec = amg.FP32 if precision == "fp32" else amg.FP64
+    h = setup(A, pre=pre, post=post, precision=prec)
+    st, infos, X = _batch(h, B)
+    assert st == 0 and all(i["converged"] for i in infos)
+    ho = orc.Hierarchy(A)
+    for j in range(k):
+        _, i1, x1 = _single(h, B[:, j])
+        assert abs(i1["iterations"] - infos[j]["iterations"]) <= 1
+        assert np.linalg.norm(X[:, j] - x1) / np.linalg.norm(x1) < (1e-9 if prec == amg.FP64
+                                                                   else 1e-6)
+        if prec == amg.FP64:
+            xo, _ = ho.pcg(B[:, j], rtol=0.0, maxit=infos[j]["iterations"], pre=pre, post=post)
+            assert np.linalg.norm(X[:, j] - xo) / np.linalg.norm(xo) < 1e-8
