@@ -37,13 +37,13 @@ __device__ __forceinline__ void sell_row(const int32_t *sptr, int32_t row, int32
   *w = (sptr[s + 1] - sptr[s]) / kSlice;
 }
 
-// rows [rb, re) of this block; chunk is a multiple of the rows per pass
-__device__ __forceinline__ void block_rows(int32_t n, int32_t chunk, int32_t *rb, int32_t *re) {
-  const int32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t b = (int64_t)lb * chunk;
-  *rb = (int32_t)b;
-  *re = (int32_t)(b + chunk < n ? b + chunk : n);
-}
+// Row groups of kBlock / KT rows are dealt to the blocks in turn, in the
+// XCD-aware block order (group g to logical block g mod gridDim.x). The blocks
+// resident at one time then work on one window of neighbouring rows, so the
+// n x k rows they gather (256 bytes each at k = 32 in FP64) are reused from
+// L2; contiguous chunks per block spread the resident blocks over the whole
+// matrix and fetched the gathered block about three times from memory.
+__device__ __forceinline__ int64_t first_group() { return xcd_block(blockIdx.x, gridDim.x); }
 
 // per-column block partial: threads of one column (same lane % KT) are summed
 template <int KT>
@@ -103,7 +103,7 @@ __device__ __forceinline__ void sell_dot_cols(const int32_t *__restrict__ col,
 
 template <typename TV, typename TR, int KT>
 __global__ void __launch_bounds__(kBlock) kb_pre_residual(
-    int32_t n, int32_t k, int32_t chunk, const int32_t *__restrict__ sptr,
+    int32_t n, int32_t k, const int32_t *__restrict__ sptr,
     const int32_t *__restrict__ col, const TV *__restrict__ val, const TV *__restrict__ minv,
     const TR *__restrict__ R, TV *__restrict__ Z, TV *__restrict__ T,
     const int32_t *__restrict__ stop) {
@@ -117,9 +117,9 @@ __global__ void __launch_bounds__(kBlock) kb_pre_residual(
     jc[q] = j0 + q * KT;
     ok[q] = jc[q] < k;
   }
-  int32_t rb, re;
-  block_rows(n, chunk, &rb, &re);
-  for (int32_t row = rb + threadIdx.x / KT; row < re; row += kBlock / KT) {
+  for (int64_t grp = first_group(); grp * (kBlock / KT) < n; grp += gridDim.x) {
+    const int32_t row = (int32_t)(grp * (kBlock / KT)) + (int32_t)threadIdx.x / KT;
+    if (row >= n) continue;
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
     TV acc[kCpt];  // val holds A M^-1
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(kBlock) kb_pre_residual(
 
 template <typename TV, typename TR, typename TO, int KT, bool DOT>
 __global__ void __launch_bounds__(kBlock) kb_post(
-    int32_t n, int32_t k, int32_t chunk, const int32_t *__restrict__ sptr,
+    int32_t n, int32_t k, const int32_t *__restrict__ sptr,
     const int32_t *__restrict__ col, const TV *__restrict__ val, const TV *__restrict__ minv,
     const TR *__restrict__ R, const TV *__restrict__ Z, TO *__restrict__ Y,
     double *__restrict__ partials, const int32_t *__restrict__ stop) {
@@ -153,13 +153,13 @@ __global__ void __launch_bounds__(kBlock) kb_post(
     jc[q] = j0 + q * KT;
     ok[q] = jc[q] < k;
   }
-  int32_t rb, re;
-  block_rows(n, chunk, &rb, &re);
   double d[kCpt];
 #pragma unroll
   for (int q = 0; q < kCpt; ++q) d[q] = 0.0;
   if (ok[0]) {
-    for (int32_t row = rb + threadIdx.x / KT; row < re; row += kBlock / KT) {
+    for (int64_t grp = first_group(); grp * (kBlock / KT) < n; grp += gridDim.x) {
+      const int32_t row = (int32_t)(grp * (kBlock / KT)) + (int32_t)threadIdx.x / KT;
+      if (row >= n) continue;
       int32_t base, w;
       sell_row(sptr, row, &base, &w);
       TV acc[kCpt];
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(kBlock) kb_post(
 // T = R - A Z (the residual after extra pre-smoothing sweeps)
 template <typename TV, typename TR, int KT>
 __global__ void __launch_bounds__(kBlock) kb_resid(
-    int32_t n, int32_t k, int32_t chunk, const int32_t *__restrict__ sptr,
+    int32_t n, int32_t k, const int32_t *__restrict__ sptr,
     const int32_t *__restrict__ col, const TV *__restrict__ val, const TR *__restrict__ R,
     const TV *__restrict__ Z, TV *__restrict__ T, const int32_t *__restrict__ stop) {
   if (*stop) return;
@@ -203,9 +203,9 @@ __global__ void __launch_bounds__(kBlock) kb_resid(
     jc[q] = j0 + q * KT;
     ok[q] = jc[q] < k;
   }
-  int32_t rb, re;
-  block_rows(n, chunk, &rb, &re);
-  for (int32_t row = rb + threadIdx.x / KT; row < re; row += kBlock / KT) {
+  for (int64_t grp = first_group(); grp * (kBlock / KT) < n; grp += gridDim.x) {
+    const int32_t row = (int32_t)(grp * (kBlock / KT)) + (int32_t)threadIdx.x / KT;
+    if (row >= n) continue;
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
     TV acc[kCpt];
@@ -307,7 +307,7 @@ __global__ void kb_coarse(int32_t nL, int32_t k, const double *__restrict__ Ainv
 
 template <int KT>
 __global__ void __launch_bounds__(kBlock) kb_spmv(
-    int32_t n, int32_t k, int32_t chunk, const int32_t *__restrict__ sptr,
+    int32_t n, int32_t k, const int32_t *__restrict__ sptr,
     const int32_t *__restrict__ col, const double *__restrict__ val,
     const double *__restrict__ Xin, const double *__restrict__ B, double *__restrict__ Out,
     double *__restrict__ partials, int32_t mode, const int32_t *__restrict__ stop) {
@@ -323,13 +323,13 @@ __global__ void __launch_bounds__(kBlock) kb_spmv(
     jc[q] = j0 + q * KT;
     ok[q] = jc[q] < k;
   }
-  int32_t rb, re;
-  block_rows(n, chunk, &rb, &re);
   double d0[kCpt], d1[kCpt];
 #pragma unroll
   for (int q = 0; q < kCpt; ++q) d0[q] = d1[q] = 0.0;
   if (ok[0]) {
-    for (int32_t row = rb + threadIdx.x / KT; row < re; row += kBlock / KT) {
+    for (int64_t grp = first_group(); grp * (kBlock / KT) < n; grp += gridDim.x) {
+      const int32_t row = (int32_t)(grp * (kBlock / KT)) + (int32_t)threadIdx.x / KT;
+      if (row >= n) continue;
       int32_t base, w;
       sell_row(sptr, row, &base, &w);
       double acc[kCpt];
@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(kBlock) kb_spmv(
 // per-column partials of (U, V) (a level-0 coarsest solve has no smoother
 // to fuse the CG dot product into)
 template <int KT>
-__global__ void __launch_bounds__(kBlock) kb_dot(int32_t n, int32_t k, int32_t chunk,
+__global__ void __launch_bounds__(kBlock) kb_dot(int32_t n, int32_t k,
                                                  const double *__restrict__ U,
                                                  const double *__restrict__ V,
                                                  double *__restrict__ partials,
@@ -379,17 +379,17 @@ __global__ void __launch_bounds__(kBlock) kb_dot(int32_t n, int32_t k, int32_t c
   if (*stop) return;
   const int32_t j = blockIdx.y * KT + threadIdx.x % KT;
   const bool valid = j < k;
-  int32_t rb, re;
-  block_rows(n, chunk, &rb, &re);
   double d = 0.0;
   if (valid)
-    for (int32_t row = rb + threadIdx.x / KT; row < re; row += kBlock / KT)
-      d += U[(int64_t)row * k + j] * V[(int64_t)row * k + j];
+    for (int64_t grp = first_group(); grp * (kBlock / KT) < n; grp += gridDim.x) {
+      const int32_t row = (int32_t)(grp * (kBlock / KT)) + (int32_t)threadIdx.x / KT;
+      if (row < n) d += U[(int64_t)row * k + j] * V[(int64_t)row * k + j];
+    }
   column_partial<KT>(d, valid, j, k, partials);
 }
 
 template <int KT>
-__global__ void __launch_bounds__(kBlock) kb_update(int32_t n, int32_t k, int32_t chunk,
+__global__ void __launch_bounds__(kBlock) kb_update(int32_t n, int32_t k,
                                                     double *__restrict__ X,
                                                     double *__restrict__ R,
                                                     const double *__restrict__ P,
@@ -403,11 +403,11 @@ __global__ void __launch_bounds__(kBlock) kb_update(int32_t n, int32_t k, int32_
   const bool valid = j < k;
   const bool live = valid && done[j] == 0;
   const double alpha = valid ? colv[cAlpha * k + j] : 0.0;
-  int32_t rb, re;
-  block_rows(n, chunk, &rb, &re);
   double d = 0.0;
   if (live) {
-    for (int32_t row = rb + threadIdx.x / KT; row < re; row += kBlock / KT) {
+    for (int64_t grp = first_group(); grp * (kBlock / KT) < n; grp += gridDim.x) {
+      const int32_t row = (int32_t)(grp * (kBlock / KT)) + (int32_t)threadIdx.x / KT;
+      if (row >= n) continue;
       const int64_t o = (int64_t)row * k + j;
       X[o] += alpha * P[o];
       const double ri = R[o] - alpha * Q[o];
@@ -534,19 +534,16 @@ __global__ void kb_all_done(int32_t k, const int32_t *done, int32_t *stop) {
 
 struct BGeom {
   dim3 grid;
-  int32_t chunk;
 };
 
-// streaming geometry: at most kBatchBlocks x-blocks, each a contiguous chunk
+// streaming geometry: one x-block per row group of kBlock / kt rows, at most
+// kBatchBlocks (the blocks then take further groups in turn)
 BGeom bgeom(int64_t n, int32_t k, int kt) {
-  const int64_t rpp = kBlock / kt;  // rows per block pass
-  int64_t passes = (n + rpp - 1) / rpp;
-  int64_t bx = passes < kBatchBlocks ? passes : kBatchBlocks;
+  const int64_t rpp = kBlock / kt;  // rows per group
+  int64_t groups = (n + rpp - 1) / rpp;
+  int64_t bx = groups < kBatchBlocks ? groups : kBatchBlocks;
   if (bx < 1) bx = 1;
-  int64_t chunk = ((n + bx - 1) / bx + rpp - 1) / rpp * rpp;
-  bx = (n + chunk - 1) / chunk;
-  if (bx < 1) bx = 1;
-  return {dim3((unsigned)bx, (unsigned)((k + kt - 1) / kt)), (int32_t)chunk};
+  return {dim3((unsigned)bx, (unsigned)((k + kt - 1) / kt))};
 }
 
 // grid of the column-tiled sparse-product kernels (kCpt columns per thread)
@@ -605,7 +602,7 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
         nL, k, h->C.Ainv, R0, Z0, stop);
     if (rz_op >= 0) {
       const BGeom g = bgeom(nL, k, KT);
-      kb_dot<KT><<<g.grid, kBlock, 0, s>>>(nL, k, g.chunk, R0, Z0, B.partials, stop);
+      kb_dot<KT><<<g.grid, kBlock, 0, s>>>(nL, k, R0, Z0, B.partials, stop);
       bfinalize(h, rz_op, (int32_t)g.grid.x, maxit, stop);
     }
     return;
@@ -621,29 +618,29 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
     TV *z = (TV *)B.z[l], *y = (TV *)B.y[l], *t = (TV *)B.t[l];
     if (l == 0)
       kb_pre_residual<TV, double, KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(
-          F.n, k, g.chunk, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), R0, z, t, stop);
+          F.n, k, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), R0, z, t, stop);
     else
       kb_pre_residual<TV, TV, KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(
-          F.n, k, g.chunk, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), (const TV *)B.r[l], z,
+          F.n, k, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), (const TV *)B.r[l], z,
           t, stop);
     for (int32_t sw = 1; sw < pre; ++sw) {
       if (l == 0)
         kb_post<TV, double, TV, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
-            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, y, nullptr,
+            F.n, k, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, y, nullptr,
             stop);
       else
         kb_post<TV, TV, TV, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
-            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), (const TV *)B.r[l], z,
+            F.n, k, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), (const TV *)B.r[l], z,
             y, nullptr, stop);
       std::swap(z, y);
     }
     if (pre > 1) {
       if (l == 0)
         kb_resid<TV, double, KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(
-            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), R0, z, t, stop);
+            F.n, k, F.S.sptr, F.S.col, vals<TV>(F), R0, z, t, stop);
       else
         kb_resid<TV, TV, KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(
-            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), (const TV *)B.r[l], z, t, stop);
+            F.n, k, F.S.sptr, F.S.col, vals<TV>(F), (const TV *)B.r[l], z, t, stop);
     }
     zc[l] = z;
     const Level &C = h->lv[l + 1];
@@ -674,24 +671,24 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
       if (l > 0) {
         TV *out = other(z);
         kb_post<TV, TV, TV, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
-            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), (const TV *)B.r[l], z,
+            F.n, k, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), (const TV *)B.r[l], z,
             out, nullptr, stop);
         z = out;
         if (last) yout[l] = out;
       } else if (!last) {
         TV *out = other(z);
         kb_post<TV, double, TV, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
-            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, out, nullptr,
+            F.n, k, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, out, nullptr,
             stop);
         z = out;
       } else if (rz_op >= 0) {
         kb_post<TV, double, double, KT, true><<<tgrid(g, k, KT), kBlock, 0, s>>>(
-            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, Z0, B.partials,
+            F.n, k, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, Z0, B.partials,
             stop);
         bfinalize(h, rz_op, (int32_t)g.grid.x, maxit, stop);
       } else {
         kb_post<TV, double, double, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
-            F.n, k, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, Z0, nullptr,
+            F.n, k, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, Z0, nullptr,
             stop);
       }
     }
@@ -707,10 +704,10 @@ void iteration_b(amg_hierarchy *h, int32_t maxit) {
   const int32_t n = L0.n;
   const int32_t *stop = B.all_done;
   const BGeom g = bgeom(n, k, KT);
-  kb_spmv<KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(n, k, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, B.P,
+  kb_spmv<KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(n, k, L0.S.sptr, L0.S.col, L0.S.v64, B.P,
                                         nullptr, B.Q, B.partials, 0, stop);
   bfinalize(h, bPq, (int32_t)g.grid.x, maxit, stop);
-  kb_update<KT><<<g.grid, kBlock, 0, s>>>(n, k, g.chunk, B.X, B.R, B.P, B.Q, B.col, B.done,
+  kb_update<KT><<<g.grid, kBlock, 0, s>>>(n, k, B.X, B.R, B.P, B.Q, B.col, B.done,
                                           B.partials, stop);
   bfinalize(h, bRr, (int32_t)g.grid.x, maxit, stop);
   kb_all_done<<<1, 64, 0, s>>>(k, B.done, B.all_done);
@@ -747,7 +744,7 @@ void launch_spmv_mode(amg_hierarchy *h, const double *Xin, const double *Bv, dou
   Batch &B = *h->batch;
   Level &L0 = h->lv[0];
   const BGeom g = bgeom(L0.n, B.k, KT);
-  kb_spmv<KT><<<tgrid(g, B.k, KT), kBlock, 0, h->stream>>>(L0.n, B.k, g.chunk, L0.S.sptr, L0.S.col,
+  kb_spmv<KT><<<tgrid(g, B.k, KT), kBlock, 0, h->stream>>>(L0.n, B.k, L0.S.sptr, L0.S.col,
                                                 L0.S.v64, Xin, Bv, Out, B.partials, mode,
                                                 nullptr);
   *nparts = (int32_t)g.grid.x;
@@ -849,7 +846,7 @@ float time_post(amg_hierarchy *h) {
   (void)hipEventCreate(&e1);
   auto go = [&]() {
     kb_post<TV, double, double, KT, true><<<tgrid(g, B.k, KT), kBlock, 0, h->stream>>>(
-        L0.n, B.k, g.chunk, L0.S.sptr, L0.S.col, vals<TV>(L0), minv<TV>(L0), B.R,
+        L0.n, B.k, L0.S.sptr, L0.S.col, vals<TV>(L0), minv<TV>(L0), B.R,
         (const TV *)B.z[0], B.Z, B.partials, h->zero_flag);
   };
   go();
