@@ -103,3 +103,29 @@ def test_aniso_256_fp32_vs_fp64():
     assert st == 0 and st32 == 0
     assert i64["rel_res_true"] <= 1.001e-8 and i32["rel_res_true"] <= 1.01e-8
     assert np.linalg.norm(x32 - x64) / np.linalg.norm(x64) < 1e-4
+
+
+def test_batch_128_k32_sampled_against_oracle(orc):
+    """Multi-RHS at its full size and launch configuration (128^3, k = 32,
+    FP32 hierarchy, autotuned tile): every column reaches the FP64 true
+    residual, and two sampled columns match the oracle's FP64 solve."""
+    import torch
+
+    from paper_2006_16147_amd import amg
+
+    c = inputs.multi_rhs_case(128, 32, seed=3)
+    A, B = c["A"], c["B"]
+    h = setup(A, precision=amg.FP32)
+    Bd = torch.from_numpy(B).cuda()
+    X = torch.zeros_like(Bd)
+    st, infos = amg.amg_pcg_solve_batch(h, Bd, X, rtol=1e-8, maxit=200)
+    assert st == 0
+    assert all(i["converged"] and i["rel_res_true"] <= 1.01e-8 for i in infos)
+    Xh = X.cpu().numpy()
+    ho = orc.Hierarchy(A)
+    for j in (0, 31):
+        xo, io = ho.pcg(B[:, j], rtol=1e-8, maxit=200)
+        assert abs(io["iterations"] - infos[j]["iterations"]) <= 2
+        # both solutions within the conditioning bound of the exact one
+        assert np.linalg.norm(Xh[:, j] - xo) / np.linalg.norm(xo) < 1e-8 * 1.2e4
+    h.close()
