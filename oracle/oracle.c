@@ -582,10 +582,19 @@ void orc_coarse_factor(const orc_hier *h, double *L) {
   memcpy(L, h->L, sizeof(double) * (size_t)h->nL * (size_t)h->nL);
 }
 
-/* eq. (amg): pre-smoothing M^-1 from a zero guess, coarse correction,
- * post-smoothing M^-T = M^-1 (M diagonal). */
-void orc_vcycle(const orc_hier *h, int32_t l, int32_t pre, int32_t post,
-                const double *r, double *z) {
+static void fcg2(const orc_hier *h, int32_t m, int32_t pre, int32_t post, const double *b,
+                 double *x);
+
+/* One application of the multilevel preconditioner on level l.
+ * eq. (amg): pre-smoothing M^-1 from a zero guess, coarse correction,
+ * post-smoothing M^-T = M^-1 (M diagonal). The coarse correction solves
+ * A_{l+1} e = P^T t: exactly on the coarsest level; else by the same cycle
+ * on level l + 1 (V-cycle, kcycle = 0), or by two iterations of flexible CG
+ * on level l + 1 preconditioned by the cycle starting there (K-cycle,
+ * kcycle = 1; Section 3.1, which applies those FCG iterations on every
+ * level but the finest and the coarsest). */
+static void cycle(const orc_hier *h, int32_t l, int32_t pre, int32_t post, int kcycle,
+                  const double *r, double *z) {
   int32_t L = h->nlev - 1;
   if (l == L) {
     orc_cholesky_solve(h->nL, h->L, r, z);
@@ -603,11 +612,12 @@ void orc_vcycle(const orc_hier *h, int32_t l, int32_t pre, int32_t post,
     orc_spmv(A, z, t);
     for (int32_t i = 0; i < n; ++i) z[i] = z[i] + (r[i] - t[i]) / m[i];
   }
-  /* residual, restriction, coarse solve, prolongation */
+  /* residual, restriction, coarse correction, prolongation */
   orc_spmv(A, z, t);
   for (int32_t i = 0; i < n; ++i) t[i] = r[i] - t[i];
   orc_restrict(n, nc, h->agg[l], h->p[l], t, rc);
-  orc_vcycle(h, l + 1, pre, post, rc, zc);
+  if (kcycle && l + 1 < L) fcg2(h, l + 1, pre, post, rc, zc);
+  else cycle(h, l + 1, pre, post, kcycle, rc, zc);
   for (int32_t i = 0; i < n; ++i) z[i] = z[i] + h->p[l][i] * zc[h->agg[l][i]];
   /* post-smoothing */
   for (int32_t s = 0; s < post; ++s) {
@@ -617,6 +627,68 @@ void orc_vcycle(const orc_hier *h, int32_t l, int32_t pre, int32_t post,
   free(t);
   free(rc);
   free(zc);
+}
+
+/* Two iterations of flexible CG on A_m x = b from x = 0, preconditioned by
+ * the K-cycle on level m ([NV2008] as cited in Section 3.1). Each direction
+ * is made A-orthogonal to the previous one (FCG with truncation 1):
+ *   c1 = K(b), v1 = A c1, rho1 = (c1, v1), s1 = (c1, b) / rho1,
+ *   r1 = b - s1 v1,
+ *   c2 = K(r1), v2 = A c2, gamma = (c2, v1),
+ *   d2 = c2 - (gamma / rho1) c1, rho2 = (d2, A d2) = (c2, v2) - gamma^2 / rho1,
+ *   s2 = (d2, r1) / rho2 = (c2, r1) / rho2   ((c1, r1) = 0),
+ *   x = s1 c1 + s2 d2 = (s1 - s2 gamma / rho1) c1 + s2 c2.
+ * A zero rho1 (b = 0) gives x = 0; a non-positive rho2 stops after the first
+ * iteration. */
+static void fcg2(const orc_hier *h, int32_t m, int32_t pre, int32_t post, const double *b,
+                 double *x) {
+  const orc_csr *A = &h->A[m];
+  int32_t n = A->n;
+  double *c1 = (double *)malloc(sizeof(double) * (size_t)n);
+  double *v1 = (double *)malloc(sizeof(double) * (size_t)n);
+  double *r1 = (double *)malloc(sizeof(double) * (size_t)n);
+  double *c2 = (double *)malloc(sizeof(double) * (size_t)n);
+  double *v2 = (double *)malloc(sizeof(double) * (size_t)n);
+  cycle(h, m, pre, post, 1, b, c1);
+  orc_spmv(A, c1, v1);
+  double rho1 = dot(n, c1, v1);
+  if (!(rho1 > 0.0)) {
+    for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+  } else {
+    double s1 = dot(n, c1, b) / rho1;
+    for (int32_t i = 0; i < n; ++i) r1[i] = b[i] - s1 * v1[i];
+    cycle(h, m, pre, post, 1, r1, c2);
+    orc_spmv(A, c2, v2);
+    double gamma = dot(n, c2, v1);
+    double rho2 = dot(n, c2, v2) - gamma * gamma / rho1;
+    if (!(rho2 > 0.0)) {
+      for (int32_t i = 0; i < n; ++i) x[i] = s1 * c1[i];
+    } else {
+      double s2 = dot(n, c2, r1) / rho2;
+      double a1 = s1 - s2 * (gamma / rho1);
+      for (int32_t i = 0; i < n; ++i) x[i] = a1 * c1[i] + s2 * c2[i];
+    }
+  }
+  free(c1);
+  free(v1);
+  free(r1);
+  free(c2);
+  free(v2);
+}
+
+void orc_vcycle(const orc_hier *h, int32_t l, int32_t pre, int32_t post,
+                const double *r, double *z) {
+  cycle(h, l, pre, post, 0, r, z);
+}
+
+void orc_kcycle(const orc_hier *h, int32_t l, int32_t pre, int32_t post,
+                const double *r, double *z) {
+  cycle(h, l, pre, post, 1, r, z);
+}
+
+void orc_fcg2(const orc_hier *h, int32_t m, int32_t pre, int32_t post, const double *b,
+              double *x) {
+  fcg2(h, m, pre, post, b, x);
 }
 
 int orc_pcg(const orc_hier *h, int32_t pre, int32_t post, const double *b,
@@ -667,6 +739,78 @@ int orc_pcg(const orc_hier *h, int32_t pre, int32_t post, const double *b,
     double rz = dot(n, r, z);
     double beta = rz / rho;
     rho = rz;
+    for (int32_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+  }
+  if (it > maxit) it = maxit;
+done:
+  out[0] = (double)it;
+  out[1] = st == ORC_OK ? 1.0 : 0.0;
+  out[2] = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+  if (bnorm > 0.0) {
+    orc_spmv(A, x, q);
+    for (int32_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+    out[3] = sqrt(dot(n, r, r)) / bnorm;
+  } else {
+    out[3] = 0.0;
+  }
+  free(r);
+  free(z);
+  free(p);
+  free(q);
+  return st;
+}
+
+/* Flexible CG (Section 5 uses FCG as the outer solver) with truncation 1:
+ * p_k = z_k - ((z_k, A p_{k-1}) / (p_{k-1}, A p_{k-1})) p_{k-1},
+ * alpha_k = (p_k, r_k) / (p_k, A p_k); same start, stop test and outputs as
+ * orc_pcg. With a fixed s.p.d. preconditioner it coincides with PCG in exact
+ * arithmetic; it is the outer solver of the K-cycle, which is not a fixed
+ * linear operator. kcycle selects the preconditioner (0: V-cycle). */
+int orc_fcg(const orc_hier *h, int32_t kcycle, int32_t pre, int32_t post, const double *b,
+            double *x, double rtol, int32_t maxit, double *out) {
+  const orc_csr *A = &h->A[0];
+  int32_t n = A->n;
+  double *r = (double *)malloc(sizeof(double) * (size_t)n);
+  double *z = (double *)malloc(sizeof(double) * (size_t)n);
+  double *p = (double *)malloc(sizeof(double) * (size_t)n);
+  double *q = (double *)malloc(sizeof(double) * (size_t)n);
+  int st = ORC_NOT_CONVERGED;
+  int32_t it = 0;
+  double bnorm = sqrt(dot(n, b, b));
+  double rnorm = 0.0;
+  if (bnorm == 0.0) {
+    for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+    st = ORC_OK;
+    goto done;
+  }
+  orc_spmv(A, x, q);
+  for (int32_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+  rnorm = sqrt(dot(n, r, r));
+  if (rnorm <= rtol * bnorm) {
+    st = ORC_OK;
+    goto done;
+  }
+  cycle(h, 0, pre, post, kcycle, r, z);
+  for (int32_t i = 0; i < n; ++i) p[i] = z[i];
+  for (it = 1; it <= maxit; ++it) {
+    orc_spmv(A, p, q);
+    double pq = dot(n, p, q);
+    if (!(pq > 0.0)) {
+      st = ORC_ERR_BREAKDOWN;
+      --it;
+      break;
+    }
+    double alpha = dot(n, p, r) / pq;
+    for (int32_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+    for (int32_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+    rnorm = sqrt(dot(n, r, r));
+    if (rnorm <= rtol * bnorm) {
+      st = ORC_OK;
+      break;
+    }
+    if (it == maxit) break;
+    cycle(h, 0, pre, post, kcycle, r, z);
+    double beta = -dot(n, z, q) / pq;
     for (int32_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
   }
   if (it > maxit) it = maxit;

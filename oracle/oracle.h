@@ -146,6 +146,18 @@ void orc_vcycle(const orc_hier *h, int32_t l, int32_t pre, int32_t post,
  * relative residual, out[3] = true relative residual ||b - A x|| / ||b||. */
 int orc_pcg(const orc_hier *h, int32_t pre, int32_t post, const double *b,
             double *x, double rtol, int32_t maxit, double *out);
+/* K-cycle on level l (Section 3.1): as orc_vcycle, with the coarse
+ * correction on every level other than the finest and the coarsest given by
+ * two flexible-CG iterations preconditioned by the K-cycle on that level. */
+void orc_kcycle(const orc_hier *h, int32_t l, int32_t pre, int32_t post,
+                const double *r, double *z);
+/* The two flexible-CG iterations of the K-cycle on level m, from x = 0. */
+void orc_fcg2(const orc_hier *h, int32_t m, int32_t pre, int32_t post, const double *b,
+              double *x);
+/* Flexible CG (truncation 1) with the V-cycle (kcycle = 0) or K-cycle (1)
+ * as preconditioner; arguments and outputs as orc_pcg. */
+int orc_fcg(const orc_hier *h, int32_t kcycle, int32_t pre, int32_t post, const double *b,
+            double *x, double rtol, int32_t maxit, double *out);
 
 #ifdef __cplusplus
 }

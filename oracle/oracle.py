@@ -108,6 +108,10 @@ def load():
         "orc_level_sweeps": (C.c_int32, [C.c_void_p, C.c_int32]),
         "orc_coarse_factor": (None, [C.c_void_p, _F64P]),
         "orc_vcycle": (None, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _F64P, _F64P]),
+        "orc_kcycle": (None, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _F64P, _F64P]),
+        "orc_fcg2": (None, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _F64P, _F64P]),
+        "orc_fcg": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _F64P, _F64P,
+                              C.c_double, C.c_int32, _F64P]),
         "orc_pcg": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _F64P, _F64P, C.c_double,
                               C.c_int32, _F64P]),
     }
@@ -317,6 +321,28 @@ class Hierarchy:
         z = np.empty(self.level_n(l))
         self._lib.orc_vcycle(self._h, l, pre, post, _f64(r), z)
         return z
+
+    def kcycle(self, r, l=0, pre=1, post=1):
+        """K-cycle on level l (Section 3.1)."""
+        z = np.empty(self.level_n(l))
+        self._lib.orc_kcycle(self._h, l, pre, post, _f64(r), z)
+        return z
+
+    def fcg2(self, b, m, pre=1, post=1):
+        """The K-cycle's two flexible-CG iterations on level m, from zero."""
+        x = np.empty(self.level_n(m))
+        self._lib.orc_fcg2(self._h, m, pre, post, _f64(b), x)
+        return x
+
+    def fcg(self, b, x0=None, rtol=1e-6, maxit=500, pre=1, post=1, cycle="K"):
+        """Flexible CG with the K-cycle (cycle="K") or V-cycle ("V")."""
+        n = self.level_n(0)
+        x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        out = np.zeros(4)
+        st = self._lib.orc_fcg(self._h, 1 if cycle == "K" else 0, pre, post, _f64(b), x, rtol,
+                               maxit, out)
+        return x, {"status": int(st), "iterations": int(out[0]), "converged": bool(out[1]),
+                   "rel_res": float(out[2]), "rel_res_true": float(out[3])}
 
     def pcg(self, b, x0=None, rtol=1e-6, maxit=500, pre=1, post=1):
         n = self.level_n(0)

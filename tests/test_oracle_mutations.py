@@ -19,6 +19,7 @@ SRC = os.path.join(ROOT, "oracle", "oracle.c")
 
 INV = "tests/test_oracle_invariants.py::"
 PIN = "tests/test_oracle_paper_pins.py::"
+KC = "tests/test_oracle_kcycle.py::"
 
 # (mistake, text in oracle.c, replacement, pin test that must reject it)
 MUTATIONS = [
@@ -86,6 +87,23 @@ MUTATIONS = [
     ("numbering: partner of a pair left unnumbered",
      "if (mate[v] >= 0) agg[mate[v]] = next;", "if (mate[v] >= 0 && 0) agg[mate[v]] = next;",
      PIN + "test_table1_gauss_seidel"),
+    ("K-cycle FCG: sign of the orthogonalisation term in rho2",
+     "double rho2 = dot(n, c2, v2) - gamma * gamma / rho1;",
+     "double rho2 = dot(n, c2, v2) + gamma * gamma / rho1;",
+     KC + "test_fcg2_is_the_galerkin_projection"),
+    ("K-cycle FCG: sign of the correction of the first coefficient",
+     "double a1 = s1 - s2 * (gamma / rho1);", "double a1 = s1 + s2 * (gamma / rho1);",
+     KC + "test_fcg2_is_the_galerkin_projection"),
+    ("K-cycle FCG: second step length from b instead of r1",
+     "double s2 = dot(n, c2, r1) / rho2;", "double s2 = dot(n, c2, b) / rho2;",
+     KC + "test_fcg2_is_the_galerkin_projection"),
+    ("outer FCG: sign of beta",
+     "double beta = -dot(n, z, q) / pq;", "double beta = dot(n, z, q) / pq;",
+     KC + "test_fcg_with_vcycle_equals_pcg"),
+    ("K-cycle: coarse correction by the plain cycle (no FCG)",
+     "if (kcycle && l + 1 < L) fcg2(h, l + 1, pre, post, rc, zc);",
+     "if (0 && kcycle && l + 1 < L) fcg2(h, l + 1, pre, post, rc, zc);",
+     KC + "test_kcycle_iterations_do_not_grow_with_the_grid"),
 ]
 
 
