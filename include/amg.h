@@ -64,6 +64,15 @@ typedef enum {
 /* precision of the stored hierarchy and of the V-cycle arithmetic */
 enum { AMG_FP64 = 0, AMG_FP32 = 1 };
 
+/* amg_params.cycle: the multilevel preconditioner.
+ * AMG_CYCLE_V: the V-cycle of eq. (amg), used inside CG.
+ * AMG_CYCLE_K: the K-cycle of Section 3.1: on every level strictly between
+ *   the finest and the coarsest, the coarse correction is two iterations of
+ *   flexible CG (truncation 1) preconditioned by the K-cycle starting on that
+ *   level; the outer solver is then flexible CG (Section 5), since the
+ *   K-cycle is not a fixed linear operator. */
+enum { AMG_CYCLE_V = 0, AMG_CYCLE_K = 1 };
+
 /* amg_params.flags */
 enum {
   AMG_FLAG_NO_GRAPH = 1,   /* launch the solve kernels directly, no hipGraph */
@@ -93,6 +102,7 @@ typedef struct {
   void *stream;       /* hipStream_t for every call on this hierarchy; NULL = the
                          device's default stream */
   int32_t flags;      /* AMG_FLAG_* */
+  int32_t cycle;      /* AMG_CYCLE_V or AMG_CYCLE_K; AMG_CYCLE_V */
 } amg_params;
 
 typedef struct {
@@ -116,7 +126,9 @@ void amg_params_default(amg_params *p);
  * AMG_ERR_HIP. On error *out is NULL. */
 amg_status amg_setup(const amg_csr *A, const amg_params *params, amg_hierarchy **out);
 
-/* Preconditioned CG on A x = b with the V-cycle as preconditioner.
+/* Preconditioned CG on A x = b with the V-cycle as preconditioner (Section
+ * 5), or, for a hierarchy built with AMG_CYCLE_K, flexible CG (truncation 1:
+ * each direction A-orthogonal to the previous) with the K-cycle.
  * b: device, n (read). x: device, n (in: initial guess, out: iterate).
  * Stops when ||r_k||_2 <= rtol ||b||_2 or after maxit iterations; b = 0 gives
  * x = 0 after 0 iterations. rtol = 0 runs exactly maxit iterations.
@@ -130,11 +142,13 @@ amg_status amg_pcg_solve(amg_hierarchy *h, const double *b, double *x, double rt
  * with its own CG recurrence (own alpha, beta, stop test); the V-cycle runs
  * once per iteration on the whole block. info: host array of k, may be NULL.
  * Returns AMG_OK if every column converged, else AMG_NOT_CONVERGED, or an
- * error. k = 0 is a no-op. */
+ * error; AMG_ERR_ARG for a hierarchy built with AMG_CYCLE_K (the block solve
+ * runs the V-cycle only). k = 0 is a no-op. */
 amg_status amg_pcg_solve_batch(amg_hierarchy *h, int32_t k, const double *B, double *X,
                                double rtol, int32_t maxit, amg_solve_info *info);
 
-/* One application of the preconditioner, z = B_0 r (eq. (amg)).
+/* One application of the hierarchy's preconditioner, z = B_0 r: the V-cycle
+ * of eq. (amg), or the K-cycle for a hierarchy built with AMG_CYCLE_K.
  * r, z: device, n. */
 amg_status amg_vcycle_apply(amg_hierarchy *h, const double *r, double *z);
 

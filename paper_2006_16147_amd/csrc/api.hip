@@ -124,6 +124,7 @@ amg_status check_params(const amg_params *p) {
   if (p->max_levels < 1 || p->max_levels > 64) return AMG_ERR_ARG;
   if (p->pre < 1 || p->pre > 8 || p->post < 1 || p->post > 8) return AMG_ERR_ARG;
   if (p->precision != AMG_FP64 && p->precision != AMG_FP32) return AMG_ERR_ARG;
+  if (p->cycle != AMG_CYCLE_V && p->cycle != AMG_CYCLE_K) return AMG_ERR_ARG;
   return AMG_OK;
 }
 
@@ -152,6 +153,7 @@ void amg_params_default(amg_params *p) {
   p->w = nullptr;
   p->stream = nullptr;
   p->flags = 0;
+  p->cycle = AMG_CYCLE_V;
 }
 
 amg_status amg_setup(const amg_csr *A, const amg_params *params, amg_hierarchy **out) {
@@ -211,6 +213,7 @@ amg_status amg_pcg_solve(amg_hierarchy *h, const double *b, double *x, double rt
 amg_status amg_pcg_solve_batch(amg_hierarchy *h, int32_t k, const double *B, double *X,
                                double rtol, int32_t maxit, amg_solve_info *info) {
   if (!h || k < 0 || !(rtol >= 0.0) || maxit < 0) return AMG_ERR_ARG;
+  if (h->params.cycle != AMG_CYCLE_V) return AMG_ERR_ARG;
   if (k == 0) return AMG_OK;
   if (!B || !X) return AMG_ERR_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return AMG_ERR_HIP;
@@ -311,7 +314,8 @@ size_t amg_estimate_footprint(int64_t n, int64_t nnz, const amg_params *params) 
   b += pad * (4 + 2 * 8 + 2 * X);               // SELL: columns, A, A M^-1 (+ FP32 copies)
   b += 4 * V * sn;                              // V-cycle vectors
   b += 6 * 8.0 * n;                             // CG vectors (x, r, z, p, q, b)
-  b += 2 * 65536 * 8.0;                         // block partials
+  b += 3 * 65536 * 8.0;                         // block partials
+  if (P.cycle == AMG_CYCLE_K) b += 5 * V * (sn - n);  // K-cycle FCG vectors
   // peak of the setup temporaries (weights, Galerkin staging, sweep matrices)
   b += 8.0 * nnz + 12.0 * nnz + 2 * (12.0 * nnz + 16.0 * n);
   const double nL = P.max_coarse;

@@ -32,7 +32,10 @@ namespace amg {
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kSlice = 64;       // rows per SELL slice (one wavefront)
 constexpr int kBlock = 256;      // threads per block of the streaming kernels
-constexpr int kMaxParts = 65536;   // most blocks of a reducing kernel (partials buffer)
+constexpr int kMaxParts = 65536;
+constexpr int kPartPlanes = 3;  // partial-sum planes (dot products per reduction)
+// K-cycle scalars of one level's two flexible-CG iterations
+enum KScal : int32_t { kRho1 = 0, kS1, kGamma, kRho2, kS2, kA1, kKScal = 8 };   // most blocks of a reducing kernel (partials buffer)
 constexpr int kNumXcd = 8;       // MI355X: 8 XCDs, blocks dispatched round-robin
 
 // Solve-phase PCG scalars, resident on the device.
@@ -98,6 +101,10 @@ struct Level {
   float *pp32 = nullptr;
   // V-cycle work vectors in the hierarchy precision
   void *r = nullptr, *z = nullptr, *t = nullptr, *y = nullptr;
+  // K-cycle flexible-CG vectors (levels strictly between the finest and the
+  // coarsest): preconditioned residuals c1, c2, their products v1 = A c1,
+  // v2 = A c2, and the second residual r1
+  void *c1 = nullptr, *v1 = nullptr, *r1 = nullptr, *c2 = nullptr, *v2 = nullptr;
   int32_t sweeps = 0;
   int32_t rounds = 0;
 };
@@ -143,7 +150,8 @@ struct amg_hierarchy {
   // CG vectors, in the aggregate-major order of level 0
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *b = nullptr;
   int32_t max_seg = 1;            // largest aggregate (segment) of any level
-  double *partials = nullptr;     // 2 x kMaxParts block partial sums
+  double *partials = nullptr;     // kPartPlanes x kMaxParts block partial sums
+  double *kscal = nullptr;  // K-cycle scalars, kKScal per level
   amg::PcgScal *scal = nullptr;   // device
   amg::PcgScal *scal_host = nullptr;  // pinned mirror
   int32_t *zero_flag = nullptr;   // device int 0 (for kernels outside CG)

@@ -131,7 +131,15 @@ __device__ void block_partial(double (&v)[NV], double *partials) {
   }
 }
 
-enum FinOp : int32_t { kFinInit = 0, kFinPQ = 1, kFinRR = 2, kFinRZ = 3, kFinTrue = 4 };
+enum FinOp : int32_t {
+  kFinInit = 0,  // (b, b), (r, r) of the initial residual
+  kFinPQ = 1,    // CG: (p, q), alpha = rho / (p, q)
+  kFinRR = 2,    // (r, r), stop test
+  kFinRZ = 3,    // CG: (r, z), beta
+  kFinTrue = 4,  // true residual
+  kFinPQR = 5,   // flexible CG: (p, q), (p, r), alpha = (p, r) / (p, q)
+  kFinZQ = 6     // flexible CG: beta = -(z, q) / (p, q)
+};
 
 __device__ __forceinline__ bool converged(double rr, double bb, double rtol) {
   return sqrt(rr) <= rtol * sqrt(bb);
@@ -147,7 +155,7 @@ __global__ void __launch_bounds__(1024) k_finalize(int32_t op, int32_t nparts,
   PcgScal sc;
   if (threadIdx.x == 0) sc = *scal;
   __shared__ double sh[2][1024 / kWave];
-  const int nv = op == kFinInit ? 2 : 1;
+  const int nv = op == kFinInit || op == kFinPQR ? 2 : 1;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   for (int q = 0; q < nv; ++q) {
     // this thread's partials in index order, sixteen loads at a time
@@ -207,6 +215,14 @@ __global__ void __launch_bounds__(1024) k_finalize(int32_t op, int32_t nparts,
         scal->beta = tot[0] / sc.rho;
         scal->rho = tot[0];
       }
+      break;
+    case kFinPQR:
+      scal->pq = tot[0];
+      if (!(tot[0] > 0.0)) scal->done = 3;
+      else scal->alpha = tot[1] / tot[0];
+      break;
+    case kFinZQ:
+      scal->beta = -tot[0] / sc.pq;
       break;
     default:
       scal->rr_true = tot[0];
@@ -374,12 +390,13 @@ __global__ void __launch_bounds__(kBlock) k_pre_restrict(
 }
 
 // y = z + M^-1 (r - A z); with DOT also the block partials of (r, y)
+// (with a dot partner dv, the partials are of (dv, y) instead)
 template <typename TV, typename TR, typename TO, bool DOT>
 __global__ void __launch_bounds__(kBlock) k_post(
     int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
     const TV *__restrict__ val, const TV *__restrict__ minv, const TR *__restrict__ r,
     const TV *__restrict__ z, TO *__restrict__ y, double *__restrict__ partials,
-    const int32_t *__restrict__ done) {
+    const int32_t *__restrict__ done, const double *__restrict__ dv = nullptr) {
   if (*done) return;
   int32_t rb, re;
   rows_of_block(n, chunk, &rb, &re);
@@ -391,7 +408,7 @@ __global__ void __launch_bounds__(kBlock) k_post(
     const TR rr = r[row];
     const TO yo = (TO)(z[row] + ((TV)rr - acc) * minv[row]);
     y[row] = yo;
-    if (DOT) d[0] += (double)rr * (double)yo;
+    if (DOT) d[0] += (dv ? dv[row] : (double)rr) * (double)yo;
   }
   if (DOT) block_partial<1>(d, partials);
 }
@@ -704,6 +721,127 @@ __global__ void k_xpay(int32_t n, const double *__restrict__ z, double *__restri
 }
 
 // ---------------------------------------------------------------------------
+// K-cycle: two flexible-CG iterations per intermediate level (Section 3.1)
+// ---------------------------------------------------------------------------
+
+// v = A c and the block partials of (c, v) and of (c, u) for each given u
+// (plane 0: (c, v); plane q >= 1: (c, u_q)), sums in FP64
+template <typename TV, int NV>
+__global__ void __launch_bounds__(kBlock) k_spmv_dots(
+    int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
+    const TV *__restrict__ val, const TV *__restrict__ c, TV *__restrict__ v,
+    const TV *__restrict__ u1, const TV *__restrict__ u2, double *__restrict__ partials,
+    const int32_t *__restrict__ done) {
+  if (*done) return;
+  int32_t rb, re;
+  rows_of_block(n, chunk, &rb, &re);
+  double d[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) d[q] = 0.0;
+  for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
+    int32_t base, w;
+    sell_row(sptr, row, &base, &w);
+    const TV acc = sell_dot(col, val, base, w, [&](int32_t cc) { return c[cc]; });
+    v[row] = acc;
+    const double ci = (double)c[row];
+    d[0] += ci * (double)acc;
+    if (NV > 1) d[1] += ci * (double)u1[row];
+    if (NV > 2) d[2] += ci * (double)u2[row];
+  }
+  block_partial<NV>(d, partials);
+}
+
+// One block: the level's flexible-CG scalars from the block partials.
+// op 1 (after c1): rho1 = (c1, v1), s1 = (c1, b) / rho1 (0 if rho1 <= 0).
+// op 2 (after c2): gamma = (c2, v1), rho2 = (c2, v2) - gamma^2 / rho1,
+// s2 = (c2, r1) / rho2, a1 = s1 - s2 (gamma / rho1); x = a1 c1 + s2 c2.
+// rho1 <= 0 gives x = 0, rho2 <= 0 gives x = s1 c1.
+__global__ void __launch_bounds__(1024) k_kfin(int32_t op, int32_t nparts,
+                                               const double *__restrict__ partials,
+                                               double *__restrict__ ks,
+                                               const int32_t *__restrict__ done) {
+  const int32_t stop = *done;
+  __shared__ double sh[3][1024 / kWave];
+  const int nv = op == 1 ? 2 : 3;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  for (int q = 0; q < nv; ++q) {
+    const double *src = partials + (int64_t)q * kMaxParts;
+    double a = 0.0;
+    for (int32_t b0 = threadIdx.x; b0 < nparts; b0 += 16 * blockDim.x) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int32_t b = b0 + u * (int32_t)blockDim.x;
+        v[u] = b < nparts ? src[b] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (b0 + u * (int32_t)blockDim.x < nparts) a += v[u];
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) a += __shfl_down(a, o, kWave);
+    if (lane == 0) sh[q][wid] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0 || stop) return;
+  double tot[3] = {0.0, 0.0, 0.0};
+  for (int q = 0; q < nv; ++q) {
+    double t = sh[q][0];
+    for (int k = 1; k < (int)(blockDim.x / kWave); ++k) t += sh[q][k];
+    tot[q] = t;
+  }
+  if (op == 1) {
+    const double rho1 = tot[0];
+    ks[kRho1] = rho1;
+    ks[kS1] = rho1 > 0.0 ? tot[1] / rho1 : 0.0;
+    return;
+  }
+  const double rho1 = ks[kRho1], s1 = ks[kS1];
+  const double beta = tot[0], gamma = tot[1], a2 = tot[2];
+  if (!(rho1 > 0.0)) {
+    ks[kA1] = 0.0;
+    ks[kS2] = 0.0;
+    return;
+  }
+  const double rho2 = beta - gamma * gamma / rho1;
+  ks[kGamma] = gamma;
+  ks[kRho2] = rho2;
+  if (!(rho2 > 0.0)) {
+    ks[kA1] = s1;
+    ks[kS2] = 0.0;
+  } else {
+    const double s2 = a2 / rho2;
+    ks[kS2] = s2;
+    ks[kA1] = s1 - s2 * (gamma / rho1);
+  }
+}
+
+// r1 = b - s1 v1
+template <typename TV>
+__global__ void k_kresid(int32_t n, const TV *__restrict__ b, const TV *__restrict__ v1,
+                         const double *__restrict__ ks, TV *__restrict__ r1,
+                         const int32_t *__restrict__ done) {
+  if (*done) return;
+  const TV s1 = (TV)ks[kS1];
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) r1[i] = b[i] - s1 * v1[i];
+}
+
+// z_f += P x with x = a1 c1 + s2 c2 formed per coarse position
+template <typename TV>
+__global__ void k_kprolong(int32_t nf, const int32_t *__restrict__ aggp,
+                           const TV *__restrict__ pp, const TV *__restrict__ c1,
+                           const TV *__restrict__ c2, const double *__restrict__ ks,
+                           TV *__restrict__ zf, const int32_t *__restrict__ done) {
+  if (*done) return;
+  const TV a1 = (TV)ks[kA1], s2 = (TV)ks[kS2];
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nf) {
+    const int32_t J = aggp[k];
+    zf[k] += pp[k] * (a1 * c1[J] + s2 * c2[J]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host: the V-cycle for one hierarchy precision
 // ---------------------------------------------------------------------------
 
@@ -852,6 +990,99 @@ void vcycle_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const in
   }
 }
 
+// ---- K-cycle (Section 3.1) ----
+
+template <typename TV>
+void fcg2_t(amg_hierarchy *h, int32_t m, const int32_t *done);
+
+// K-cycle on level l < L. in: the level's right-hand side (level 0: the FP64
+// CG residual); out: the result (level 0: FP64). With a dot partner dv the
+// last post-sweep also writes the block partials of (dv, out).
+template <typename TV, typename TR, typename TO>
+void kcycle_t(amg_hierarchy *h, int32_t l, const TR *in, TO *out, const double *dv,
+              const int32_t *done) {
+  hipStream_t s = h->stream;
+  const int32_t L = (int32_t)h->lv.size() - 1;
+  Level &F = h->lv[l];
+  TV *z = launch_down<TV, TR>(h, l, in, done);
+  if (l + 1 == L) {
+    const int32_t nL = h->C.n;
+    k_coarse_prolong<TV><<<1, 1024, 2 * sizeof(double) * nL, s>>>(
+        nL, h->C.Ainv, (const TV *)h->lv[L].r, F.n, F.aggp, ppv<TV>(F), z, done);
+  } else {
+    const Level &C = h->lv[l + 1];
+    fcg2_t<TV>(h, l + 1, done);
+    k_kprolong<TV><<<grid1(F.n), kBlock, 0, s>>>(F.n, F.aggp, ppv<TV>(F), (const TV *)C.c1,
+                                                 (const TV *)C.c2,
+                                                 h->kscal + (int64_t)(l + 1) * kKScal, z, done);
+  }
+  // post-smoothing: post - 1 sweeps alternating two level buffers, the last
+  // into out
+  TV *tmp = (TV *)F.y;
+  if (tmp == z) tmp = (TV *)F.z;
+  const Geom g = geom(F.n);
+  for (int32_t k = 1; k < h->params.post; ++k) {
+    k_post<TV, TR, TV, false><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
+                                                       vals<TV>(F), minv<TV>(F), in, z, tmp,
+                                                       nullptr, done);
+    std::swap(z, tmp);
+  }
+  if (dv)
+    k_post<TV, TR, TO, true><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
+                                                      vals<TV>(F), minv<TV>(F), in, z, out,
+                                                      h->partials, done, dv);
+  else
+    k_post<TV, TR, TO, false><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
+                                                       vals<TV>(F), minv<TV>(F), in, z, out,
+                                                       nullptr, done);
+}
+
+// Two flexible-CG iterations on level m (0 < m < L) for the right-hand side
+// the level above restricted into lv[m].r, from zero; the result stays as
+// x = a1 c1 + s2 c2 (vectors c1, c2 of the level, scalars in its kscal slot)
+// for the prolongation to combine.
+template <typename TV>
+void fcg2_t(amg_hierarchy *h, int32_t m, const int32_t *done) {
+  hipStream_t s = h->stream;
+  Level &M = h->lv[m];
+  const int32_t n = M.n;
+  const TV *b = (const TV *)M.r;
+  double *ks = h->kscal + (int64_t)m * kKScal;
+  const Geom g = geom(n);
+  kcycle_t<TV, TV, TV>(h, m, b, (TV *)M.c1, nullptr, done);
+  k_spmv_dots<TV, 2><<<g.grid, kBlock, 0, s>>>(n, g.chunk, M.S.sptr, M.S.col, vals<TV>(M),
+                                               (const TV *)M.c1, (TV *)M.v1, b, nullptr,
+                                               h->partials, done);
+  k_kfin<<<1, 1024, 0, s>>>(1, g.grid, h->partials, ks, done);
+  k_kresid<TV><<<grid1(n), kBlock, 0, s>>>(n, b, (const TV *)M.v1, ks, (TV *)M.r1, done);
+  kcycle_t<TV, TV, TV>(h, m, (const TV *)M.r1, (TV *)M.c2, nullptr, done);
+  k_spmv_dots<TV, 3><<<g.grid, kBlock, 0, s>>>(n, g.chunk, M.S.sptr, M.S.col, vals<TV>(M),
+                                               (const TV *)M.c2, (TV *)M.v2,
+                                               (const TV *)M.v1, (const TV *)M.r1,
+                                               h->partials, done);
+  k_kfin<<<1, 1024, 0, s>>>(2, g.grid, h->partials, ks, done);
+}
+
+// z0 = K r0 on the aggregate-major level-0 vectors (with dv: the partials of
+// (dv, z0) as well)
+template <typename TV>
+void kcycle_top(amg_hierarchy *h, const double *r0, double *z0, const double *dv,
+                const int32_t *done) {
+  hipStream_t s = h->stream;
+  const int32_t L = (int32_t)h->lv.size() - 1;
+  if (L == 0) {
+    const int32_t n = h->C.n;
+    k_coarse_solve<double, double><<<ceil_div(n, kCoarseWaves), kWave * kCoarseWaves, 0, s>>>(
+        n, h->C.Ainv, r0, z0, done);
+    if (dv) {
+      const Geom g = geom(h->lv[0].n);
+      k_dot_rz<<<g.grid, kBlock, 0, s>>>(h->lv[0].n, g.chunk, dv, z0, h->partials, done);
+    }
+    return;
+  }
+  kcycle_t<TV, double, double>(h, 0, r0, z0, dv, done);
+}
+
 amg_status alloc_level_vectors(amg_hierarchy *h, Level &L, size_t vbytes) {
   AMG_TRY(dev_alloc(h, &L.r, vbytes * L.n + 16));
   AMG_TRY(dev_alloc(h, &L.z, vbytes * L.n + 16));
@@ -935,7 +1166,17 @@ amg_status build_solve_formats(amg_hierarchy *h) {
       }
     }
     AMG_TRY(alloc_level_vectors(h, L, vbytes));
+    // K-cycle flexible-CG vectors on the levels strictly between the finest
+    // and the coarsest
+    if (h->params.cycle == AMG_CYCLE_K && l > 0 && l + 1 < nlev) {
+      AMG_TRY(dev_alloc(h, &L.c1, vbytes * L.n + 16));
+      AMG_TRY(dev_alloc(h, &L.v1, vbytes * L.n + 16));
+      AMG_TRY(dev_alloc(h, &L.r1, vbytes * L.n + 16));
+      AMG_TRY(dev_alloc(h, &L.c2, vbytes * L.n + 16));
+      AMG_TRY(dev_alloc(h, &L.v2, vbytes * L.n + 16));
+    }
   }
+  if (h->params.cycle == AMG_CYCLE_K) AMG_TRY(dalloc(h, &h->kscal, (size_t)kKScal * nlev));
   // outer CG vectors and scalars (aggregate-major order of level 0)
   const int32_t n0 = h->lv[0].n;
   AMG_TRY(dalloc(h, &h->x, (size_t)n0));
@@ -944,7 +1185,7 @@ amg_status build_solve_formats(amg_hierarchy *h) {
   AMG_TRY(dalloc(h, &h->z, (size_t)n0));
   AMG_TRY(dalloc(h, &h->p, (size_t)n0));
   AMG_TRY(dalloc(h, &h->q, (size_t)n0));
-  AMG_TRY(dalloc(h, &h->partials, (size_t)kMaxParts * 2));
+  AMG_TRY(dalloc(h, &h->partials, (size_t)kMaxParts * kPartPlanes));
   AMG_TRY(dalloc(h, &h->scal, 1));
   AMG_TRY(dalloc(h, &h->zero_flag, 4));
   AMG_HIP(hipMemsetAsync(h->zero_flag, 0, sizeof(int32_t) * 4, s));
@@ -954,8 +1195,18 @@ amg_status build_solve_formats(amg_hierarchy *h) {
 }
 
 // Applies the V-cycle to vectors in the aggregate-major order of level 0.
+// The K-cycle with an optional dot partner (see kcycle_top)
+amg_status kcycle_perm(amg_hierarchy *h, const double *r, double *z, const double *dv,
+                       const int32_t *done) {
+  if (h->params.precision == AMG_FP32) kcycle_top<float>(h, r, z, dv, done);
+  else kcycle_top<double>(h, r, z, dv, done);
+  AMG_HIP(hipGetLastError());
+  return AMG_OK;
+}
+
 amg_status vcycle_perm(amg_hierarchy *h, const double *r, double *z, bool fuse_dot,
                        const int32_t *done) {
+  if (h->params.cycle == AMG_CYCLE_K) return kcycle_perm(h, r, z, nullptr, done);
   if (h->params.precision == AMG_FP32) vcycle_t<float>(h, r, z, fuse_dot, done);
   else vcycle_t<double>(h, r, z, fuse_dot, done);
   AMG_HIP(hipGetLastError());
@@ -979,7 +1230,32 @@ namespace {
 // One CG iteration: q = A p, alpha, x and r updates with the stop test,
 // z = B r with (r, z) and beta, p = z + beta p. Touches only hierarchy
 // buffers, so it is captured once and replayed.
+// One flexible-CG iteration with the K-cycle: q = A p with (p, q), (p, r),
+// alpha = (p, r) / (p, q), the x and r updates with the stop test,
+// z = K r with (q, z), beta = -(z, q) / (p, q), p = z + beta p.
+void fcg_iteration(amg_hierarchy *h) {
+  hipStream_t s = h->stream;
+  Level &L0 = h->lv[0];
+  const int32_t n = L0.n;
+  const int32_t *done = &h->scal->done;
+  const Geom g = geom(n);
+  k_spmv_dots<double, 2><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64,
+                                                   h->p, h->q, h->r, nullptr, h->partials,
+                                                   done);
+  finalize(h, kFinPQR, g.grid, done);
+  k_update_xr<<<g.grid, kBlock, 0, s>>>(n, g.chunk, h->x, h->r, h->p, h->q, h->partials, h->scal,
+                                        done);
+  finalize(h, kFinRR, g.grid, done);
+  kcycle_perm(h, h->r, h->z, h->q, done);
+  finalize(h, kFinZQ, g.grid, done);
+  k_xpay<<<grid1(n), kBlock, 0, s>>>(n, h->z, h->p, h->scal, 0, done);
+}
+
 void cg_iteration(amg_hierarchy *h) {
+  if (h->params.cycle == AMG_CYCLE_K) {
+    fcg_iteration(h);
+    return;
+  }
   hipStream_t s = h->stream;
   Level &L0 = h->lv[0];
   const int32_t n = L0.n;
@@ -1054,7 +1330,8 @@ amg_status pcg(amg_hierarchy *h, const double *b_user, double *x_user, double rt
                                                h->x, h->r, h->partials);
   finalize(h, kFinInit, g.grid, nullptr);
   k_zero_if_zero_rhs<<<grid1(n), kBlock, 0, s>>>(n, h->x, h->scal);
-  AMG_TRY(vcycle_perm(h, h->r, h->z, true, done));
+  if (h->params.cycle == AMG_CYCLE_K) AMG_TRY(kcycle_perm(h, h->r, h->z, nullptr, done));
+  else AMG_TRY(vcycle_perm(h, h->r, h->z, true, done));
   k_xpay<<<grid1(n), kBlock, 0, s>>>(n, h->z, h->p, h->scal, 1, done);
   // iterations in chunks; the chunk length follows the observed convergence
   int32_t queued = 0, chunk = 4;
