@@ -171,6 +171,44 @@ def ingest_pmc(fetch_csv, write_csv, n=160 ** 3):
     print(json.dumps(out))
 
 
+def bench_kcycle(args):
+    """160^3 Poisson (b = A u): flexible CG with the K-cycle (Section 3.1)
+    against CG with the V-cycle, both hierarchy precisions, same run."""
+    import torch
+
+    from paper_2006_16147_amd import amg, inputs
+
+    dev = torch.device("cuda:0")
+    case = inputs.headline_case(args.N, seed=1)
+    A = case["A"]
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    ci = torch.from_numpy(A.col).to(dev)
+    va = torch.from_numpy(A.val).to(dev)
+    b = torch.from_numpy(case["b"]).to(dev)
+    out = {"mode": "kcycle", "workload": "poisson7_%d^3_b=Au_seed1_rtol1e-8" % args.N,
+           "n": A.n, "nnz": A.nnz}
+    for cyc, cname in ((amg.CYCLE_K, "K"), (amg.CYCLE_V, "V")):
+        for prec, pname in ((amg.FP64, "fp64"), (amg.FP32, "fp32_prec")):
+            h = amg.amg_setup(rp, ci, va, precision=prec, cycle=cyc)
+            x = torch.zeros_like(b)
+            times = []
+            for k in range(args.warmup + args.steps):
+                x.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, info = amg.amg_pcg_solve(h, b, x, rtol=1e-8, maxit=500)
+                if k >= args.warmup:
+                    times.append((time.perf_counter() - t0) * 1e3)
+            p50 = percentile(times, 50)
+            out["%s_%s" % (cname, pname)] = {
+                "p50_ms": round(p50, 3), "p99_ms": round(percentile(times, 99), 3),
+                "iterations": info["iterations"], "rel_res_true": info["rel_res_true"],
+                "ms_per_iteration": round(p50 / max(1, info["iterations"]), 4),
+                "setup_ms": round(h.setup_times()["total"], 1)}
+            h.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_aniso(args):
     """256^3 block-anisotropic diffusion: FP64 vs FP32 hierarchy (outer CG FP64)."""
     import torch
@@ -302,7 +340,7 @@ def main():
     ap.add_argument("--N", type=int, default=160)
     ap.add_argument("--vcycles", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="headline", choices=["headline", "aniso", "batch", "serve"],
+    ap.add_argument("--mode", default="headline", choices=["headline", "aniso", "batch", "serve", "kcycle"],
                     help="headline (default): the 160^3 benchmark line; the others print "
                          "their own JSON lines")
     ap.add_argument("--rates", default="10,50,200,500", help="serve mode: arrival rates /s")
@@ -323,10 +361,11 @@ def main():
         import torch
 
         torch.cuda.set_device(0)
-        {"aniso": bench_aniso, "batch": bench_batch, "serve": bench_serve}[args.mode](args)
+        {"aniso": bench_aniso, "batch": bench_batch, "serve": bench_serve,
+         "kcycle": bench_kcycle}[args.mode](args)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -815,6 +815,162 @@ __global__ void __launch_bounds__(1024) k_kfin(int32_t op, int32_t nparts,
   }
 }
 
+// ---- the deepest flexible-CG step in one block ----
+// For the level t just above the coarsest (pre = post = 1), the K-cycle's two
+// flexible-CG iterations, each with its cycle (down step, A_L^-1, up step),
+// the products, the dot products and the prolongation of x = a1 c1 + s2 c2
+// into the level above, in one 1024-thread block with the level's vectors in
+// LDS. Same arithmetic as the multi-kernel form; the dot products are summed
+// in a fixed order of their own.
+constexpr int kKTailMax = 1536;   // largest level t in LDS (five vectors)
+constexpr int kKTailCoarse = 128; // coarsest size for the one-pass A_L^-1 product
+
+// sum over the block; every thread gets the same value (fixed order)
+__device__ __forceinline__ double block_sum_all(double v, double *red) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double t = red[0];
+  for (int k = 1; k < nw; ++k) t += red[k];
+  return t;
+}
+
+// one K-cycle on level t (iv -> out; the coarse correction is A_L^-1)
+template <typename TV>
+__device__ void ktail_cycle(int32_t nt, const int32_t *__restrict__ sptr,
+                            const int32_t *__restrict__ col, const TV *__restrict__ sval,
+                            const TV *__restrict__ val, const TV *__restrict__ minv,
+                            const TV *__restrict__ pp, const int32_t *__restrict__ seg,
+                            const int32_t *__restrict__ aggp, int32_t nL,
+                            const double *__restrict__ Ainv, const TV *iv, TV *zs, TV *ys,
+                            TV *out, double *rl, double *zl) {
+  const int32_t tid = threadIdx.x, nth = blockDim.x;
+  for (int32_t k = tid; k < nt; k += nth) zs[k] = iv[k] * minv[k];
+  for (int32_t k = tid; k < nt; k += nth) {
+    const int32_t s = k / kSlice, base = sptr[s] + k % kSlice, w = (sptr[s + 1] - sptr[s]) / kSlice;
+    const TV acc = sell_dot(col, sval, base, w, [&](int32_t c) { return iv[c]; });
+    ys[k] = pp[k] * (iv[k] - acc);
+  }
+  __syncthreads();
+  for (int32_t J = tid; J < nL; J += nth) {
+    TV a = 0;
+    for (int32_t m = seg[J]; m < seg[J + 1]; ++m) a += ys[m];
+    rl[J] = (double)a;
+  }
+  __syncthreads();
+  {
+    const int32_t part = tid % kCoarseSplit, i = tid / kCoarseSplit;
+    double a = 0.0;
+    if (i < nL) {
+      const double *row = Ainv + (int64_t)i * nL;
+#pragma unroll 8
+      for (int32_t k = part; k < nL; k += kCoarseSplit) a += row[k] * rl[k];
+    }
+    for (int o = kCoarseSplit / 2; o > 0; o >>= 1) a += __shfl_down(a, o, kCoarseSplit);
+    if (i < nL && part == 0) zl[i] = a;
+  }
+  __syncthreads();
+  for (int32_t k = tid; k < nt; k += nth) zs[k] += pp[k] * (TV)zl[aggp[k]];
+  __syncthreads();
+  for (int32_t k = tid; k < nt; k += nth) {
+    const int32_t s = k / kSlice, base = sptr[s] + k % kSlice, w = (sptr[s + 1] - sptr[s]) / kSlice;
+    const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return zs[c]; });
+    out[k] = zs[k] + (iv[k] - acc) * minv[k];
+  }
+  __syncthreads();
+}
+
+template <typename TV>
+__global__ void __launch_bounds__(1024) k_ktail(
+    int32_t nt, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
+    const TV *__restrict__ sval, const TV *__restrict__ val, const TV *__restrict__ minv,
+    const TV *__restrict__ pp, const int32_t *__restrict__ seg, const int32_t *__restrict__ aggp,
+    int32_t nL, const double *__restrict__ Ainv, const TV *__restrict__ b, int32_t nf,
+    const int32_t *__restrict__ aggp_f, const TV *__restrict__ pp_f, TV *__restrict__ zf,
+    double *__restrict__ ks, const int32_t *__restrict__ done) {
+  __shared__ TV IV[kKTailMax], ZS[kKTailMax], YS[kKTailMax], C1[kKTailMax], C2[kKTailMax];
+  __shared__ double rl[kKTailCoarse], zl[kKTailCoarse], red[1024 / kWave];
+  if (*done) return;
+  const int32_t tid = threadIdx.x, nth = blockDim.x;
+  constexpr int kRows = kKTailMax / 1024 + 1;  // rows per thread
+  for (int32_t k = tid; k < nt; k += nth) IV[k] = b[k];
+  __syncthreads();
+  ktail_cycle<TV>(nt, sptr, col, sval, val, minv, pp, seg, aggp, nL, Ainv, IV, ZS, YS, C1, rl,
+                  zl);
+  // v1 = A c1, rho1 = (c1, v1), s1 = (c1, b) / rho1
+  TV v1[kRows];
+  double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+  for (int u = 0; u < kRows; ++u) {
+    const int32_t k = tid + u * nth;
+    v1[u] = 0;
+    if (k < nt) {
+      const int32_t s = k / kSlice, base = sptr[s] + k % kSlice,
+                    w = (sptr[s + 1] - sptr[s]) / kSlice;
+      const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return C1[c]; });
+      v1[u] = acc;
+      d0 += (double)C1[k] * (double)acc;
+      d1 += (double)C1[k] * (double)IV[k];
+    }
+  }
+  const double rho1 = block_sum_all(d0, red);
+  const double cb = block_sum_all(d1, red);
+  const double s1 = rho1 > 0.0 ? cb / rho1 : 0.0;
+  // r1 = b - s1 v1 (in IV)
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kRows; ++u) {
+    const int32_t k = tid + u * nth;
+    if (k < nt) IV[k] = IV[k] - (TV)s1 * v1[u];
+  }
+  __syncthreads();
+  ktail_cycle<TV>(nt, sptr, col, sval, val, minv, pp, seg, aggp, nL, Ainv, IV, ZS, YS, C2, rl,
+                  zl);
+  // v2 = A c2; (c2, v2), gamma = (c2, v1), (c2, r1)
+  double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+#pragma unroll
+  for (int u = 0; u < kRows; ++u) {
+    const int32_t k = tid + u * nth;
+    if (k < nt) {
+      const int32_t s = k / kSlice, base = sptr[s] + k % kSlice,
+                    w = (sptr[s + 1] - sptr[s]) / kSlice;
+      const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return C2[c]; });
+      const double c2 = (double)C2[k];
+      e0 += c2 * (double)acc;
+      e1 += c2 * (double)v1[u];
+      e2 += c2 * (double)IV[k];
+    }
+  }
+  const double beta = block_sum_all(e0, red);
+  const double gamma = block_sum_all(e1, red);
+  const double a2 = block_sum_all(e2, red);
+  double a1 = 0.0, s2 = 0.0;
+  if (rho1 > 0.0) {
+    const double rho2 = beta - gamma * gamma / rho1;
+    if (!(rho2 > 0.0)) {
+      a1 = s1;
+    } else {
+      s2 = a2 / rho2;
+      a1 = s1 - s2 * (gamma / rho1);
+    }
+  }
+  if (tid == 0) {
+    ks[kRho1] = rho1;
+    ks[kS1] = s1;
+    ks[kA1] = a1;
+    ks[kS2] = s2;
+  }
+  // z_f += P x, x = a1 c1 + s2 c2
+  const TV ta1 = (TV)a1, ts2 = (TV)s2;
+  for (int32_t k = tid; k < nf; k += nth) {
+    const int32_t J = aggp_f[k];
+    zf[k] += pp_f[k] * (ta1 * C1[J] + ts2 * C2[J]);
+  }
+}
+
 // r1 = b - s1 v1
 template <typename TV>
 __global__ void k_kresid(int32_t n, const TV *__restrict__ b, const TV *__restrict__ v1,
@@ -1009,6 +1165,13 @@ void kcycle_t(amg_hierarchy *h, int32_t l, const TR *in, TO *out, const double *
     const int32_t nL = h->C.n;
     k_coarse_prolong<TV><<<1, 1024, 2 * sizeof(double) * nL, s>>>(
         nL, h->C.Ainv, (const TV *)h->lv[L].r, F.n, F.aggp, ppv<TV>(F), z, done);
+  } else if (l + 2 == L && h->params.pre == 1 && h->params.post == 1 &&
+             h->lv[l + 1].n <= kKTailMax && h->C.n <= kKTailCoarse) {
+    const Level &T = h->lv[l + 1];
+    k_ktail<TV><<<1, 1024, 0, s>>>(T.n, T.S.sptr, T.S.col, svals<TV>(T), vals<TV>(T),
+                                   minv<TV>(T), ppv<TV>(T), T.seg, T.aggp, h->C.n, h->C.Ainv,
+                                   (const TV *)T.r, F.n, F.aggp, ppv<TV>(F), z,
+                                   h->kscal + (int64_t)(l + 1) * kKScal, done);
   } else {
     const Level &C = h->lv[l + 1];
     fcg2_t<TV>(h, l + 1, done);
