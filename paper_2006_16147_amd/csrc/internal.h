@@ -69,6 +69,7 @@ struct Sell {
   float *v32 = nullptr;
   double *s64 = nullptr;
   float *s32 = nullptr;
+  int32_t max_width = 0;  // widest slice (entries per row); set for levels of <= 1024 rows
 };
 
 // A level holds its setup data in the original numbering of that level and

@@ -838,20 +838,60 @@ __device__ __forceinline__ double block_sum_all(double v, double *red) {
   return t;
 }
 
-// one K-cycle on level t (iv -> out; the coarse correction is A_L^-1)
+// One SELL row of the level held in registers (w <= kRowBatch entries):
+// loaded once per launch when every thread owns at most one row, then used
+// by all six products of the step.
 template <typename TV>
+struct RegRow {
+  int32_t w = 0;
+  int32_t c[kRowBatch];
+  TV v[kRowBatch], sv[kRowBatch];
+  __device__ void load(const int32_t *sptr, const int32_t *col, const TV *val, const TV *sval,
+                       int32_t k) {
+    const int32_t s = k / kSlice, base = sptr[s] + k % kSlice;
+    w = (sptr[s + 1] - sptr[s]) / kSlice;
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      c[u] = 0;
+      v[u] = sv[u] = 0;
+      if (u < w) {
+        c[u] = col[base + u * kSlice];
+        v[u] = val[base + u * kSlice];
+        sv[u] = sval[base + u * kSlice];
+      }
+    }
+  }
+  // sum_e a_e x[c_e] (scaled: A M^-1) in entry order
+  template <bool SCALED>
+  __device__ TV dot(const TV *x) const {
+    TV acc = 0;
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u)
+      if (u < w) acc += (SCALED ? sv[u] : v[u]) * x[c[u]];
+    return acc;
+  }
+};
+
+// one K-cycle on level t (iv -> out; the coarse correction is A_L^-1)
+template <typename TV, bool REG>
 __device__ void ktail_cycle(int32_t nt, const int32_t *__restrict__ sptr,
                             const int32_t *__restrict__ col, const TV *__restrict__ sval,
                             const TV *__restrict__ val, const TV *__restrict__ minv,
                             const TV *__restrict__ pp, const int32_t *__restrict__ seg,
                             const int32_t *__restrict__ aggp, int32_t nL,
                             const double *__restrict__ Ainv, const TV *iv, TV *zs, TV *ys,
-                            TV *out, double *rl, double *zl) {
+                            TV *out, double *rl, double *zl, const RegRow<TV> &rr) {
   const int32_t tid = threadIdx.x, nth = blockDim.x;
   for (int32_t k = tid; k < nt; k += nth) zs[k] = iv[k] * minv[k];
   for (int32_t k = tid; k < nt; k += nth) {
-    const int32_t s = k / kSlice, base = sptr[s] + k % kSlice, w = (sptr[s + 1] - sptr[s]) / kSlice;
-    const TV acc = sell_dot(col, sval, base, w, [&](int32_t c) { return iv[c]; });
+    TV acc;
+    if (REG) {
+      acc = rr.template dot<true>(iv);
+    } else {
+      const int32_t s = k / kSlice, base = sptr[s] + k % kSlice,
+                    w = (sptr[s + 1] - sptr[s]) / kSlice;
+      acc = sell_dot(col, sval, base, w, [&](int32_t c) { return iv[c]; });
+    }
     ys[k] = pp[k] * (iv[k] - acc);
   }
   __syncthreads();
@@ -876,14 +916,20 @@ __device__ void ktail_cycle(int32_t nt, const int32_t *__restrict__ sptr,
   for (int32_t k = tid; k < nt; k += nth) zs[k] += pp[k] * (TV)zl[aggp[k]];
   __syncthreads();
   for (int32_t k = tid; k < nt; k += nth) {
-    const int32_t s = k / kSlice, base = sptr[s] + k % kSlice, w = (sptr[s + 1] - sptr[s]) / kSlice;
-    const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return zs[c]; });
+    TV acc;
+    if (REG) {
+      acc = rr.template dot<false>(zs);
+    } else {
+      const int32_t s = k / kSlice, base = sptr[s] + k % kSlice,
+                    w = (sptr[s + 1] - sptr[s]) / kSlice;
+      acc = sell_dot(col, val, base, w, [&](int32_t c) { return zs[c]; });
+    }
     out[k] = zs[k] + (iv[k] - acc) * minv[k];
   }
   __syncthreads();
 }
 
-template <typename TV>
+template <typename TV, bool REG>
 __global__ void __launch_bounds__(1024) k_ktail(
     int32_t nt, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
     const TV *__restrict__ sval, const TV *__restrict__ val, const TV *__restrict__ minv,
@@ -896,10 +942,14 @@ __global__ void __launch_bounds__(1024) k_ktail(
   if (*done) return;
   const int32_t tid = threadIdx.x, nth = blockDim.x;
   constexpr int kRows = kKTailMax / 1024 + 1;  // rows per thread
+  // REG: one row per thread (nt <= blockDim.x, rows of at most kRowBatch
+  // entries), held in registers for every product of the step
+  RegRow<TV> rr;
+  if (REG && tid < nt) rr.load(sptr, col, val, sval, tid);
   for (int32_t k = tid; k < nt; k += nth) IV[k] = b[k];
   __syncthreads();
-  ktail_cycle<TV>(nt, sptr, col, sval, val, minv, pp, seg, aggp, nL, Ainv, IV, ZS, YS, C1, rl,
-                  zl);
+  ktail_cycle<TV, REG>(nt, sptr, col, sval, val, minv, pp, seg, aggp, nL, Ainv, IV, ZS, YS, C1,
+                       rl, zl, rr);
   // v1 = A c1, rho1 = (c1, v1), s1 = (c1, b) / rho1
   TV v1[kRows];
   double d0 = 0.0, d1 = 0.0;
@@ -908,9 +958,14 @@ __global__ void __launch_bounds__(1024) k_ktail(
     const int32_t k = tid + u * nth;
     v1[u] = 0;
     if (k < nt) {
-      const int32_t s = k / kSlice, base = sptr[s] + k % kSlice,
-                    w = (sptr[s + 1] - sptr[s]) / kSlice;
-      const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return C1[c]; });
+      TV acc;
+      if (REG) {
+        acc = rr.template dot<false>(C1);
+      } else {
+        const int32_t s = k / kSlice, base = sptr[s] + k % kSlice,
+                      w = (sptr[s + 1] - sptr[s]) / kSlice;
+        acc = sell_dot(col, val, base, w, [&](int32_t c) { return C1[c]; });
+      }
       v1[u] = acc;
       d0 += (double)C1[k] * (double)acc;
       d1 += (double)C1[k] * (double)IV[k];
@@ -927,17 +982,22 @@ __global__ void __launch_bounds__(1024) k_ktail(
     if (k < nt) IV[k] = IV[k] - (TV)s1 * v1[u];
   }
   __syncthreads();
-  ktail_cycle<TV>(nt, sptr, col, sval, val, minv, pp, seg, aggp, nL, Ainv, IV, ZS, YS, C2, rl,
-                  zl);
+  ktail_cycle<TV, REG>(nt, sptr, col, sval, val, minv, pp, seg, aggp, nL, Ainv, IV, ZS, YS, C2,
+                       rl, zl, rr);
   // v2 = A c2; (c2, v2), gamma = (c2, v1), (c2, r1)
   double e0 = 0.0, e1 = 0.0, e2 = 0.0;
 #pragma unroll
   for (int u = 0; u < kRows; ++u) {
     const int32_t k = tid + u * nth;
     if (k < nt) {
-      const int32_t s = k / kSlice, base = sptr[s] + k % kSlice,
-                    w = (sptr[s + 1] - sptr[s]) / kSlice;
-      const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return C2[c]; });
+      TV acc;
+      if (REG) {
+        acc = rr.template dot<false>(C2);
+      } else {
+        const int32_t s = k / kSlice, base = sptr[s] + k % kSlice,
+                      w = (sptr[s + 1] - sptr[s]) / kSlice;
+        acc = sell_dot(col, val, base, w, [&](int32_t c) { return C2[c]; });
+      }
       const double c2 = (double)C2[k];
       e0 += c2 * (double)acc;
       e1 += c2 * (double)v1[u];
@@ -1168,10 +1228,10 @@ void kcycle_t(amg_hierarchy *h, int32_t l, const TR *in, TO *out, const double *
   } else if (l + 2 == L && h->params.pre == 1 && h->params.post == 1 &&
              h->lv[l + 1].n <= kKTailMax && h->C.n <= kKTailCoarse) {
     const Level &T = h->lv[l + 1];
-    k_ktail<TV><<<1, 1024, 0, s>>>(T.n, T.S.sptr, T.S.col, svals<TV>(T), vals<TV>(T),
-                                   minv<TV>(T), ppv<TV>(T), T.seg, T.aggp, h->C.n, h->C.Ainv,
-                                   (const TV *)T.r, F.n, F.aggp, ppv<TV>(F), z,
-                                   h->kscal + (int64_t)(l + 1) * kKScal, done);
+    auto kt = T.n <= 1024 && T.S.max_width <= kRowBatch ? k_ktail<TV, true> : k_ktail<TV, false>;
+    kt<<<1, 1024, 0, s>>>(T.n, T.S.sptr, T.S.col, svals<TV>(T), vals<TV>(T), minv<TV>(T),
+                          ppv<TV>(T), T.seg, T.aggp, h->C.n, h->C.Ainv, (const TV *)T.r, F.n,
+                          F.aggp, ppv<TV>(F), z, h->kscal + (int64_t)(l + 1) * kKScal, done);
   } else {
     const Level &C = h->lv[l + 1];
     fcg2_t<TV>(h, l + 1, done);
@@ -1309,6 +1369,14 @@ amg_status build_solve_formats(amg_hierarchy *h) {
                              hipMemcpyDeviceToHost, s));
       AMG_HIP(hipStreamSynchronize(s));
       S.nnz_padded = padded;
+      if (L.n <= 1024) {  // small levels: the widest slice, for register-held rows
+        std::vector<int32_t> sp(S.nslices + 1);
+        AMG_HIP(hipMemcpyAsync(sp.data(), S.sptr, sizeof(int32_t) * (S.nslices + 1),
+                               hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipStreamSynchronize(s));
+        for (int32_t q = 0; q < S.nslices; ++q)
+          S.max_width = std::max(S.max_width, (sp[q + 1] - sp[q]) / kSlice);
+      }
       AMG_TRY(dalloc(h, &S.col, (size_t)padded));
       if (need64) AMG_TRY(dalloc(h, &S.v64, (size_t)padded));
       if (need32) AMG_TRY(dalloc(h, &S.v32, (size_t)padded));
