@@ -209,6 +209,43 @@ def bench_kcycle(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_variants(args):
+    """160^3 Poisson (b = A u), V-cycle PCG in FP64: 3 or 4 pairwise sweeps
+    per level, w = ones or an algebraically smooth w (4 l1-Jacobi sweeps on
+    A w = 0 from ones)."""
+    import torch
+
+    from paper_2006_16147_amd import amg, inputs
+
+    dev = torch.device("cuda:0")
+    case = inputs.headline_case(args.N, seed=1)
+    A = case["A"]
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    ci = torch.from_numpy(A.col).to(dev)
+    va = torch.from_numpy(A.val).to(dev)
+    b = torch.from_numpy(case["b"]).to(dev)
+    out = {"mode": "variants", "workload": "poisson7_%d^3_b=Au_seed1_rtol1e-8" % args.N}
+    for sweeps in (3, 4):
+        for nu in (0, 4):
+            h = amg.amg_setup(rp, ci, va, sweeps=sweeps, w_sweeps=nu)
+            x = torch.zeros_like(b)
+            times = []
+            for k in range(args.warmup + args.steps):
+                x.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, info = amg.amg_pcg_solve(h, b, x, rtol=1e-8, maxit=500)
+                if k >= args.warmup:
+                    times.append((time.perf_counter() - t0) * 1e3)
+            out["sweeps%d_wsweeps%d" % (sweeps, nu)] = {
+                "levels": h.sizes(), "opc": round(h.opc(), 5),
+                "setup_ms": round(h.setup_times()["total"], 1),
+                "iterations": info["iterations"], "rel_res_true": info["rel_res_true"],
+                "p50_ms": round(percentile(times, 50), 3)}
+            h.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_aniso(args):
     """256^3 block-anisotropic diffusion: FP64 vs FP32 hierarchy (outer CG FP64)."""
     import torch
@@ -340,7 +377,7 @@ def main():
     ap.add_argument("--N", type=int, default=160)
     ap.add_argument("--vcycles", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="headline", choices=["headline", "aniso", "batch", "serve", "kcycle"],
+    ap.add_argument("--mode", default="headline", choices=["headline", "aniso", "batch", "serve", "kcycle", "variants"],
                     help="headline (default): the 160^3 benchmark line; the others print "
                          "their own JSON lines")
     ap.add_argument("--rates", default="10,50,200,500", help="serve mode: arrival rates /s")
@@ -362,7 +399,7 @@ def main():
 
         torch.cuda.set_device(0)
         {"aniso": bench_aniso, "batch": bench_batch, "serve": bench_serve,
-         "kcycle": bench_kcycle}[args.mode](args)
+         "kcycle": bench_kcycle, "variants": bench_variants}[args.mode](args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "

@@ -98,11 +98,16 @@ typedef struct {
   int32_t max_levels; /* hard cap on the number of levels; 32 */
   int32_t pre, post;  /* l1-Jacobi sweeps before / after the coarse correction; 1, 1 */
   int32_t precision;  /* AMG_FP64 or AMG_FP32 (hierarchy values and V-cycle) */
-  const double *w;    /* device, n: smooth vector, no zero entry; NULL = ones */
+  const double *w;    /* device, n: smooth vector (or the sample smoothed by w_sweeps),
+                         no zero entry; NULL = ones */
   void *stream;       /* hipStream_t for every call on this hierarchy; NULL = the
                          device's default stream */
   int32_t flags;      /* AMG_FLAG_* */
   int32_t cycle;      /* AMG_CYCLE_V or AMG_CYCLE_K; AMG_CYCLE_V */
+  int32_t w_sweeps;   /* smooth vector: w = (I - M^-1 A)^w_sweeps w0, with M the l1-Jacobi
+                         diagonal of A and w0 = w (NULL: ones), i.e. w_sweeps iterations of
+                         the smoother on A w = 0 from the sample w0 (the algebraically
+                         smooth vectors recommended after eq. (prolongator)); 0 */
 } amg_params;
 
 typedef struct {

@@ -363,6 +363,22 @@ void orc_l1_diag(const orc_csr *A, double *m) {
   }
 }
 
+/* Algebraically smooth vector (the remark after eq. (prolongator)): nu
+ * iterations of the l1-Jacobi smoother on A w = 0 from the sample w,
+ * w <- w - (A w) / m, in place. */
+void orc_smooth_w(const orc_csr *A, int32_t nu, double *w) {
+  int32_t n = A->n;
+  double *m = (double *)malloc(sizeof(double) * (size_t)n);
+  double *t = (double *)malloc(sizeof(double) * (size_t)n);
+  orc_l1_diag(A, m);
+  for (int32_t s = 0; s < nu; ++s) {
+    orc_spmv(A, w, t);
+    for (int32_t i = 0; i < n; ++i) w[i] = w[i] - t[i] / m[i];
+  }
+  free(m);
+  free(t);
+}
+
 int orc_cholesky(int32_t n, double *a) {
   for (int32_t j = 0; j < n; ++j) {
     double s = a[(int64_t)j * n + j];

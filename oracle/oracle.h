@@ -106,6 +106,9 @@ void orc_l1_diag(const orc_csr *A, double *m);
 /* Dense Cholesky A = L L^T of a row-major n x n s.p.d. matrix, in place
  * (lower triangle holds L, upper is zeroed). Returns ORC_ERR_NOT_SPD on a
  * non-positive pivot. */
+/* nu l1-Jacobi iterations on A w = 0 from the sample w (in place): an
+ * algebraically smooth vector for the matching weights. */
+void orc_smooth_w(const orc_csr *A, int32_t nu, double *w);
 int orc_cholesky(int32_t n, double *a);
 /* z = L^-T L^-1 r by forward then backward substitution. */
 void orc_cholesky_solve(int32_t n, const double *L, const double *r, double *z);

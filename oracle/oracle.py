@@ -28,6 +28,7 @@ __all__ = [
     "l1_diag",
     "cholesky",
     "cholesky_solve",
+    "smooth_w",
     "Hierarchy",
 ]
 
@@ -108,6 +109,7 @@ def load():
         "orc_level_sweeps": (C.c_int32, [C.c_void_p, C.c_int32]),
         "orc_coarse_factor": (None, [C.c_void_p, _F64P]),
         "orc_vcycle": (None, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _F64P, _F64P]),
+        "orc_smooth_w": (None, [P, C.c_int32, _F64P]),
         "orc_kcycle": (None, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _F64P, _F64P]),
         "orc_fcg2": (None, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _F64P, _F64P]),
         "orc_fcg": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _F64P, _F64P,
@@ -233,6 +235,15 @@ def cholesky_solve(L, r):
     z = np.empty(L.shape[0])
     load().orc_cholesky_solve(L.shape[0], L, _f64(r), z)
     return z
+
+
+def smooth_w(A, nu, w0=None):
+    """nu l1-Jacobi iterations on A w = 0 from the sample w0 (ones if None)."""
+    lib = load()
+    w = np.ones(A.n) if w0 is None else np.array(w0, dtype=np.float64, copy=True)
+    hc = _HostCsr(A)
+    lib.orc_smooth_w(hc.ref, int(nu), w)
+    return w
 
 
 class Hierarchy:

@@ -64,7 +64,7 @@ class Params(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("max_coarse", C.c_int32), ("max_levels", C.c_int32),
                 ("pre", C.c_int32), ("post", C.c_int32), ("precision", C.c_int32),
                 ("w", C.c_void_p), ("stream", C.c_void_p), ("flags", C.c_int32),
-                ("cycle", C.c_int32)]
+                ("cycle", C.c_int32), ("w_sweeps", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

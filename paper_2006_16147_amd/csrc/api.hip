@@ -125,6 +125,7 @@ amg_status check_params(const amg_params *p) {
   if (p->pre < 1 || p->pre > 8 || p->post < 1 || p->post > 8) return AMG_ERR_ARG;
   if (p->precision != AMG_FP64 && p->precision != AMG_FP32) return AMG_ERR_ARG;
   if (p->cycle != AMG_CYCLE_V && p->cycle != AMG_CYCLE_K) return AMG_ERR_ARG;
+  if (p->w_sweeps < 0 || p->w_sweeps > 1000) return AMG_ERR_ARG;
   return AMG_OK;
 }
 
@@ -154,6 +155,7 @@ void amg_params_default(amg_params *p) {
   p->stream = nullptr;
   p->flags = 0;
   p->cycle = AMG_CYCLE_V;
+  p->w_sweeps = 0;
 }
 
 amg_status amg_setup(const amg_csr *A, const amg_params *params, amg_hierarchy **out) {

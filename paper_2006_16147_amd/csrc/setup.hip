@@ -190,6 +190,21 @@ __global__ void k_check_w(int32_t n, const double *w, int32_t *err) {
   if (i < n && !(w[i] != 0.0 && isfinite(w[i]))) atomicOr(err, kErrArg);
 }
 
+// One sweep of the smoother on A w = 0: w_out = w - (A w) / m (row sums
+// left to right from the first term, as the serial definition)
+__global__ void k_smooth_w(int32_t n, const int32_t *rp, const int32_t *ci, const double *val,
+                           const double *m, const double *w, double *w_out) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t b = rp[i], e = rp[i + 1];
+  double t = 0.0;
+  if (e > b) {
+    t = val[b] * w[ci[b]];
+    for (int32_t k = b + 1; k < e; ++k) t = t + val[k] * w[ci[k]];
+  }
+  w_out[i] = w[i] - t / m[i];
+}
+
 // position of the diagonal entry of each row
 __global__ void k_diag_pos(int32_t n, const int32_t *rp, const int32_t *ci, int32_t *dpos) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -938,6 +953,26 @@ amg_status build_hierarchy(amg_hierarchy *h, const amg_csr *A) {
       AMG_HIP(hipMemcpyAsync(L0.w, P.w, sizeof(double) * n0, hipMemcpyDeviceToDevice, s));
     else
       k_fill<double><<<grid(n0), kBlock, 0, s>>>(L0.w, 1.0, n0);
+    // algebraically smooth w: w_sweeps l1-Jacobi sweeps on A w = 0 from the
+    // sample; the result must still have no zero entry
+    if (P.w_sweeps > 0) {
+      double *m, *minv, *w2;
+      AMG_TRY(tmp.get(&m, n0));
+      AMG_TRY(tmp.get(&minv, n0));
+      AMG_TRY(tmp.get(&w2, n0));
+      k_l1_diag<<<grid(n0), kBlock, 0, s>>>(n0, L0.rp, L0.ci, L0.val, m, minv);
+      double *src = L0.w, *dst = w2;
+      for (int32_t k = 0; k < P.w_sweeps; ++k) {
+        k_smooth_w<<<grid(n0), kBlock, 0, s>>>(n0, L0.rp, L0.ci, L0.val, m, src, dst);
+        std::swap(src, dst);
+      }
+      if (src != L0.w)
+        AMG_HIP(hipMemcpyAsync(L0.w, src, sizeof(double) * n0, hipMemcpyDeviceToDevice, s));
+      k_fill<int32_t><<<1, 1, 0, s>>>(err, 0, 1);
+      k_check_w<<<grid(n0), kBlock, 0, s>>>(n0, L0.w, err);
+      AMG_TRY(read_i32(err, &herr, s));
+      AMG_TRY(map_err(herr));
+    }
   }
 
   double t_match = 0, t_number = 0, t_rap = 0, t_compose = 0;

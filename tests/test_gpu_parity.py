@@ -281,3 +281,30 @@ def test_pcg_extra_sweeps_match_oracle(orc, pre, post):
     assert abs(info["iterations"] - io["iterations"]) <= 1
     xo, _ = ho.pcg(b, rtol=0.0, maxit=info["iterations"], pre=pre, post=post)
     assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8
+
+
+@pytest.mark.parametrize("case,sweeps,nu", [("poisson20", 3, 4), ("poisson20", 4, 2),
+                                            ("aniso24_random_sample", 3, 3)])
+def test_setup_smoothed_w_bit_exact(orc, case, sweeps, nu):
+    """w = nu l1-Jacobi sweeps on A w = 0 from the sample (ones, or a random
+    positive sample): the smoothed w and the whole hierarchy are bit-exact."""
+    from paper_2006_16147_amd import amg
+
+    if case == "poisson20":
+        A = inputs.laplacian7(20)
+        w0 = None
+    else:
+        rng = np.random.default_rng(2)
+        A = inputs.diffusion7(24, *inputs.block_log_uniform_eps(24, 8, rng), 1.0)
+        w0 = np.random.default_rng(9).uniform(0.5, 1.5, A.n)
+    kw = {"w": to_dev(w0)} if w0 is not None else {}
+    h = setup(A, sweeps=sweeps, w_sweeps=nu, max_coarse=60, **kw)
+    ws = orc.smooth_w(A, nu, w0)
+    np.testing.assert_array_equal(h.w(0), ws)
+    ho = orc.Hierarchy(A, w=ws, sweeps=sweeps, max_coarse=60)
+    assert_same_hierarchy(h, ho)
+    b = np.random.default_rng(4).uniform(-1, 1, A.n)
+    st, info, x = solve(h, b, rtol=1e-8, maxit=300)
+    assert st == 0 and info["converged"]
+    xo, _ = ho.pcg(b, rtol=0.0, maxit=info["iterations"])
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8

@@ -20,6 +20,7 @@ SRC = os.path.join(ROOT, "oracle", "oracle.c")
 INV = "tests/test_oracle_invariants.py::"
 PIN = "tests/test_oracle_paper_pins.py::"
 KC = "tests/test_oracle_kcycle.py::"
+SW = "tests/test_oracle_smooth_w.py::"
 
 # (mistake, text in oracle.c, replacement, pin test that must reject it)
 MUTATIONS = [
@@ -100,6 +101,10 @@ MUTATIONS = [
     ("outer FCG: sign of beta",
      "double beta = -dot(n, z, q) / pq;", "double beta = dot(n, z, q) / pq;",
      KC + "test_fcg_with_vcycle_equals_pcg"),
+    ("smooth w: sweep with the wrong sign",
+     "for (int32_t i = 0; i < n; ++i) w[i] = w[i] - t[i] / m[i];",
+     "for (int32_t i = 0; i < n; ++i) w[i] = w[i] + t[i] / m[i];",
+     SW + "test_every_sweep_lowers_the_energy"),
     ("K-cycle: coarse correction by the plain cycle (no FCG)",
      "if (kcycle && l + 1 < L) fcg2(h, l + 1, pre, post, rc, zc);",
      "if (0 && kcycle && l + 1 < L) fcg2(h, l + 1, pre, post, rc, zc);",
