@@ -270,8 +270,10 @@ __global__ void k_gather_f64(int32_t n, const int32_t *perm, const double *src, 
   if (k < n) dst[k] = src[perm[k]];
 }
 
+// Entries of each 64-row slice (width = longest row, times 64), and their
+// 64-bit total: the int32 offsets of the format must not overflow.
 __global__ void k_sell_width(int32_t n, int32_t ns, const int32_t *rp, const int32_t *perm,
-                             int32_t *w64) {
+                             int32_t *w64, unsigned long long *total) {
   const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= ns) return;
   const int32_t r0 = s * kSlice, r1 = min(n, r0 + kSlice);
@@ -280,7 +282,9 @@ __global__ void k_sell_width(int32_t n, int32_t ns, const int32_t *rp, const int
     const int32_t i = perm[k];
     w = max(w, rp[i + 1] - rp[i]);
   }
-  w64[s] = w * kSlice;
+  const int64_t e = (int64_t)w * kSlice;
+  w64[s] = e > INT32_MAX ? INT32_MAX : (int32_t)e;
+  atomicAdd(total, (unsigned long long)e);
 }
 
 // Row k of the permuted matrix is original row perm[k] with columns renumbered
@@ -1360,8 +1364,19 @@ amg_status build_solve_formats(amg_hierarchy *h) {
       S.nslices = ceil_div(L.n, kSlice);
       int32_t *w64;
       AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&w64), sizeof(int32_t) * S.nslices + 16, s));
+      unsigned long long *total;
+      AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&total), sizeof(unsigned long long), s));
+      AMG_HIP(hipMemsetAsync(total, 0, sizeof(unsigned long long), s));
       AMG_TRY(dalloc(h, &S.sptr, (size_t)S.nslices + 1));
-      k_sell_width<<<grid1(S.nslices), kBlock, 0, s>>>(L.n, S.nslices, L.rp, L.perm, w64);
+      k_sell_width<<<grid1(S.nslices), kBlock, 0, s>>>(L.n, S.nslices, L.rp, L.perm, w64, total);
+      unsigned long long htotal = 0;
+      AMG_HIP(hipMemcpyAsync(&htotal, total, sizeof(htotal), hipMemcpyDeviceToHost, s));
+      AMG_HIP(hipStreamSynchronize(s));
+      AMG_HIP(hipFreeAsync(total, s));
+      if (htotal > (unsigned long long)INT32_MAX) {
+        (void)hipFreeAsync(w64, s);
+        return AMG_ERR_ARG;  // padded rows exceed the format's 32-bit offsets
+      }
       AMG_TRY(scan_exclusive_i32(w64, S.sptr, S.nslices, s));
       AMG_HIP(hipFreeAsync(w64, s));
       int32_t padded = 0;
