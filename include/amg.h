@@ -127,7 +127,9 @@ void amg_params_default(amg_params *p);
  * Errors: AMG_ERR_ARG (n < 1, bad sizes, unsorted or out-of-range columns,
  * zero or non-finite w before or after smoothing, bad params, or a level
  * whose 64-row slices padded to their longest row exceed 2^31 - 1 stored
- * entries), AMG_ERR_NOT_SYMMETRIC, AMG_ERR_NOT_SPD
+ * entries, or a pairwise Galerkin row that gathers more than 2048 fine
+ * entries, i.e. two matched rows with more than 2048 entries together),
+ * AMG_ERR_NOT_SYMMETRIC, AMG_ERR_NOT_SPD
  * (diagonal <= 0 or coarsest Cholesky failure), AMG_ERR_STALL (a level that
  * no longer coarsens holds more than AMG_MAX_DENSE unknowns), AMG_ERR_OOM,
  * AMG_ERR_HIP. On error *out is NULL. */
