@@ -205,7 +205,9 @@ amg_status amg_matching_rounds(const amg_hierarchy *h, int32_t l, int32_t *round
  * 1 = post-smoothing (on level 0 with the CG dot product),
  * 2 = post-smoothing of level l + 1 fused with the prolongation into level l
  *     (level l + 1 must not be the coarsest), 3 = same as 2,
- * 4 = outer-CG SpMV with its dot product (level 0). */
+ * 4 = outer-CG SpMV with its dot product (level 0),
+ * 5 = one whole V-cycle as inside the solve (level ignored; *bytes its
+ *     algorithmic total; AMG_ERR_ARG for a K-cycle hierarchy). */
 amg_status amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
                            double *ms, double *bytes);
 

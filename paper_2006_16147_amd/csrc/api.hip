@@ -339,7 +339,7 @@ amg_status amg_matching_rounds(const amg_hierarchy *h, int32_t l, int32_t *round
 
 amg_status amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
                            double *ms, double *bytes) {
-  if (!h || !ms || !bytes || kernel < 0 || kernel > 4) return AMG_ERR_ARG;
+  if (!h || !ms || !bytes || kernel < 0 || kernel > 5) return AMG_ERR_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return AMG_ERR_HIP;
   AMG_TRY(join_user_stream(h));
   return time_kernel(h, kernel, level, reps, ms, bytes);

@@ -1627,9 +1627,57 @@ amg_status pcg(amg_hierarchy *h, const double *b_user, double *x_user, double rt
   return st;
 }
 
+namespace {
+
+// One V-cycle exactly as the solve runs it (aggregate-major vectors, no
+// permutation, no host work between launches), timed with HIP events; bytes
+// = the cycle's algorithmic HBM bytes (0 for a K-cycle hierarchy, whose
+// traffic depends on the level visits).
+amg_status time_vcycle(amg_hierarchy *h, int32_t reps, double *ms, double *bytes) {
+  if (reps < 1 || h->params.cycle != AMG_CYCLE_V) return AMG_ERR_ARG;
+  hipStream_t s = h->stream;
+  const int32_t *done = h->zero_flag;
+  AMG_TRY(vcycle_perm(h, h->r, h->z, false, done));  // warm
+  hipEvent_t e0, e1;
+  AMG_HIP(hipEventCreate(&e0));
+  AMG_HIP(hipEventCreate(&e1));
+  AMG_HIP(hipEventRecord(e0, s));
+  for (int32_t k = 0; k < reps; ++k) AMG_TRY(vcycle_perm(h, h->r, h->z, false, done));
+  AMG_HIP(hipEventRecord(e1, s));
+  AMG_HIP(hipEventSynchronize(e1));
+  float t = 0.f;
+  AMG_HIP(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = (double)t / reps;
+  // per level l < L: down step z(V+4) + 4(n+1) + n(Vr+3V) + n_c(V+4) and the
+  // prolongation into it n(3V+4); per coarse level 0 < c < L its
+  // post-smoothing z(V+4) + 4(n+1) + 3V n; the coarsest 8 n_L^2 + V n_L; the
+  // level-0 post-smoothing z(V+4) + 4(n+1) + n(16+2V)
+  const int32_t L = (int32_t)h->lv.size() - 1;
+  const double V = h->params.precision == AMG_FP32 ? 4.0 : 8.0;
+  const double nL = h->C.n;
+  double b = 8.0 * nL * nL + (L == 0 ? 16.0 : V) * nL;
+  for (int32_t l = 0; l < L; ++l) {
+    const double n = h->lv[l].n, z = (double)h->lv[l].nnz, nc = h->lv[l + 1].n;
+    const double Vr = l == 0 ? 8.0 : V;
+    b += z * (V + 4) + 4 * (n + 1) + n * (Vr + 3 * V) + nc * (V + 4) + n * (3 * V + 4);
+    if (l > 0) b += z * (V + 4) + 4 * (n + 1) + 3 * V * n;
+  }
+  if (L > 0) {
+    const double n0 = h->lv[0].n, z0 = (double)h->lv[0].nnz;
+    b += z0 * (V + 4) + 4 * (n0 + 1) + n0 * (16 + 2 * V);
+  }
+  *bytes = b;
+  return AMG_OK;
+}
+
+}  // namespace
+
 amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
                        double *ms, double *bytes) {
   const int32_t L = (int32_t)h->lv.size() - 1;
+  if (kernel == 5) return time_vcycle(h, reps, ms, bytes);
   if (level < 0 || level >= L || reps < 1 || kernel < 0 || kernel > 4) return AMG_ERR_ARG;
   if (kernel == 4 && level != 0) return AMG_ERR_ARG;
   if ((kernel == 2 || kernel == 3) && level + 1 >= L) return AMG_ERR_ARG;

@@ -308,3 +308,20 @@ def test_setup_smoothed_w_bit_exact(orc, case, sweeps, nu):
     assert st == 0 and info["converged"]
     xo, _ = ho.pcg(b, rtol=0.0, maxit=info["iterations"])
     assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8
+
+
+def test_time_whole_vcycle_reports_bytes_and_rejects_kcycle():
+    """amg_time_kernel id 5: one V-cycle as inside the solve, with the
+    cycle's algorithmic bytes; a K-cycle hierarchy has no fixed byte count."""
+    import bench
+    from paper_2006_16147_amd import amg
+
+    A = inputs.laplacian7(24)
+    for prec, V in ((amg.FP64, 8.0), (amg.FP32, 4.0)):
+        h = setup(A, precision=prec)
+        ms, by = h.time_kernel(5, 0, reps=5)
+        assert ms > 0.0
+        assert abs(by - bench.vcycle_bytes(h.sizes(), h.nnzs(), V, h.sizes()[-1])) < 1.0
+    hk = setup(A, cycle=amg.CYCLE_K)
+    with pytest.raises(amg.AmgError):
+        hk.time_kernel(5, 0, reps=2)
