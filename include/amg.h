@@ -76,7 +76,12 @@ enum { AMG_CYCLE_V = 0, AMG_CYCLE_K = 1 };
 /* amg_params.flags */
 enum {
   AMG_FLAG_NO_GRAPH = 1,   /* launch the solve kernels directly, no hipGraph */
-  AMG_FLAG_SKIP_CHECKS = 2 /* skip the symmetry/structure validation pass */
+  AMG_FLAG_SKIP_CHECKS = 2, /* skip the symmetry/structure validation pass */
+  /* keep level 0's values in FP64 only. By default, when every value of A is
+   * an FP32 number, the FP64 products of level 0 (outer CG SpMV, level-0
+   * post-smoothing) read an FP32 copy of A: the same numbers, half the value
+   * bytes, bit-identical results. */
+  AMG_FLAG_NO_VALUE_COMPRESSION = 4
 };
 
 /* Largest coarsest level the dense Cholesky accepts (AMG_ERR_STALL above). */

@@ -24,7 +24,7 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 FP64, FP32 = 0, 1
 CYCLE_V, CYCLE_K = 0, 1
-FLAG_NO_GRAPH, FLAG_SKIP_CHECKS = 1, 2
+FLAG_NO_GRAPH, FLAG_SKIP_CHECKS, FLAG_NO_VALUE_COMPRESSION = 1, 2, 4
 MAX_DENSE = 4096
 
 EXPORTED_SYMBOLS = (

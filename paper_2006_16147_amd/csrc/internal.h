@@ -70,6 +70,9 @@ struct Sell {
   double *s64 = nullptr;
   float *s32 = nullptr;
   int32_t max_width = 0;  // widest slice (entries per row); set for levels of <= 1024 rows
+  // every value of A is an FP32 number: v32 holds A exactly and the FP64
+  // kernels of level 0 read it (half the value bytes, identical arithmetic)
+  bool exact32 = false;
 };
 
 // A level holds its setup data in the original numbering of that level and
@@ -223,9 +226,12 @@ __device__ __forceinline__ T ld_stream(const T *p) {
 // loads, then all its gathers, before the first product, which keeps eight
 // gathers per lane in flight instead of one.
 constexpr int kRowBatch = 8;
-template <typename TV, typename X>
-__device__ __forceinline__ TV sell_dot(const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                       int32_t base, int32_t w, X x) {
+// (TA: the stored value type, converted exactly to the accumulation type TV;
+// FP32-stored values are used only where every value is an FP32 number)
+template <typename TV, typename TA, typename X>
+__device__ __forceinline__ TV sell_dot_t(const int32_t *__restrict__ col,
+                                         const TA *__restrict__ val, int32_t base, int32_t w,
+                                         X x) {
   TV acc = 0;
   for (int32_t k0 = 0; k0 < w; k0 += kRowBatch) {
     int32_t c[kRowBatch];
@@ -237,7 +243,7 @@ __device__ __forceinline__ TV sell_dot(const int32_t *__restrict__ col, const TV
       if (k0 + u < w) {
         const int32_t idx = base + (k0 + u) * kSlice;
         c[u] = ld_stream(&col[idx]);
-        v[u] = ld_stream(&val[idx]);
+        v[u] = (TV)ld_stream(&val[idx]);
       }
     }
 #pragma unroll
@@ -247,6 +253,12 @@ __device__ __forceinline__ TV sell_dot(const int32_t *__restrict__ col, const TV
       if (k0 + u < w) acc += v[u] * g[u];
   }
   return acc;
+}
+
+template <typename TV, typename X>
+__device__ __forceinline__ TV sell_dot(const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                       int32_t base, int32_t w, X x) {
+  return sell_dot_t<TV, TV>(col, val, base, w, x);
 }
 
 // grid helpers

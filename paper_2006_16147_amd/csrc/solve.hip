@@ -335,6 +335,12 @@ __global__ void k_sell_fill(int32_t n, int32_t ns, const int32_t *rp, const int3
   }
 }
 
+// flags a value that an FP32 number cannot hold exactly (or a NaN)
+__global__ void k_not_fp32_exact(int64_t n, const double *a, int32_t *flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !((double)(float)a[i] == a[i])) *flag = 1;
+}
+
 __global__ void k_demote(int64_t n, const double *a, float *b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (float)a[i];
@@ -358,11 +364,13 @@ __global__ void k_permute_out(int32_t n, const int32_t *__restrict__ perm,
 // ---------------------------------------------------------------------------
 
 // Down step on level l for the coarse positions [J0, J0 + G) of this block:
-// z = M^-1 r (FROM_Z = false; the residual uses the stored A M^-1) or, after
-// extra pre-smoothing sweeps, the given z (FROM_Z = true, plain A); then
+// z = M^-1 r with the residual through the stored A M^-1 (kPreScaled) or,
+// after extra pre-smoothing sweeps, the given z (kPreFromZ, plain A); then
 // r_{l+1}(J) = sum over the segment of J, in order, of p_k (r - A z)_k.
 // The block's fine rows are the union of its segments (at most kBlock rows).
-template <typename TV, typename TR, bool FROM_Z>
+enum PreMode : int { kPreScaled = 0, kPreFromZ = 1 };
+
+template <typename TV, typename TR, int MODE>
 __global__ void __launch_bounds__(kBlock) k_pre_restrict(
     int32_t nc, int32_t G, const int32_t *__restrict__ seg, const int32_t *__restrict__ sptr,
     const int32_t *__restrict__ col, const TV *__restrict__ val, const TV *__restrict__ minv,
@@ -377,10 +385,11 @@ __global__ void __launch_bounds__(kBlock) k_pre_restrict(
   if (row < f1) {
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
-    const TV acc = FROM_Z ? sell_dot(col, val, base, w, [&](int32_t c) { return z[c]; })
+    const TV acc =
+        MODE == kPreFromZ ? sell_dot(col, val, base, w, [&](int32_t c) { return z[c]; })
                           : sell_dot(col, val, base, w, [&](int32_t c) { return (TV)r[c]; });
     const TV ri = (TV)r[row];
-    if (!FROM_Z) z[row] = ri * minv[row];
+    if (MODE == kPreScaled) z[row] = ri * minv[row];
     sh[threadIdx.x] = pp[row] * (ri - acc);
   }
   __syncthreads();
@@ -395,10 +404,10 @@ __global__ void __launch_bounds__(kBlock) k_pre_restrict(
 
 // y = z + M^-1 (r - A z); with DOT also the block partials of (r, y)
 // (with a dot partner dv, the partials are of (dv, y) instead)
-template <typename TV, typename TR, typename TO, bool DOT>
+template <typename TV, typename TR, typename TO, bool DOT, typename TA = TV>
 __global__ void __launch_bounds__(kBlock) k_post(
     int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
-    const TV *__restrict__ val, const TV *__restrict__ minv, const TR *__restrict__ r,
+    const TA *__restrict__ val, const TV *__restrict__ minv, const TR *__restrict__ r,
     const TV *__restrict__ z, TO *__restrict__ y, double *__restrict__ partials,
     const int32_t *__restrict__ done, const double *__restrict__ dv = nullptr) {
   if (*done) return;
@@ -408,7 +417,7 @@ __global__ void __launch_bounds__(kBlock) k_post(
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
-    const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return z[c]; });
+    const TV acc = sell_dot_t<TV, TA>(col, val, base, w, [&](int32_t c) { return z[c]; });
     const TR rr = r[row];
     const TO yo = (TO)(z[row] + ((TV)rr - acc) * minv[row]);
     y[row] = yo;
@@ -639,10 +648,10 @@ __global__ void k_scal_init(PcgScal *s, double rtol, int32_t maxit) {
 
 // MODE 0: r = b - A x and partials of (b, b), (r, r)
 // MODE 1: partials of ||b - A x||^2 only
-template <int MODE>
+template <int MODE, typename TA>
 __global__ void __launch_bounds__(kBlock) k_residual_norms(
     int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
-    const double *__restrict__ val, const double *__restrict__ b, const double *__restrict__ x,
+    const TA *__restrict__ val, const double *__restrict__ b, const double *__restrict__ x,
     double *__restrict__ r, double *__restrict__ partials) {
   constexpr int NV = MODE == 0 ? 2 : 1;
   int32_t rb, re;
@@ -652,7 +661,7 @@ __global__ void __launch_bounds__(kBlock) k_residual_norms(
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
-    const double acc = sell_dot(col, val, base, w, [&](int32_t c) { return x[c]; });
+    const double acc = sell_dot_t<double, TA>(col, val, base, w, [&](int32_t c) { return x[c]; });
     const double bi = b[row];
     const double ri = bi - acc;
     if (MODE == 0) {
@@ -673,9 +682,10 @@ __global__ void k_zero_if_zero_rhs(int32_t n, double *x, const PcgScal *scal) {
 }
 
 // q = A p ; partials of (p, q)
+template <typename TA>
 __global__ void __launch_bounds__(kBlock) k_spmv_dot(
     int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
-    const double *__restrict__ val, const double *__restrict__ p, double *__restrict__ q,
+    const TA *__restrict__ val, const double *__restrict__ p, double *__restrict__ q,
     double *__restrict__ partials, const int32_t *__restrict__ done) {
   if (*done) return;
   int32_t rb, re;
@@ -684,7 +694,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot(
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
-    const double acc = sell_dot(col, val, base, w, [&](int32_t c) { return p[c]; });
+    const double acc = sell_dot_t<double, TA>(col, val, base, w, [&](int32_t c) { return p[c]; });
     q[row] = acc;
     d[0] += p[row] * acc;
   }
@@ -1110,9 +1120,9 @@ TV *launch_down(amg_hierarchy *h, int32_t l, const TR *r, const int32_t *done) {
   const int32_t G = coarse_per_block(h);
   const int32_t grid = ceil_div(C.n, G);
   if (h->params.pre == 1) {
-    k_pre_restrict<TV, TR, false><<<grid, kBlock, 0, s>>>(C.n, G, F.seg, F.S.sptr, F.S.col,
-                                                         svals<TV>(F), minv<TV>(F), ppv<TV>(F), r,
-                                                         z, (TV *)C.r, done);
+    k_pre_restrict<TV, TR, kPreScaled><<<grid, kBlock, 0, s>>>(C.n, G, F.seg, F.S.sptr, F.S.col,
+                                                              svals<TV>(F), minv<TV>(F),
+                                                              ppv<TV>(F), r, z, (TV *)C.r, done);
     return z;
   }
   const Geom g = geom(F.n);
@@ -1123,9 +1133,9 @@ TV *launch_down(amg_hierarchy *h, int32_t l, const TR *r, const int32_t *done) {
                                                        nullptr, done);
     std::swap(z, tmp);
   }
-  k_pre_restrict<TV, TR, true><<<grid, kBlock, 0, s>>>(C.n, G, F.seg, F.S.sptr, F.S.col,
-                                                      vals<TV>(F), minv<TV>(F), ppv<TV>(F), r, z,
-                                                      (TV *)C.r, done);
+  k_pre_restrict<TV, TR, kPreFromZ><<<grid, kBlock, 0, s>>>(C.n, G, F.seg, F.S.sptr, F.S.col,
+                                                           vals<TV>(F), minv<TV>(F), ppv<TV>(F),
+                                                           r, z, (TV *)C.r, done);
   return z;
 }
 
@@ -1192,21 +1202,33 @@ void vcycle_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const in
   TV *z = zb[0], *tmp = (TV *)F.y;
   if (tmp == z) tmp = (TV *)F.z;
   const Geom g = geom(F.n);
+  // an FP64 hierarchy reads A from its exact FP32 copy when there is one
+  const bool a32 = sizeof(TV) == 8 && F.S.exact32;
   for (int32_t k = 1; k < h->params.post; ++k) {
-    k_post<TV, double, TV, false><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
-                                                           vals<TV>(F), minv<TV>(F), r0, z, tmp,
-                                                           nullptr, done);
+    if (a32)
+      k_post<TV, double, TV, false, float><<<g.grid, kBlock, 0, s>>>(
+          F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), r0, z, tmp, nullptr, done);
+    else
+      k_post<TV, double, TV, false><<<g.grid, kBlock, 0, s>>>(
+          F.n, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), r0, z, tmp, nullptr, done);
     std::swap(z, tmp);
   }
   if (dot) {
-    k_post<TV, double, double, true><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
-                                                              vals<TV>(F), minv<TV>(F), r0, z, z0,
-                                                              h->partials, done);
+    if (a32)
+      k_post<TV, double, double, true, float><<<g.grid, kBlock, 0, s>>>(
+          F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), r0, z, z0, h->partials, done);
+    else
+      k_post<TV, double, double, true><<<g.grid, kBlock, 0, s>>>(
+          F.n, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), r0, z, z0, h->partials,
+          done);
     finalize(h, kFinRZ, g.grid, done);
   } else {
-    k_post<TV, double, double, false><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
-                                                               vals<TV>(F), minv<TV>(F), r0, z,
-                                                               z0, nullptr, done);
+    if (a32)
+      k_post<TV, double, double, false, float><<<g.grid, kBlock, 0, s>>>(
+          F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), r0, z, z0, nullptr, done);
+    else
+      k_post<TV, double, double, false><<<g.grid, kBlock, 0, s>>>(
+          F.n, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), r0, z, z0, nullptr, done);
   }
 }
 
@@ -1357,7 +1379,21 @@ amg_status build_solve_formats(amg_hierarchy *h) {
     // level 0 needs FP64 values for the outer CG; V-cycle levels need the
     // hierarchy precision (plain and scaled); the coarsest uses A_L^-1 only
     const bool need64 = (l == 0) || (!coarsest && !fp32);
-    const bool need32 = !coarsest && fp32;
+    bool need32 = !coarsest && fp32;
+    if (l == 0 && !(h->params.flags & AMG_FLAG_NO_VALUE_COMPRESSION)) {
+      // every value of A an FP32 number: the FP64 products of level 0 read
+      // the exact FP32 copy (identical arithmetic, half the value bytes)
+      int32_t *flag;
+      AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&flag), sizeof(int32_t), s));
+      AMG_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+      k_not_fp32_exact<<<grid1(L.nnz), kBlock, 0, s>>>(L.nnz, L.val, flag);
+      int32_t hflag = 1;
+      AMG_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      AMG_HIP(hipStreamSynchronize(s));
+      AMG_HIP(hipFreeAsync(flag, s));
+      L.S.exact32 = hflag == 0;
+      need32 = need32 || L.S.exact32;
+    }
     if (need64 || need32) {
       Sell &S = L.S;
       S.n = L.n;
@@ -1396,7 +1432,7 @@ amg_status build_solve_formats(amg_hierarchy *h) {
       if (need64) AMG_TRY(dalloc(h, &S.v64, (size_t)padded));
       if (need32) AMG_TRY(dalloc(h, &S.v32, (size_t)padded));
       if (!coarsest && !fp32) AMG_TRY(dalloc(h, &S.s64, (size_t)padded));
-      if (need32) AMG_TRY(dalloc(h, &S.s32, (size_t)padded));
+      if (!coarsest && fp32) AMG_TRY(dalloc(h, &S.s32, (size_t)padded));
       k_sell_fill<<<ceil_div((int64_t)S.nslices * kSlice, kBlock), kBlock, 0, s>>>(
           L.n, S.nslices, L.rp, L.ci, L.val, L.perm, L.iperm, L.minv64, S.sptr, S.col, S.v64,
           S.v32, S.s64, S.s32);
@@ -1507,8 +1543,12 @@ void cg_iteration(amg_hierarchy *h) {
   const int32_t n = L0.n;
   const int32_t *done = &h->scal->done;
   const Geom g = geom(n);
-  k_spmv_dot<<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, h->p, h->q,
-                                       h->partials, done);
+  if (L0.S.exact32)
+    k_spmv_dot<float><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v32, h->p,
+                                                h->q, h->partials, done);
+  else
+    k_spmv_dot<double><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64,
+                                                 h->p, h->q, h->partials, done);
   finalize(h, kFinPQ, g.grid, done);
   k_update_xr<<<g.grid, kBlock, 0, s>>>(n, g.chunk, h->x, h->r, h->p, h->q, h->partials, h->scal,
                                         done);
@@ -1572,8 +1612,13 @@ amg_status pcg(amg_hierarchy *h, const double *b_user, double *x_user, double rt
   k_permute_in<<<grid1(n), kBlock, 0, s>>>(n, L0.perm, b_user, h->b);
   k_permute_in<<<grid1(n), kBlock, 0, s>>>(n, L0.perm, x_user, h->x);
   k_scal_init<<<1, 1, 0, s>>>(h->scal, rtol, maxit);
-  k_residual_norms<0><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, h->b,
-                                               h->x, h->r, h->partials);
+  if (L0.S.exact32)
+    k_residual_norms<0, float><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col,
+                                                         L0.S.v32, h->b, h->x, h->r, h->partials);
+  else
+    k_residual_norms<0, double><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col,
+                                                          L0.S.v64, h->b, h->x, h->r,
+                                                          h->partials);
   finalize(h, kFinInit, g.grid, nullptr);
   k_zero_if_zero_rhs<<<grid1(n), kBlock, 0, s>>>(n, h->x, h->scal);
   if (h->params.cycle == AMG_CYCLE_K) AMG_TRY(kcycle_perm(h, h->r, h->z, nullptr, done));
@@ -1607,8 +1652,14 @@ amg_status pcg(amg_hierarchy *h, const double *b_user, double *x_user, double rt
     AMG_HIP(hipGetLastError());
     queued += c;
   }
-  k_residual_norms<1><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64, h->b,
-                                               h->x, nullptr, h->partials);
+  if (L0.S.exact32)
+    k_residual_norms<1, float><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col,
+                                                         L0.S.v32, h->b, h->x, nullptr,
+                                                         h->partials);
+  else
+    k_residual_norms<1, double><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col,
+                                                          L0.S.v64, h->b, h->x, nullptr,
+                                                          h->partials);
   finalize(h, kFinTrue, g.grid, nullptr);
   k_permute_out<<<grid1(n), kBlock, 0, s>>>(n, L0.perm, h->x, x_user);
   AMG_HIP(hipMemcpyAsync(h->scal_host, h->scal, sizeof(PcgScal), hipMemcpyDeviceToHost, s));
@@ -1666,7 +1717,8 @@ amg_status time_vcycle(amg_hierarchy *h, int32_t reps, double *ms, double *bytes
   }
   if (L > 0) {
     const double n0 = h->lv[0].n, z0 = (double)h->lv[0].nnz;
-    b += z0 * (V + 4) + 4 * (n0 + 1) + n0 * (16 + 2 * V);
+    const double Va = V == 8.0 && h->lv[0].S.exact32 ? 4.0 : V;  // level-0 A as stored
+    b += z0 * (Va + 4) + 4 * (n0 + 1) + n0 * (16 + 2 * V);
   }
   *bytes = b;
   return AMG_OK;
@@ -1696,15 +1748,15 @@ amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t 
       case 0:  // pre-smoothing + residual + restriction on `level`
         if (fp32) {
           if (level == 0)
-            k_pre_restrict<float, double, false><<<ceil_div(C.n, G), kBlock, 0, s>>>(
+            k_pre_restrict<float, double, kPreScaled><<<ceil_div(C.n, G), kBlock, 0, s>>>(
                 C.n, G, F.seg, F.S.sptr, F.S.col, F.S.s32, F.sminv32, F.pp32, h->r, (float *)F.z,
                 (float *)C.r, done);
           else
-            k_pre_restrict<float, float, false><<<ceil_div(C.n, G), kBlock, 0, s>>>(
+            k_pre_restrict<float, float, kPreScaled><<<ceil_div(C.n, G), kBlock, 0, s>>>(
                 C.n, G, F.seg, F.S.sptr, F.S.col, F.S.s32, F.sminv32, F.pp32, (const float *)F.r,
                 (float *)F.z, (float *)C.r, done);
         } else {
-          k_pre_restrict<double, double, false><<<ceil_div(C.n, G), kBlock, 0, s>>>(
+          k_pre_restrict<double, double, kPreScaled><<<ceil_div(C.n, G), kBlock, 0, s>>>(
               C.n, G, F.seg, F.S.sptr, F.S.col, F.S.s64, F.sminv64, F.pp64,
               level == 0 ? h->r : (const double *)F.r, (double *)F.z, (double *)C.r, done);
         }
@@ -1720,7 +1772,11 @@ amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t 
                 F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, F.sminv32, (const float *)F.r,
                 (const float *)F.z, (float *)F.y, nullptr, done);
         } else {
-          if (level == 0)
+          if (level == 0 && F.S.exact32)
+            k_post<double, double, double, true, float><<<g.grid, kBlock, 0, s>>>(
+                F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, F.sminv64, h->r, (const double *)F.z,
+                h->z, h->partials, done);
+          else if (level == 0)
             k_post<double, double, double, true><<<g.grid, kBlock, 0, s>>>(
                 F.n, g.chunk, F.S.sptr, F.S.col, F.S.v64, F.sminv64, h->r, (const double *)F.z,
                 h->z, h->partials, done);
@@ -1742,8 +1798,12 @@ amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t 
               (const double *)C.z, F.seg, F.aggp, F.pp64, (double *)F.t, done);
         break;
       default:
-        k_spmv_dot<<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col, F.S.v64, h->p,
-                                             h->q, h->partials, done);
+        if (F.S.exact32)
+          k_spmv_dot<float><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32,
+                                                      h->p, h->q, h->partials, done);
+        else
+          k_spmv_dot<double><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
+                                                       F.S.v64, h->p, h->q, h->partials, done);
         break;
     }
   };
@@ -1766,15 +1826,16 @@ amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t 
     case 0:  // A M^-1, r, minv, p read; z, r_c written; segment offsets
       *bytes = nnz * (V + 4) + 4 * (n + 1) + n * (Vr + 3 * V) + nc * (V + 4);
       break;
-    case 1:  // A, r, z, minv read; y written
-      *bytes = nnz * (V + 4) + 4 * (n + 1) + n * (Vr + V + V + Vr);
+    case 1:  // A, r, z, minv read; y written (level 0: A from its exact FP32 copy if any)
+      *bytes = nnz * ((level == 0 && F.S.exact32 ? 4.0 : V) + 4) + 4 * (n + 1) +
+               n * (Vr + V + V + Vr);
       break;
     case 2:
     case 3:  // coarse A, r_c, z_c, minv_c; fine z read + written, p, positions
       *bytes = nnzc * (V + 4) + 4 * (nc + 1) + nc * (3 * V + 4) + n * (3 * V + 4);
       break;
-    default:  // A, p read; q written
-      *bytes = nnz * 12 + 4 * (n + 1) + n * 16;
+    default:  // A (8 or, from the exact FP32 copy, 4 bytes per value), p read; q written
+      *bytes = nnz * ((F.S.exact32 ? 4.0 : 8.0) + 4) + 4 * (n + 1) + n * 16;
       break;
   }
   return AMG_OK;

@@ -321,7 +321,42 @@ def test_time_whole_vcycle_reports_bytes_and_rejects_kcycle():
         h = setup(A, precision=prec)
         ms, by = h.time_kernel(5, 0, reps=5)
         assert ms > 0.0
-        assert abs(by - bench.vcycle_bytes(h.sizes(), h.nnzs(), V, h.sizes()[-1])) < 1.0
+        # the 7-point Laplacian's values are FP32 numbers: level 0 reads 4-byte values
+        assert abs(by - bench.vcycle_bytes(h.sizes(), h.nnzs(), V, h.sizes()[-1], a0=4.0)) < 1.0
     hk = setup(A, cycle=amg.CYCLE_K)
     with pytest.raises(amg.AmgError):
         hk.time_kernel(5, 0, reps=2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_exact_fp32_level0_values_are_lossless(precision):
+    """When every value of A is an FP32 number (the 7-point Laplacian), level
+    0's FP64 products read an FP32 copy of A: the solve and the V-cycle are
+    bit-identical to the FP64-value path, and the byte count shows the copy
+    in use. An operator with other values keeps FP64 values."""
+    import torch
+
+    from paper_2006_16147_amd import amg
+
+    prec = amg.FP32 if precision == "fp32" else amg.FP64
+    c = inputs.small_case(20, seed=0)
+    A, b = c["A"], c["b"]
+    on = setup(A, precision=prec)
+    off = setup(A, precision=prec, flags=amg.FLAG_NO_VALUE_COMPRESSION)
+    _, by_on = on.time_kernel(4, 0, reps=1)
+    _, by_off = off.time_kernel(4, 0, reps=1)
+    assert by_off - by_on == 4 * A.nnz
+    r = to_dev(np.random.default_rng(3).uniform(-1, 1, A.n))
+    z1, z2 = torch.zeros_like(r), torch.zeros_like(r)
+    amg.amg_vcycle_apply(on, r, z1)
+    amg.amg_vcycle_apply(off, r, z2)
+    assert torch.equal(z1, z2)
+    s1, i1, x1 = solve(on, b, rtol=1e-10)
+    s2, i2, x2 = solve(off, b, rtol=1e-10)
+    assert s1 == s2 == 0 and i1["iterations"] == i2["iterations"]
+    np.testing.assert_array_equal(x1.view(np.uint64), x2.view(np.uint64))
+    rng = np.random.default_rng(2)
+    Aa = inputs.diffusion7(16, *inputs.block_log_uniform_eps(16, 8, rng), 1.0)
+    ha = setup(Aa, precision=prec)
+    ha_off = setup(Aa, precision=prec, flags=amg.FLAG_NO_VALUE_COMPRESSION)
+    assert ha.time_kernel(4, 0, reps=1)[1] == ha_off.time_kernel(4, 0, reps=1)[1]
