@@ -22,7 +22,9 @@
  *   - one level runs `sweeps` pairwise sweeps; a sweep that matches nothing
  *     ends the level's sweeps; a level whose size does not shrink becomes
  *     the coarsest (an error if it exceeds ORC_MAX_DENSE);
- *   - the coarsest level is factored by dense Cholesky.
+ *   - the coarsest level is factored by dense Cholesky; the alternative
+ *     iterative coarsest solver (CG with the l1-Jacobi diagonal) stops on
+ *     the first ||r_k|| < rtol ||b||, strictly, from a zero guess.
  *
  * Arithmetic: IEEE binary64, round to nearest, built with -ffp-contract=off
  * and without fast-math. Every sum starts from its first term and runs in
@@ -426,6 +428,9 @@ struct orc_hier {
   int32_t nsweeps[ORC_MAX_LEVELS];
   int32_t nL;
   double *L; /* coarsest Cholesky factor */
+  int32_t coarse_solver; /* 0: Cholesky; 1: orc_coarse_pcg */
+  double coarse_rtol;
+  int32_t coarse_maxit;
 };
 
 void orc_free(orc_hier *h) {
@@ -545,7 +550,7 @@ int orc_setup(const orc_csr *A0, const double *w0, int32_t sweeps,
     ++l;
   }
   h->nlev = l + 1;
-  for (int32_t k = 0; k < l; ++k) {
+  for (int32_t k = 0; k <= l; ++k) {
     h->m[k] = (double *)malloc(sizeof(double) * (size_t)h->A[k].n);
     orc_l1_diag(&h->A[k], h->m[k]);
   }
@@ -598,13 +603,61 @@ void orc_coarse_factor(const orc_hier *h, double *L) {
   memcpy(L, h->L, sizeof(double) * (size_t)h->nL * (size_t)h->nL);
 }
 
+void orc_set_coarse_solver(orc_hier *h, int32_t solver, double rtol, int32_t maxit) {
+  h->coarse_solver = solver;
+  h->coarse_rtol = rtol;
+  h->coarse_maxit = maxit;
+}
+
+/* Hestenes-Stiefel PCG from x = 0 (r_0 = b), preconditioner z = r / m:
+ *   q = A p_k, alpha = (r_k, z_k) / (p_k, q), x += alpha p_k, r -= alpha q;
+ *   stop if ||r_{k+1}|| < rtol ||b|| or k + 1 = maxit;
+ *   z = r / m, beta = (r_{k+1}, z_{k+1}) / (r_k, z_k), p = z + beta p. */
+int32_t orc_coarse_pcg(const orc_csr *A, const double *m, const double *b, double rtol,
+                       int32_t maxit, double *x) {
+  int32_t n = A->n;
+  for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+  double bnorm = sqrt(dot(n, b, b));
+  if (bnorm == 0.0 || maxit < 1) return 0;
+  double *r = (double *)malloc(sizeof(double) * (size_t)n);
+  double *z = (double *)malloc(sizeof(double) * (size_t)n);
+  double *p = (double *)malloc(sizeof(double) * (size_t)n);
+  double *q = (double *)malloc(sizeof(double) * (size_t)n);
+  for (int32_t i = 0; i < n; ++i) r[i] = b[i];
+  for (int32_t i = 0; i < n; ++i) z[i] = r[i] / m[i];
+  for (int32_t i = 0; i < n; ++i) p[i] = z[i];
+  double rz0 = dot(n, r, z);
+  int32_t it = 0;
+  while (it < maxit) {
+    orc_spmv(A, p, q);
+    double pq = dot(n, p, q);
+    if (!(pq > 0.0)) break;
+    double step = rz0 / pq;
+    for (int32_t i = 0; i < n; ++i) x[i] = x[i] + step * p[i];
+    for (int32_t i = 0; i < n; ++i) r[i] = r[i] - step * q[i];
+    ++it;
+    if (sqrt(dot(n, r, r)) < rtol * bnorm) break;
+    for (int32_t i = 0; i < n; ++i) z[i] = r[i] / m[i]; /* preconditioned residual */
+    double rz1 = dot(n, r, z);
+    double beta = rz1 / rz0;
+    rz0 = rz1;
+    for (int32_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+  }
+  free(r);
+  free(z);
+  free(p);
+  free(q);
+  return it;
+}
+
 static void fcg2(const orc_hier *h, int32_t m, int32_t pre, int32_t post, const double *b,
                  double *x);
 
 /* One application of the multilevel preconditioner on level l.
  * eq. (amg): pre-smoothing M^-1 from a zero guess, coarse correction,
  * post-smoothing M^-T = M^-1 (M diagonal). The coarse correction solves
- * A_{l+1} e = P^T t: exactly on the coarsest level; else by the same cycle
+ * A_{l+1} e = P^T t: on the coarsest level exactly (Cholesky) or by the
+ * hierarchy's iterative coarsest solver; else by the same cycle
  * on level l + 1 (V-cycle, kcycle = 0), or by two iterations of flexible CG
  * on level l + 1 preconditioned by the cycle starting there (K-cycle,
  * kcycle = 1; Section 3.1, which applies those FCG iterations on every
@@ -613,7 +666,10 @@ static void cycle(const orc_hier *h, int32_t l, int32_t pre, int32_t post, int k
                   const double *r, double *z) {
   int32_t L = h->nlev - 1;
   if (l == L) {
-    orc_cholesky_solve(h->nL, h->L, r, z);
+    if (h->coarse_solver == 1)
+      (void)orc_coarse_pcg(&h->A[L], h->m[L], r, h->coarse_rtol, h->coarse_maxit, z);
+    else
+      orc_cholesky_solve(h->nL, h->L, r, z);
     return;
   }
   const orc_csr *A = &h->A[l];

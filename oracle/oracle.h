@@ -103,15 +103,22 @@ void orc_csr_free(orc_csr *A);
  * m_i = a_ii + (sum over j != i, ascending, of |a_ij|). */
 void orc_l1_diag(const orc_csr *A, double *m);
 
-/* Dense Cholesky A = L L^T of a row-major n x n s.p.d. matrix, in place
- * (lower triangle holds L, upper is zeroed). Returns ORC_ERR_NOT_SPD on a
- * non-positive pivot. */
 /* nu l1-Jacobi iterations on A w = 0 from the sample w (in place): an
  * algebraically smooth vector for the matching weights. */
 void orc_smooth_w(const orc_csr *A, int32_t nu, double *w);
+/* Dense Cholesky A = L L^T of a row-major n x n s.p.d. matrix, in place
+ * (lower triangle holds L, upper is zeroed). Returns ORC_ERR_NOT_SPD on a
+ * non-positive pivot. */
 int orc_cholesky(int32_t n, double *a);
 /* z = L^-T L^-1 r by forward then backward substitution. */
 void orc_cholesky_solve(int32_t n, const double *L, const double *r, double *z);
+/* The iterative coarsest solver of Section 5 with the l1-Jacobi
+ * preconditioner of the GPU runs: CG on A x = b from x = 0, preconditioned
+ * by the diagonal m (z = r / m), stopped as soon as ||r_k||_2 < rtol ||b||_2
+ * or after maxit iterations. Returns the number of iterations (0 for b = 0,
+ * which gives x = 0). */
+int32_t orc_coarse_pcg(const orc_csr *A, const double *m, const double *b, double rtol,
+                       int32_t maxit, double *x);
 
 /* ---- hierarchy ------------------------------------------------------------ */
 
@@ -137,6 +144,10 @@ void orc_level_w(const orc_hier *h, int32_t l, double *w);
 int32_t orc_level_sweeps(const orc_hier *h, int32_t l);
 /* coarsest Cholesky factor, row-major n_L x n_L */
 void orc_coarse_factor(const orc_hier *h, double *L);
+/* Coarsest solver of the hierarchy's cycles: solver 0 applies the dense
+ * Cholesky factor (the default), solver 1 runs orc_coarse_pcg with the
+ * coarsest level's l1-Jacobi diagonal, rtol and maxit. */
+void orc_set_coarse_solver(orc_hier *h, int32_t solver, double rtol, int32_t maxit);
 
 /* One V-cycle z = B_l r on level l, eq. (amg) with pre/post l1-Jacobi. */
 void orc_vcycle(const orc_hier *h, int32_t l, int32_t pre, int32_t post,

@@ -29,6 +29,7 @@ __all__ = [
     "cholesky",
     "cholesky_solve",
     "smooth_w",
+    "coarse_pcg",
     "Hierarchy",
 ]
 
@@ -96,6 +97,8 @@ def load():
         "orc_l1_diag": (None, [P, _F64P]),
         "orc_cholesky": (C.c_int, [C.c_int32, _F64P]),
         "orc_cholesky_solve": (None, [C.c_int32, _F64P, _F64P, _F64P]),
+        "orc_coarse_pcg": (C.c_int32, [P, _F64P, _F64P, C.c_double, C.c_int32, _F64P]),
+        "orc_set_coarse_solver": (None, [C.c_void_p, C.c_int32, C.c_double, C.c_int32]),
         "orc_setup": (C.c_int, [P, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                 C.POINTER(C.c_void_p)]),
         "orc_free": (None, [C.c_void_p]),
@@ -237,6 +240,15 @@ def cholesky_solve(L, r):
     return z
 
 
+def coarse_pcg(A, m, b, rtol=1e-4, maxit=30):
+    """CG from zero preconditioned by the diagonal m, stopped on the first
+    ||r_k|| < rtol ||b|| or after maxit iterations (Section 5's coarsest
+    solver). Returns (x, iterations)."""
+    x = np.empty(A.n)
+    it = load().orc_coarse_pcg(_HostCsr(A).ref, _f64(m), _f64(b), float(rtol), int(maxit), x)
+    return x, int(it)
+
+
 def smooth_w(A, nu, w0=None):
     """nu l1-Jacobi iterations on A w = 0 from the sample w0 (ones if None)."""
     lib = load()
@@ -249,7 +261,9 @@ def smooth_w(A, nu, w0=None):
 class Hierarchy:
     """Oracle multilevel hierarchy (Sections 3.1-3.3)."""
 
-    def __init__(self, A, w=None, sweeps=3, max_coarse=200, max_levels=32):
+    def __init__(self, A, w=None, sweeps=3, max_coarse=200, max_levels=32, coarse=None):
+        """coarse: None for the dense Cholesky coarsest solve, or (rtol, maxit)
+        for the iterative one (CG with the l1-Jacobi diagonal)."""
         lib = load()
         self._lib = lib
         self._h = C.c_void_p()
@@ -262,6 +276,8 @@ class Hierarchy:
                                     C.byref(self._h))
         if self.status != Status.OK:
             self._h = None
+        elif coarse is not None:
+            lib.orc_set_coarse_solver(self._h, 1, float(coarse[0]), int(coarse[1]))
 
     def __del__(self):
         if getattr(self, "_h", None):

@@ -21,6 +21,7 @@ INV = "tests/test_oracle_invariants.py::"
 PIN = "tests/test_oracle_paper_pins.py::"
 KC = "tests/test_oracle_kcycle.py::"
 SW = "tests/test_oracle_smooth_w.py::"
+CP = "tests/test_oracle_coarse_pcg.py::"
 
 # (mistake, text in oracle.c, replacement, pin test that must reject it)
 MUTATIONS = [
@@ -109,6 +110,20 @@ MUTATIONS = [
      "if (kcycle && l + 1 < L) fcg2(h, l + 1, pre, post, rc, zc);",
      "if (0 && kcycle && l + 1 < L) fcg2(h, l + 1, pre, post, rc, zc);",
      KC + "test_kcycle_iterations_do_not_grow_with_the_grid"),
+    ("coarsest CG: residual not preconditioned",
+     "z[i] = r[i] / m[i]; /* preconditioned residual */",
+     "z[i] = r[i]; /* preconditioned residual */",
+     CP + "test_coarse_pcg_is_scipy_cg_with_the_l1_diagonal"),
+    ("coarsest CG: beta inverted",
+     "double beta = rz1 / rz0;", "double beta = rz0 / rz1;",
+     CP + "test_coarse_pcg_terminates_at_the_exact_solution"),
+    ("coarsest CG: stop test on the squared residual norm",
+     "if (sqrt(dot(n, r, r)) < rtol * bnorm) break;",
+     "if (dot(n, r, r) < rtol * bnorm) break;",
+     CP + "test_coarse_pcg_is_scipy_cg_with_the_l1_diagonal"),
+    ("coarsest CG: the hierarchy keeps the Cholesky solve",
+     "if (h->coarse_solver == 1)", "if (h->coarse_solver == 7)",
+     CP + "test_vcycle_with_iterative_coarsest_solves_the_coarsest_system"),
 ]
 
 
