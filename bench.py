@@ -213,6 +213,58 @@ def bench_kcycle(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_coarse(args):
+    """160^3 Poisson (b = A u): the coarsest solve by CG with the l1-Jacobi
+    diagonal (rtol 1e-4, at most 30 iterations) against the dense Cholesky
+    solve. V-cycle with 4 l1-Jacobi pre/post sweeps and the CG coarsest
+    solve is the paper's GPU preconditioner (Section 5); flexible CG is the
+    outer solver whenever the coarsest solve is iterative. Outer tolerance
+    1e-6 (Section 5) and 1e-8."""
+    import torch
+
+    from paper_2006_16147_amd import amg, inputs
+
+    dev = torch.device("cuda:0")
+    case = inputs.headline_case(args.N, seed=1)
+    A = case["A"]
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    ci = torch.from_numpy(A.col).to(dev)
+    va = torch.from_numpy(A.val).to(dev)
+    b = torch.from_numpy(case["b"]).to(dev)
+    out = {"mode": "coarse", "workload": "poisson7_%d^3_b=Au_seed1" % args.N}
+    configs = [("V_l1x1_cholesky", amg.CYCLE_V, 1, amg.COARSE_CHOLESKY, amg.FP64),
+               ("V_l1x1_cg", amg.CYCLE_V, 1, amg.COARSE_PCG, amg.FP64),
+               ("V_l1x4_cholesky", amg.CYCLE_V, 4, amg.COARSE_CHOLESKY, amg.FP64),
+               ("V_l1x4_cg", amg.CYCLE_V, 4, amg.COARSE_PCG, amg.FP64),
+               ("V_l1x4_cg_fp32_prec", amg.CYCLE_V, 4, amg.COARSE_PCG, amg.FP32),
+               ("K_l1x1_cg", amg.CYCLE_K, 1, amg.COARSE_PCG, amg.FP64)]
+    for name, cyc, sw, cs, prec in configs:
+        h = amg.amg_setup(rp, ci, va, precision=prec, cycle=cyc, pre=sw, post=sw,
+                          coarse_solver=cs)
+        res = {"setup_ms": round(h.setup_times()["total"], 1)}
+        for rtol in (1e-6, 1e-8):
+            x = torch.zeros_like(b)
+            times = []
+            for k in range(args.warmup + args.steps):
+                x.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, info = amg.amg_pcg_solve(h, b, x, rtol=rtol, maxit=500)
+                if k >= args.warmup:
+                    times.append((time.perf_counter() - t0) * 1e3)
+            p50 = percentile(times, 50)
+            res["rtol%g" % rtol] = {
+                "p50_ms": round(p50, 3), "p99_ms": round(percentile(times, 99), 3),
+                "iterations": info["iterations"], "rel_res_true": info["rel_res_true"],
+                "ms_per_iteration": round(p50 / max(1, info["iterations"]), 4)}
+        if cyc == amg.CYCLE_V:
+            ms, _ = h.time_kernel(5, 0, reps=args.vcycles)
+            res["vcycle_ms"] = round(ms, 4)
+        out[name] = res
+        h.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_variants(args):
     """160^3 Poisson (b = A u), V-cycle PCG in FP64: 3 or 4 pairwise sweeps
     per level, w = ones or an algebraically smooth w (4 l1-Jacobi sweeps on
@@ -381,7 +433,8 @@ def main():
     ap.add_argument("--N", type=int, default=160)
     ap.add_argument("--vcycles", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="headline", choices=["headline", "aniso", "batch", "serve", "kcycle", "variants"],
+    ap.add_argument("--mode", default="headline",
+                    choices=["headline", "aniso", "batch", "serve", "kcycle", "variants", "coarse"],
                     help="headline (default): the 160^3 benchmark line; the others print "
                          "their own JSON lines")
     ap.add_argument("--rates", default="10,50,200,500", help="serve mode: arrival rates /s")
@@ -403,7 +456,8 @@ def main():
 
         torch.cuda.set_device(0)
         {"aniso": bench_aniso, "batch": bench_batch, "serve": bench_serve,
-         "kcycle": bench_kcycle, "variants": bench_variants}[args.mode](args)
+         "kcycle": bench_kcycle, "variants": bench_variants,
+         "coarse": bench_coarse}[args.mode](args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "

@@ -13,8 +13,10 @@
  *     `max_coarse` unknowns (Section 5).
  *   - Smoother: l1-Jacobi, eqs. (ml1hgs)/(l1weights) with blocks of one row
  *     (Section 3.3); one pre- and one post-sweep by default.
- *   - Preconditioner: the V-cycle of eq. (amg); the coarsest system is
- *     solved exactly with a dense Cholesky factorisation.
+ *   - Preconditioner: the V-cycle of eq. (amg) or the K-cycle (Section
+ *     3.1); the coarsest system is solved exactly with a dense Cholesky
+ *     factorisation, or iteratively by CG with the l1-Jacobi diagonal as in
+ *     the GPU runs of Section 5 (AMG_COARSE_PCG).
  *   - Solver: preconditioned CG, stopped on the relative residual (Section 5).
  *
  * Matching ties are broken by the strict key (weight descending, smaller
@@ -73,6 +75,17 @@ enum { AMG_FP64 = 0, AMG_FP32 = 1 };
  *   K-cycle is not a fixed linear operator. */
 enum { AMG_CYCLE_V = 0, AMG_CYCLE_K = 1 };
 
+/* amg_params.coarse_solver: how a cycle solves the coarsest system.
+ * AMG_COARSE_CHOLESKY: exactly, z_L = A_L^-1 r_L from a dense Cholesky
+ *   factorisation made at setup.
+ * AMG_COARSE_PCG: the iterative coarsest solver of Section 5 with the
+ *   l1-Jacobi preconditioner: CG on A_L z_L = r_L from z_L = 0 with
+ *   z = r / m_L, stopped as soon as ||r_k||_2 < coarse_rtol ||r_L||_2 or
+ *   after coarse_maxit iterations. The cycle then differs slightly from one
+ *   right-hand side to the next (it is not a fixed linear operator), so
+ *   amg_pcg_solve runs flexible CG, as the paper does. */
+enum { AMG_COARSE_CHOLESKY = 0, AMG_COARSE_PCG = 1 };
+
 /* amg_params.flags */
 enum {
   AMG_FLAG_NO_GRAPH = 1,   /* launch the solve kernels directly, no hipGraph */
@@ -113,6 +126,10 @@ typedef struct {
                          diagonal of A and w0 = w (NULL: ones), i.e. w_sweeps iterations of
                          the smoother on A w = 0 from the sample w0 (the algebraically
                          smooth vectors recommended after eq. (prolongator)); 0 */
+  int32_t coarse_solver; /* AMG_COARSE_CHOLESKY or AMG_COARSE_PCG; AMG_COARSE_CHOLESKY */
+  int32_t coarse_maxit;  /* AMG_COARSE_PCG: iteration cap, 1..10000; 30 (Section 5) */
+  double coarse_rtol;    /* AMG_COARSE_PCG: relative residual target, >= 0 (0: run
+                            coarse_maxit iterations); 1e-4 (Section 5) */
 } amg_params;
 
 typedef struct {
@@ -141,8 +158,9 @@ void amg_params_default(amg_params *p);
 amg_status amg_setup(const amg_csr *A, const amg_params *params, amg_hierarchy **out);
 
 /* Preconditioned CG on A x = b with the V-cycle as preconditioner (Section
- * 5), or, for a hierarchy built with AMG_CYCLE_K, flexible CG (truncation 1:
- * each direction A-orthogonal to the previous) with the K-cycle.
+ * 5), or, for a hierarchy built with AMG_CYCLE_K or AMG_COARSE_PCG, flexible
+ * CG (truncation 1: each direction A-orthogonal to the previous) with the
+ * hierarchy's cycle.
  * b: device, n (read). x: device, n (in: initial guess, out: iterate).
  * Stops when ||r_k||_2 <= rtol ||b||_2 or after maxit iterations; b = 0 gives
  * x = 0 after 0 iterations. rtol = 0 runs exactly maxit iterations.
@@ -156,8 +174,9 @@ amg_status amg_pcg_solve(amg_hierarchy *h, const double *b, double *x, double rt
  * with its own CG recurrence (own alpha, beta, stop test); the V-cycle runs
  * once per iteration on the whole block. info: host array of k, may be NULL.
  * Returns AMG_OK if every column converged, else AMG_NOT_CONVERGED, or an
- * error; AMG_ERR_ARG for a hierarchy built with AMG_CYCLE_K (the block solve
- * runs the V-cycle only). k = 0 is a no-op. */
+ * error; AMG_ERR_ARG for a hierarchy built with AMG_CYCLE_K or
+ * AMG_COARSE_PCG (the block solve runs the V-cycle with the Cholesky
+ * coarsest solve only). k = 0 is a no-op. */
 amg_status amg_pcg_solve_batch(amg_hierarchy *h, int32_t k, const double *B, double *X,
                                double rtol, int32_t maxit, amg_solve_info *info);
 
@@ -187,7 +206,8 @@ amg_status amg_get_level_csr(const amg_hierarchy *h, int32_t l, int32_t *row_ptr
  * p_host[i] the entry P_l(i, agg_host[i]). Either pointer may be NULL. */
 amg_status amg_get_transfer(const amg_hierarchy *h, int32_t l, int32_t *agg_host,
                             double *p_host);
-/* Copies the l1-Jacobi diagonal m of level l (l < nlev - 1). */
+/* Copies the l1-Jacobi diagonal m of level l (l < nlev - 1; also the
+ * coarsest level of an AMG_COARSE_PCG hierarchy, whose CG uses it). */
 amg_status amg_get_l1diag(const amg_hierarchy *h, int32_t l, double *m_host);
 /* Copies the smooth vector w restricted to level l. */
 amg_status amg_get_w(const amg_hierarchy *h, int32_t l, double *w_host);
@@ -212,7 +232,9 @@ amg_status amg_matching_rounds(const amg_hierarchy *h, int32_t l, int32_t *round
  *     (level l + 1 must not be the coarsest), 3 = same as 2,
  * 4 = outer-CG SpMV with its dot product (level 0),
  * 5 = one whole V-cycle as inside the solve (level ignored; *bytes its
- *     algorithmic total; AMG_ERR_ARG for a K-cycle hierarchy). */
+ *     algorithmic total, without the coarsest solve when it is the
+ *     iterative one, whose L2-resident traffic depends on its iteration
+ *     count; AMG_ERR_ARG for a K-cycle hierarchy). */
 amg_status amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
                            double *ms, double *bytes);
 

@@ -24,6 +24,7 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 FP64, FP32 = 0, 1
 CYCLE_V, CYCLE_K = 0, 1
+COARSE_CHOLESKY, COARSE_PCG = 0, 1
 FLAG_NO_GRAPH, FLAG_SKIP_CHECKS, FLAG_NO_VALUE_COMPRESSION = 1, 2, 4
 MAX_DENSE = 4096
 
@@ -64,7 +65,8 @@ class Params(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("max_coarse", C.c_int32), ("max_levels", C.c_int32),
                 ("pre", C.c_int32), ("post", C.c_int32), ("precision", C.c_int32),
                 ("w", C.c_void_p), ("stream", C.c_void_p), ("flags", C.c_int32),
-                ("cycle", C.c_int32), ("w_sweeps", C.c_int32)]
+                ("cycle", C.c_int32), ("w_sweeps", C.c_int32), ("coarse_solver", C.c_int32),
+                ("coarse_maxit", C.c_int32), ("coarse_rtol", C.c_double)]
 
 
 class SolveInfo(C.Structure):

@@ -126,6 +126,12 @@ amg_status check_params(const amg_params *p) {
   if (p->precision != AMG_FP64 && p->precision != AMG_FP32) return AMG_ERR_ARG;
   if (p->cycle != AMG_CYCLE_V && p->cycle != AMG_CYCLE_K) return AMG_ERR_ARG;
   if (p->w_sweeps < 0 || p->w_sweeps > 1000) return AMG_ERR_ARG;
+  if (p->coarse_solver != AMG_COARSE_CHOLESKY && p->coarse_solver != AMG_COARSE_PCG)
+    return AMG_ERR_ARG;
+  if (p->coarse_solver == AMG_COARSE_PCG &&
+      (p->coarse_maxit < 1 || p->coarse_maxit > 10000 || !(p->coarse_rtol >= 0.0) ||
+       !std::isfinite(p->coarse_rtol)))
+    return AMG_ERR_ARG;
   return AMG_OK;
 }
 
@@ -156,6 +162,9 @@ void amg_params_default(amg_params *p) {
   p->flags = 0;
   p->cycle = AMG_CYCLE_V;
   p->w_sweeps = 0;
+  p->coarse_solver = AMG_COARSE_CHOLESKY;
+  p->coarse_maxit = 30;
+  p->coarse_rtol = 1e-4;
 }
 
 amg_status amg_setup(const amg_csr *A, const amg_params *params, amg_hierarchy **out) {
@@ -215,7 +224,8 @@ amg_status amg_pcg_solve(amg_hierarchy *h, const double *b, double *x, double rt
 amg_status amg_pcg_solve_batch(amg_hierarchy *h, int32_t k, const double *B, double *X,
                                double rtol, int32_t maxit, amg_solve_info *info) {
   if (!h || k < 0 || !(rtol >= 0.0) || maxit < 0) return AMG_ERR_ARG;
-  if (h->params.cycle != AMG_CYCLE_V) return AMG_ERR_ARG;
+  if (h->params.cycle != AMG_CYCLE_V || h->params.coarse_solver != AMG_COARSE_CHOLESKY)
+    return AMG_ERR_ARG;
   if (k == 0) return AMG_OK;
   if (!B || !X) return AMG_ERR_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return AMG_ERR_HIP;
@@ -281,8 +291,9 @@ amg_status amg_get_transfer(const amg_hierarchy *h, int32_t l, int32_t *agg, dou
 }
 
 amg_status amg_get_l1diag(const amg_hierarchy *h, int32_t l, double *m) {
-  if (!h || !m || l < 0 || l + 1 >= (int32_t)h->lv.size()) return AMG_ERR_ARG;
+  if (!h || !m || l < 0 || l >= (int32_t)h->lv.size()) return AMG_ERR_ARG;
   const Level &L = h->lv[l];
+  if (!L.m) return AMG_ERR_ARG;  // the coarsest level has one only for the CG coarsest solve
   AMG_TRY(d2h(h, m, L.m, sizeof(double) * L.n));
   return AMG_OK;
 }

@@ -1060,7 +1060,9 @@ amg_status build_hierarchy(amg_hierarchy *h, const amg_csr *A) {
   // smoother diagonals
   double ts = now_ms();
   const int32_t nlev = (int32_t)h->lv.size();
-  for (int32_t l = 0; l + 1 < nlev; ++l) {
+  // (the coarsest level too when its system is solved by CG with them)
+  const int32_t nsmooth = h->params.coarse_solver == AMG_COARSE_PCG ? nlev : nlev - 1;
+  for (int32_t l = 0; l < nsmooth; ++l) {
     Level &L = h->lv[l];
     AMG_TRY(dalloc(h, &L.m, (size_t)L.n));
     AMG_TRY(dalloc(h, &L.minv64, (size_t)L.n));

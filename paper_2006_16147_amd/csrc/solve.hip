@@ -365,15 +365,16 @@ __global__ void k_permute_out(int32_t n, const int32_t *__restrict__ perm,
 
 // Down step on level l for the coarse positions [J0, J0 + G) of this block:
 // z = M^-1 r with the residual through the stored A M^-1 (kPreScaled) or,
-// after extra pre-smoothing sweeps, the given z (kPreFromZ, plain A); then
+// after extra pre-smoothing sweeps, the given z (kPreFromZ, plain A stored
+// as TA); then
 // r_{l+1}(J) = sum over the segment of J, in order, of p_k (r - A z)_k.
 // The block's fine rows are the union of its segments (at most kBlock rows).
 enum PreMode : int { kPreScaled = 0, kPreFromZ = 1 };
 
-template <typename TV, typename TR, int MODE>
+template <typename TV, typename TR, int MODE, typename TA = TV>
 __global__ void __launch_bounds__(kBlock) k_pre_restrict(
     int32_t nc, int32_t G, const int32_t *__restrict__ seg, const int32_t *__restrict__ sptr,
-    const int32_t *__restrict__ col, const TV *__restrict__ val, const TV *__restrict__ minv,
+    const int32_t *__restrict__ col, const TA *__restrict__ val, const TV *__restrict__ minv,
     const TV *__restrict__ pp, const TR *__restrict__ r, TV *__restrict__ z,
     TV *__restrict__ rc, const int32_t *__restrict__ done) {
   __shared__ TV sh[kBlock];
@@ -386,8 +387,9 @@ __global__ void __launch_bounds__(kBlock) k_pre_restrict(
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
     const TV acc =
-        MODE == kPreFromZ ? sell_dot(col, val, base, w, [&](int32_t c) { return z[c]; })
-                          : sell_dot(col, val, base, w, [&](int32_t c) { return (TV)r[c]; });
+        MODE == kPreFromZ
+            ? sell_dot_t<TV, TA>(col, val, base, w, [&](int32_t c) { return z[c]; })
+            : sell_dot_t<TV, TA>(col, val, base, w, [&](int32_t c) { return (TV)r[c]; });
     const TV ri = (TV)r[row];
     if (MODE == kPreScaled) z[row] = ri * minv[row];
     sh[threadIdx.x] = pp[row] * (ri - acc);
@@ -740,10 +742,10 @@ __global__ void k_xpay(int32_t n, const double *__restrict__ z, double *__restri
 
 // v = A c and the block partials of (c, v) and of (c, u) for each given u
 // (plane 0: (c, v); plane q >= 1: (c, u_q)), sums in FP64
-template <typename TV, int NV>
+template <typename TV, int NV, typename TA = TV>
 __global__ void __launch_bounds__(kBlock) k_spmv_dots(
     int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
-    const TV *__restrict__ val, const TV *__restrict__ c, TV *__restrict__ v,
+    const TA *__restrict__ val, const TV *__restrict__ c, TV *__restrict__ v,
     const TV *__restrict__ u1, const TV *__restrict__ u2, double *__restrict__ partials,
     const int32_t *__restrict__ done) {
   if (*done) return;
@@ -755,7 +757,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dots(
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
-    const TV acc = sell_dot(col, val, base, w, [&](int32_t cc) { return c[cc]; });
+    const TV acc = sell_dot_t<TV, TA>(col, val, base, w, [&](int32_t cc) { return c[cc]; });
     v[row] = acc;
     const double ci = (double)c[row];
     d[0] += ci * (double)acc;
@@ -1045,6 +1047,128 @@ __global__ void __launch_bounds__(1024) k_ktail(
   }
 }
 
+// ---------------------------------------------------------------------------
+// iterative coarsest solver (Section 5): CG with the l1-Jacobi diagonal
+// ---------------------------------------------------------------------------
+
+// two sums over the block at once; every thread gets both (fixed order)
+__device__ __forceinline__ void block_sum2(double &a, double &b, double (*red)[1024 / kWave]) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, kWave);
+    b += __shfl_down(b, o, kWave);
+  }
+  __syncthreads();
+  if (lane == 0) {
+    red[0][wid] = a;
+    red[1][wid] = b;
+  }
+  __syncthreads();
+  double ta = red[0][0], tb = red[1][0];
+  for (int k = 1; k < nw; ++k) {
+    ta += red[0][k];
+    tb += red[1][k];
+  }
+  a = ta;
+  b = tb;
+}
+
+// z_L from A_L z_L = r_L by CG from zero with z = r / m (minv = 1 / m),
+// stopped as soon as ||r_k|| < rtol ||r_L|| or after maxit steps. zout (if
+// given) receives z_L; then z_f += P z_L over the nf positions of the level
+// above (nf = 0: none). One block; thread t owns rows t, t + blockDim.x, ...
+// (at most kCgRows), keeps its rows' x, r, q in registers and the search
+// direction in LDS for the products; FP64 throughout, A_L in CSR.
+constexpr int kCgRows = AMG_MAX_DENSE / 1024;
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(1024) k_coarse_pcg(
+    int32_t nL, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const double *__restrict__ val, const double *__restrict__ minv, double rtol,
+    int32_t maxit, const TI *__restrict__ rL, TO *__restrict__ zout, int32_t nf,
+    const int32_t *__restrict__ aggp, const TO *__restrict__ pp, TO *__restrict__ zf,
+    const int32_t *__restrict__ done) {
+  __shared__ double P[AMG_MAX_DENSE];
+  __shared__ double red[2][1024 / kWave];
+  if (*done) return;
+  const int32_t tid = threadIdx.x, nth = blockDim.x;
+  double x[kCgRows], r[kCgRows], q[kCgRows];
+  double bb = 0.0, rz0 = 0.0;
+#pragma unroll
+  for (int u = 0; u < kCgRows; ++u) {
+    const int32_t i = tid + u * nth;
+    x[u] = r[u] = q[u] = 0.0;
+    if (i < nL) {
+      r[u] = (double)rL[i];
+      const double z = r[u] * minv[i];
+      P[i] = z;
+      bb += r[u] * r[u];
+      rz0 += r[u] * z;
+    }
+  }
+  block_sum2(bb, rz0, red);  // also orders the P writes before the first product
+  const double bstop = rtol * sqrt(bb);
+  for (int32_t it = 0; bb > 0.0 && it < maxit; ++it) {
+    // q = A p and (p, q)
+    double pq = 0.0, unused = 0.0;
+#pragma unroll
+    for (int u = 0; u < kCgRows; ++u) {
+      const int32_t i = tid + u * nth;
+      if (i < nL) {
+        double acc = 0.0;
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) acc += val[k] * P[ci[k]];
+        q[u] = acc;
+        pq += P[i] * acc;
+      }
+    }
+    block_sum2(pq, unused, red);
+    if (!(pq > 0.0)) break;
+    const double step = rz0 / pq;
+    // x += step p, r -= step q, then ||r||^2 and (r, z) with z = r / m
+    double rr = 0.0, rz1 = 0.0;
+    double z[kCgRows];
+#pragma unroll
+    for (int u = 0; u < kCgRows; ++u) {
+      const int32_t i = tid + u * nth;
+      z[u] = 0.0;
+      if (i < nL) {
+        x[u] += step * P[i];
+        r[u] -= step * q[u];
+        z[u] = r[u] * minv[i];
+        rr += r[u] * r[u];
+        rz1 += r[u] * z[u];
+      }
+    }
+    block_sum2(rr, rz1, red);  // every thread has read P before any rewrites it
+    if (sqrt(rr) < bstop) break;
+    const double beta = rz1 / rz0;
+    rz0 = rz1;
+#pragma unroll
+    for (int u = 0; u < kCgRows; ++u) {
+      const int32_t i = tid + u * nth;
+      if (i < nL) P[i] = z[u] + beta * P[i];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kCgRows; ++u) {
+    const int32_t i = tid + u * nth;
+    if (i < nL) {
+      P[i] = x[u];
+      if (zout) zout[i] = (TO)x[u];
+    }
+  }
+  __syncthreads();
+  for (int32_t k = tid; k < nf; k += nth) zf[k] += pp[k] * (TO)P[aggp[k]];
+}
+
+// threads of the coarsest CG block: one wavefront per 64 rows, at most 1024
+inline int32_t coarse_pcg_threads(int32_t nL) {
+  const int32_t t = ceil_div(nL, kWave) * kWave;
+  return t < kWave ? kWave : (t > 1024 ? 1024 : t);
+}
+
 // r1 = b - s1 v1
 template <typename TV>
 __global__ void k_kresid(int32_t n, const TV *__restrict__ b, const TV *__restrict__ v1,
@@ -1109,6 +1233,13 @@ int32_t coarse_per_block(const amg_hierarchy *h) {
   return g < 1 ? 1 : g;
 }
 
+// whether the products of level l read A from its exact FP32 copy: level 0
+// of an FP64 hierarchy whose values are all FP32 numbers (same arithmetic)
+template <typename TV>
+bool reads32(const Level &F, int32_t l) {
+  return l == 0 && sizeof(TV) == 8 && F.S.exact32;
+}
+
 // down step on level l: smoothing from zero, residual, restriction into
 // level l + 1's right-hand side; returns the buffer holding z_l
 template <typename TV, typename TR>
@@ -1126,16 +1257,26 @@ TV *launch_down(amg_hierarchy *h, int32_t l, const TR *r, const int32_t *done) {
     return z;
   }
   const Geom g = geom(F.n);
+  const bool a32 = reads32<TV>(F, l);
   k_jacobi0<TV, TR><<<grid1(F.n), kBlock, 0, s>>>(F.n, minv<TV>(F), r, z, done);
   for (int32_t k = 1; k < h->params.pre; ++k) {
-    k_post<TV, TR, TV, false><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
-                                                       vals<TV>(F), minv<TV>(F), r, z, tmp,
-                                                       nullptr, done);
+    if (a32)
+      k_post<TV, TR, TV, false, float><<<g.grid, kBlock, 0, s>>>(
+          F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), r, z, tmp, nullptr, done);
+    else
+      k_post<TV, TR, TV, false><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
+                                                         vals<TV>(F), minv<TV>(F), r, z, tmp,
+                                                         nullptr, done);
     std::swap(z, tmp);
   }
-  k_pre_restrict<TV, TR, kPreFromZ><<<grid, kBlock, 0, s>>>(C.n, G, F.seg, F.S.sptr, F.S.col,
-                                                           vals<TV>(F), minv<TV>(F), ppv<TV>(F),
-                                                           r, z, (TV *)C.r, done);
+  if (a32)
+    k_pre_restrict<TV, TR, kPreFromZ, float><<<grid, kBlock, 0, s>>>(
+        C.n, G, F.seg, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), ppv<TV>(F), r, z, (TV *)C.r,
+        done);
+  else
+    k_pre_restrict<TV, TR, kPreFromZ><<<grid, kBlock, 0, s>>>(C.n, G, F.seg, F.S.sptr, F.S.col,
+                                                             vals<TV>(F), minv<TV>(F),
+                                                             ppv<TV>(F), r, z, (TV *)C.r, done);
   return z;
 }
 
@@ -1160,25 +1301,54 @@ void launch_up(amg_hierarchy *h, int32_t c, TV *zc, TV *zf, const int32_t *done)
                                                    F.aggp, ppv<TV>(F), zf, done);
 }
 
-// V-cycle z0 = B r0 on the aggregate-major vectors of level 0
+inline bool coarse_is_pcg(const amg_hierarchy *h) {
+  return h->params.coarse_solver == AMG_COARSE_PCG;
+}
+
+// The coarsest solve by CG (coarse_is_pcg): z_L into zout and/or
+// prolongated into zf (nf positions of the level above).
+template <typename TI, typename TO>
+void launch_coarse_pcg(amg_hierarchy *h, const TI *rL, TO *zout, int32_t nf,
+                       const int32_t *aggp, const TO *pp, TO *zf, const int32_t *done) {
+  const Level &C = h->lv.back();
+  k_coarse_pcg<TI, TO><<<1, coarse_pcg_threads(C.n), 0, h->stream>>>(
+      C.n, C.rp, C.ci, C.val, C.minv64, h->params.coarse_rtol, h->params.coarse_maxit, rL, zout,
+      nf, aggp, pp, zf, done);
+}
+
+// z0 = coarsest solve of r0 when level 0 is the coarsest level; with dot,
+// the partials of (dv, z0) (dv = NULL: of (r0, z0), finalized into rho)
+void one_level_cycle(amg_hierarchy *h, const double *r0, double *z0, bool dot, const double *dv,
+                     const int32_t *done) {
+  hipStream_t s = h->stream;
+  const int32_t n = h->C.n;
+  if (coarse_is_pcg(h))
+    launch_coarse_pcg<double, double>(h, r0, z0, 0, nullptr, nullptr, nullptr, done);
+  else
+    k_coarse_solve<double, double><<<ceil_div(n, kCoarseWaves), kWave * kCoarseWaves, 0, s>>>(
+        n, h->C.Ainv, r0, z0, done);
+  if (dot) {
+    const Geom g = geom(h->lv[0].n);
+    k_dot_rz<<<g.grid, kBlock, 0, s>>>(h->lv[0].n, g.chunk, dv ? dv : r0, z0, h->partials, done);
+    if (!dv) finalize(h, kFinRZ, g.grid, done);
+  }
+}
+
+// V-cycle z0 = B r0 on the aggregate-major vectors of level 0. With dot, the
+// last kernel also writes the block partials of (r0, z0), finalized into the
+// CG scalars, or, with a dot partner dv, of (dv, z0), left to the caller.
 template <typename TV>
-void vcycle_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const int32_t *done) {
+void vcycle_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const double *dv,
+              const int32_t *done) {
   hipStream_t s = h->stream;
   const int32_t L = (int32_t)h->lv.size() - 1;
   if (L == 0) {
-    const int32_t n = h->C.n;
-    k_coarse_solve<double, double><<<ceil_div(n, kCoarseWaves), kWave * kCoarseWaves, 0, s>>>(
-        n, h->C.Ainv, r0, z0, done);
-    if (dot) {
-      const Geom g = geom(h->lv[0].n);
-      k_dot_rz<<<g.grid, kBlock, 0, s>>>(h->lv[0].n, g.chunk, r0, z0, h->partials, done);
-      finalize(h, kFinRZ, g.grid, done);
-    }
+    one_level_cycle(h, r0, z0, dot, dv, done);
     return;
   }
   std::vector<TV *> zb(L);
   const bool tail = L >= 2 && h->params.pre == 1 && h->params.post == 1 &&
-                    h->lv[L - 1].n <= kTailMax && h->C.n <= kTailCoarseMax;
+                    h->lv[L - 1].n <= kTailMax && h->C.n <= kTailCoarseMax && !coarse_is_pcg(h);
   const int32_t down_end = tail ? L - 1 : L;  // levels [0, down_end) take the down step
   zb[0] = launch_down<TV, double>(h, 0, r0, done);
   for (int32_t l = 1; l < down_end; ++l)
@@ -1193,8 +1363,12 @@ void vcycle_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const in
   } else {
     Level &F = h->lv[L - 1];
     const int32_t nL = h->C.n;
-    k_coarse_prolong<TV><<<1, 1024, 2 * sizeof(double) * nL, s>>>(
-        nL, h->C.Ainv, (const TV *)h->lv[L].r, F.n, F.aggp, ppv<TV>(F), zb[L - 1], done);
+    if (coarse_is_pcg(h))
+      launch_coarse_pcg<TV, TV>(h, (const TV *)h->lv[L].r, nullptr, F.n, F.aggp, ppv<TV>(F),
+                                zb[L - 1], done);
+    else
+      k_coarse_prolong<TV><<<1, 1024, 2 * sizeof(double) * nL, s>>>(
+          nL, h->C.Ainv, (const TV *)h->lv[L].r, F.n, F.aggp, ppv<TV>(F), zb[L - 1], done);
     for (int32_t c = L - 1; c >= 1; --c) launch_up<TV>(h, c, zb[c], zb[c - 1], done);
   }
   // level 0: extra post sweeps, then the last with the (r, z) partials
@@ -1203,7 +1377,7 @@ void vcycle_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const in
   if (tmp == z) tmp = (TV *)F.z;
   const Geom g = geom(F.n);
   // an FP64 hierarchy reads A from its exact FP32 copy when there is one
-  const bool a32 = sizeof(TV) == 8 && F.S.exact32;
+  const bool a32 = reads32<TV>(F, 0);
   for (int32_t k = 1; k < h->params.post; ++k) {
     if (a32)
       k_post<TV, double, TV, false, float><<<g.grid, kBlock, 0, s>>>(
@@ -1216,12 +1390,13 @@ void vcycle_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const in
   if (dot) {
     if (a32)
       k_post<TV, double, double, true, float><<<g.grid, kBlock, 0, s>>>(
-          F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), r0, z, z0, h->partials, done);
+          F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), r0, z, z0, h->partials, done,
+          dv);
     else
       k_post<TV, double, double, true><<<g.grid, kBlock, 0, s>>>(
           F.n, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), r0, z, z0, h->partials,
-          done);
-    finalize(h, kFinRZ, g.grid, done);
+          done, dv);
+    if (!dv) finalize(h, kFinRZ, g.grid, done);
   } else {
     if (a32)
       k_post<TV, double, double, false, float><<<g.grid, kBlock, 0, s>>>(
@@ -1249,10 +1424,14 @@ void kcycle_t(amg_hierarchy *h, int32_t l, const TR *in, TO *out, const double *
   TV *z = launch_down<TV, TR>(h, l, in, done);
   if (l + 1 == L) {
     const int32_t nL = h->C.n;
-    k_coarse_prolong<TV><<<1, 1024, 2 * sizeof(double) * nL, s>>>(
-        nL, h->C.Ainv, (const TV *)h->lv[L].r, F.n, F.aggp, ppv<TV>(F), z, done);
+    if (coarse_is_pcg(h))
+      launch_coarse_pcg<TV, TV>(h, (const TV *)h->lv[L].r, nullptr, F.n, F.aggp, ppv<TV>(F), z,
+                                done);
+    else
+      k_coarse_prolong<TV><<<1, 1024, 2 * sizeof(double) * nL, s>>>(
+          nL, h->C.Ainv, (const TV *)h->lv[L].r, F.n, F.aggp, ppv<TV>(F), z, done);
   } else if (l + 2 == L && h->params.pre == 1 && h->params.post == 1 &&
-             h->lv[l + 1].n <= kKTailMax && h->C.n <= kKTailCoarse) {
+             h->lv[l + 1].n <= kKTailMax && h->C.n <= kKTailCoarse && !coarse_is_pcg(h)) {
     const Level &T = h->lv[l + 1];
     auto kt = T.n <= 1024 && T.S.max_width <= kRowBatch ? k_ktail<TV, true> : k_ktail<TV, false>;
     kt<<<1, 1024, 0, s>>>(T.n, T.S.sptr, T.S.col, svals<TV>(T), vals<TV>(T), minv<TV>(T),
@@ -1270,16 +1449,27 @@ void kcycle_t(amg_hierarchy *h, int32_t l, const TR *in, TO *out, const double *
   TV *tmp = (TV *)F.y;
   if (tmp == z) tmp = (TV *)F.z;
   const Geom g = geom(F.n);
+  const bool a32 = reads32<TV>(F, l);
   for (int32_t k = 1; k < h->params.post; ++k) {
-    k_post<TV, TR, TV, false><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
-                                                       vals<TV>(F), minv<TV>(F), in, z, tmp,
-                                                       nullptr, done);
+    if (a32)
+      k_post<TV, TR, TV, false, float><<<g.grid, kBlock, 0, s>>>(
+          F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), in, z, tmp, nullptr, done);
+    else
+      k_post<TV, TR, TV, false><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
+                                                         vals<TV>(F), minv<TV>(F), in, z, tmp,
+                                                         nullptr, done);
     std::swap(z, tmp);
   }
-  if (dv)
+  if (dv && a32)
+    k_post<TV, TR, TO, true, float><<<g.grid, kBlock, 0, s>>>(
+        F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), in, z, out, h->partials, done, dv);
+  else if (dv)
     k_post<TV, TR, TO, true><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
                                                       vals<TV>(F), minv<TV>(F), in, z, out,
                                                       h->partials, done, dv);
+  else if (a32)
+    k_post<TV, TR, TO, false, float><<<g.grid, kBlock, 0, s>>>(
+        F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), in, z, out, nullptr, done);
   else
     k_post<TV, TR, TO, false><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
                                                        vals<TV>(F), minv<TV>(F), in, z, out,
@@ -1317,16 +1507,10 @@ void fcg2_t(amg_hierarchy *h, int32_t m, const int32_t *done) {
 template <typename TV>
 void kcycle_top(amg_hierarchy *h, const double *r0, double *z0, const double *dv,
                 const int32_t *done) {
-  hipStream_t s = h->stream;
   const int32_t L = (int32_t)h->lv.size() - 1;
   if (L == 0) {
-    const int32_t n = h->C.n;
-    k_coarse_solve<double, double><<<ceil_div(n, kCoarseWaves), kWave * kCoarseWaves, 0, s>>>(
-        n, h->C.Ainv, r0, z0, done);
-    if (dv) {
-      const Geom g = geom(h->lv[0].n);
-      k_dot_rz<<<g.grid, kBlock, 0, s>>>(h->lv[0].n, g.chunk, dv, z0, h->partials, done);
-    }
+    if (dv) one_level_cycle(h, r0, z0, true, dv, done);
+    else one_level_cycle(h, r0, z0, false, nullptr, done);
     return;
   }
   kcycle_t<TV, double, double>(h, 0, r0, z0, dv, done);
@@ -1489,10 +1673,28 @@ amg_status kcycle_perm(amg_hierarchy *h, const double *r, double *z, const doubl
 amg_status vcycle_perm(amg_hierarchy *h, const double *r, double *z, bool fuse_dot,
                        const int32_t *done) {
   if (h->params.cycle == AMG_CYCLE_K) return kcycle_perm(h, r, z, nullptr, done);
-  if (h->params.precision == AMG_FP32) vcycle_t<float>(h, r, z, fuse_dot, done);
-  else vcycle_t<double>(h, r, z, fuse_dot, done);
+  if (h->params.precision == AMG_FP32) vcycle_t<float>(h, r, z, fuse_dot, nullptr, done);
+  else vcycle_t<double>(h, r, z, fuse_dot, nullptr, done);
   AMG_HIP(hipGetLastError());
   return AMG_OK;
+}
+
+// The preconditioner of flexible CG (K-cycle, or a cycle with the iterative
+// coarsest solve): z = B r with the block partials of (dv, z) when dv is
+// given, left for the caller's finalize.
+amg_status precond_perm(amg_hierarchy *h, const double *r, double *z, const double *dv,
+                        const int32_t *done) {
+  if (h->params.cycle == AMG_CYCLE_K) return kcycle_perm(h, r, z, dv, done);
+  if (h->params.precision == AMG_FP32) vcycle_t<float>(h, r, z, dv != nullptr, dv, done);
+  else vcycle_t<double>(h, r, z, dv != nullptr, dv, done);
+  AMG_HIP(hipGetLastError());
+  return AMG_OK;
+}
+
+// flexible CG is the outer solver when the preconditioner is not a fixed
+// linear operator
+inline bool flexible(const amg_hierarchy *h) {
+  return h->params.cycle == AMG_CYCLE_K || h->params.coarse_solver == AMG_COARSE_PCG;
 }
 
 // z = B r on vectors in the caller's numbering
@@ -1512,29 +1714,35 @@ namespace {
 // One CG iteration: q = A p, alpha, x and r updates with the stop test,
 // z = B r with (r, z) and beta, p = z + beta p. Touches only hierarchy
 // buffers, so it is captured once and replayed.
-// One flexible-CG iteration with the K-cycle: q = A p with (p, q), (p, r),
-// alpha = (p, r) / (p, q), the x and r updates with the stop test,
-// z = K r with (q, z), beta = -(z, q) / (p, q), p = z + beta p.
+// One flexible-CG iteration (K-cycle, or the iterative coarsest solve):
+// q = A p with (p, q), (p, r), alpha = (p, r) / (p, q), the x and r updates
+// with the stop test, z = B r with (q, z), beta = -(z, q) / (p, q),
+// p = z + beta p.
 void fcg_iteration(amg_hierarchy *h) {
   hipStream_t s = h->stream;
   Level &L0 = h->lv[0];
   const int32_t n = L0.n;
   const int32_t *done = &h->scal->done;
   const Geom g = geom(n);
-  k_spmv_dots<double, 2><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64,
-                                                   h->p, h->q, h->r, nullptr, h->partials,
-                                                   done);
+  if (L0.S.exact32)
+    k_spmv_dots<double, 2, float><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col,
+                                                            L0.S.v32, h->p, h->q, h->r, nullptr,
+                                                            h->partials, done);
+  else
+    k_spmv_dots<double, 2><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64,
+                                                     h->p, h->q, h->r, nullptr, h->partials,
+                                                     done);
   finalize(h, kFinPQR, g.grid, done);
   k_update_xr<<<g.grid, kBlock, 0, s>>>(n, g.chunk, h->x, h->r, h->p, h->q, h->partials, h->scal,
                                         done);
   finalize(h, kFinRR, g.grid, done);
-  kcycle_perm(h, h->r, h->z, h->q, done);
+  precond_perm(h, h->r, h->z, h->q, done);
   finalize(h, kFinZQ, g.grid, done);
   k_xpay<<<grid1(n), kBlock, 0, s>>>(n, h->z, h->p, h->scal, 0, done);
 }
 
 void cg_iteration(amg_hierarchy *h) {
-  if (h->params.cycle == AMG_CYCLE_K) {
+  if (flexible(h)) {
     fcg_iteration(h);
     return;
   }
@@ -1621,7 +1829,7 @@ amg_status pcg(amg_hierarchy *h, const double *b_user, double *x_user, double rt
                                                           h->partials);
   finalize(h, kFinInit, g.grid, nullptr);
   k_zero_if_zero_rhs<<<grid1(n), kBlock, 0, s>>>(n, h->x, h->scal);
-  if (h->params.cycle == AMG_CYCLE_K) AMG_TRY(kcycle_perm(h, h->r, h->z, nullptr, done));
+  if (flexible(h)) AMG_TRY(precond_perm(h, h->r, h->z, nullptr, done));
   else AMG_TRY(vcycle_perm(h, h->r, h->z, true, done));
   k_xpay<<<grid1(n), kBlock, 0, s>>>(n, h->z, h->p, h->scal, 1, done);
   // iterations in chunks; the chunk length follows the observed convergence
@@ -1704,11 +1912,12 @@ amg_status time_vcycle(amg_hierarchy *h, int32_t reps, double *ms, double *bytes
   // per level l < L: down step z(V+4) + 4(n+1) + n(Vr+3V) + n_c(V+4) and the
   // prolongation into it n(3V+4); per coarse level 0 < c < L its
   // post-smoothing z(V+4) + 4(n+1) + 3V n; the coarsest 8 n_L^2 + V n_L; the
-  // level-0 post-smoothing z(V+4) + 4(n+1) + n(16+2V)
+  // level-0 post-smoothing z(V+4) + 4(n+1) + n(16+2V); the iterative
+  // coarsest solve is not counted (its traffic stays in L2)
   const int32_t L = (int32_t)h->lv.size() - 1;
   const double V = h->params.precision == AMG_FP32 ? 4.0 : 8.0;
   const double nL = h->C.n;
-  double b = 8.0 * nL * nL + (L == 0 ? 16.0 : V) * nL;
+  double b = coarse_is_pcg(h) ? 0.0 : 8.0 * nL * nL + (L == 0 ? 16.0 : V) * nL;
   for (int32_t l = 0; l < L; ++l) {
     const double n = h->lv[l].n, z = (double)h->lv[l].nnz, nc = h->lv[l + 1].n;
     const double Vr = l == 0 ? 8.0 : V;

@@ -360,3 +360,31 @@ def test_exact_fp32_level0_values_are_lossless(precision):
     ha = setup(Aa, precision=prec)
     ha_off = setup(Aa, precision=prec, flags=amg.FLAG_NO_VALUE_COMPRESSION)
     assert ha.time_kernel(4, 0, reps=1)[1] == ha_off.time_kernel(4, 0, reps=1)[1]
+
+
+@pytest.mark.parametrize("config", [
+    {"pre": 3, "post": 2},                                   # extra sweeps on level 0
+    {"cycle": 1},                                            # K-cycle with flexible CG
+    {"coarse_solver": 1, "pre": 4, "post": 4},               # CG coarsest, flexible CG
+])
+def test_exact_fp32_level0_values_are_lossless_in_every_product(config):
+    """Every level-0 product of an FP64 hierarchy (extra pre- and post-sweeps,
+    the K-cycle's and flexible CG's products) reads the exact FP32 copy of A
+    without changing a bit of the iterates."""
+    import torch
+
+    from paper_2006_16147_amd import amg
+
+    c = inputs.small_case(20, seed=1)
+    A, b = c["A"], c["b"]
+    on = setup(A, **config)
+    off = setup(A, flags=amg.FLAG_NO_VALUE_COMPRESSION, **config)
+    r = to_dev(np.random.default_rng(5).uniform(-1, 1, A.n))
+    z1, z2 = torch.zeros_like(r), torch.zeros_like(r)
+    amg.amg_vcycle_apply(on, r, z1)
+    amg.amg_vcycle_apply(off, r, z2)
+    assert torch.equal(z1, z2)
+    s1, i1, x1 = solve(on, b, rtol=1e-10)
+    s2, i2, x2 = solve(off, b, rtol=1e-10)
+    assert s1 == s2 == 0 and i1["iterations"] == i2["iterations"]
+    np.testing.assert_array_equal(x1.view(np.uint64), x2.view(np.uint64))
