@@ -66,6 +66,11 @@ static double diag_of(const orc_csr *A, int32_t i) {
   return k >= 0 ? A->val[k] : 0.0;
 }
 
+static int i32_cmp(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
 static double dot(int64_t n, const double *x, const double *y) {
   if (n == 0) return 0.0;
   double s = x[0] * y[0];
@@ -259,6 +264,20 @@ void orc_restrict(int32_t n, int32_t nc, const int32_t *agg, const double *p,
   free(seen);
 }
 
+/* y = M x for a rectangular CSR M (rows summed over ascending columns;
+ * an empty row gives 0) */
+static void csr_apply(const orc_csr *M, const double *x, double *y) {
+  for (int32_t i = 0; i < M->n; ++i) {
+    int64_t k = M->rp[i];
+    double s = 0.0;
+    if (k < M->rp[i + 1]) {
+      s = M->val[k] * x[M->ci[k]];
+      for (++k; k < M->rp[i + 1]; ++k) s = s + M->val[k] * x[M->ci[k]];
+    }
+    y[i] = s;
+  }
+}
+
 /* one Galerkin term of the pairwise product */
 typedef struct {
   int32_t J, lo, hi;
@@ -343,6 +362,181 @@ int orc_galerkin_pairwise(const orc_csr *A, int32_t nc, const int32_t *agg,
   Ac->rp = rp;
   Ac->ci = ci;
   Ac->val = vv;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* smoothed aggregation (the alternative to the K-cycle in Section 3.2)      */
+/* ------------------------------------------------------------------------ */
+
+/* omega = 1 / ||D^-1 A||_inf: per row (sum over ascending j of |a_ij|) / a_ii,
+ * the maximum over rows, inverted. */
+double orc_smoothing_omega(const orc_csr *A) {
+  double nrm = 0.0;
+  for (int32_t i = 0; i < A->n; ++i) {
+    double s = 0.0;
+    for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) s = s + fabs(A->val[k]);
+    double r = s / diag_of(A, i);
+    if (r > nrm) nrm = r;
+  }
+  return 1.0 / nrm;
+}
+
+/* Pbar = (I - omega D^-1 A) P for the tentative prolongator P (one entry
+ * p[i] in column agg[i] per row). Row i of Pbar has one entry per distinct
+ * aggregate J among the columns of row i of A, J ascending:
+ *   s = sum over j ascending with agg[j] = J of a_ij p_j,  t = s / a_ii,
+ *   Pbar(i, J) = (J = agg[i] ? p_i : 0) - omega t.
+ * Pbar has nc columns. */
+int orc_smooth_prolongator(const orc_csr *A, int32_t nc, const int32_t *agg, const double *p,
+                           double omega, orc_csr *Pb) {
+  int32_t n = A->n;
+  int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+  int32_t *cols = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  double *acc = (double *)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
+  for (int32_t J = 0; J < nc; ++J) pos[J] = -1;
+  int st = csr_alloc(Pb, n, A->nnz); /* at most one entry per entry of A */
+  if (st) return st;
+  int64_t out = 0;
+  Pb->rp[0] = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t cnt = 0;
+    for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+      int32_t j = A->ci[k], J = agg[j];
+      double t = A->val[k] * p[j];
+      if (pos[J] < 0) {
+        pos[J] = cnt;
+        cols[cnt++] = J;
+        acc[J] = t;
+      } else {
+        acc[J] = acc[J] + t;
+      }
+    }
+    /* ascending J (insertion sort: a row has few distinct aggregates) */
+    for (int32_t a = 1; a < cnt; ++a) {
+      int32_t v = cols[a], b = a - 1;
+      while (b >= 0 && cols[b] > v) {
+        cols[b + 1] = cols[b];
+        --b;
+      }
+      cols[b + 1] = v;
+    }
+    double aii = diag_of(A, i);
+    for (int32_t a = 0; a < cnt; ++a) {
+      int32_t J = cols[a];
+      double t = acc[J] / aii;
+      double base = J == agg[i] ? p[i] : 0.0;
+      Pb->ci[out] = J;
+      Pb->val[out] = base - omega * t;
+      ++out;
+      pos[J] = -1;
+    }
+    Pb->rp[i + 1] = (int32_t)out;
+  }
+  Pb->nnz = out;
+  free(pos);
+  free(cols);
+  free(acc);
+  return ORC_OK;
+}
+
+/* C(r, :) = sum over k in [xp[r], xp[r+1]) ascending of coef[k] B(src[k], :):
+ * every column's terms coef[k] * b are added in k order onto the first one;
+ * columns ascending. B has ncols columns; C has nr rows. */
+static int rowcomb(int32_t nr, const int32_t *xp, const int32_t *src, const double *coef,
+                   const orc_csr *B, int32_t ncols, orc_csr *C) {
+  int32_t *mark = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ncols > 0 ? ncols : 1));
+  int32_t *cols = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ncols > 0 ? ncols : 1));
+  double *acc = (double *)malloc(sizeof(double) * (size_t)(ncols > 0 ? ncols : 1));
+  for (int32_t J = 0; J < ncols; ++J) mark[J] = 0;
+  int32_t *rp = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nr + 1));
+  int64_t cap = 1024, out = 0;
+  int32_t *ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+  double *vv = (double *)malloc(sizeof(double) * (size_t)cap);
+  rp[0] = 0;
+  for (int32_t r = 0; r < nr; ++r) {
+    int32_t cnt = 0;
+    for (int32_t k = xp[r]; k < xp[r + 1]; ++k) {
+      int32_t s = src[k];
+      for (int64_t e = B->rp[s]; e < B->rp[s + 1]; ++e) {
+        int32_t J = B->ci[e];
+        double t = coef[k] * B->val[e];
+        if (!mark[J]) {
+          mark[J] = 1;
+          cols[cnt++] = J;
+          acc[J] = t;
+        } else {
+          acc[J] = acc[J] + t;
+        }
+      }
+    }
+    qsort(cols, (size_t)cnt, sizeof(int32_t), i32_cmp);
+    if (out + cnt > cap) {
+      while (out + cnt > cap) cap *= 2;
+      ci = (int32_t *)realloc(ci, sizeof(int32_t) * (size_t)cap);
+      vv = (double *)realloc(vv, sizeof(double) * (size_t)cap);
+    }
+    for (int32_t a = 0; a < cnt; ++a) {
+      ci[out] = cols[a];
+      vv[out] = acc[cols[a]];
+      mark[cols[a]] = 0;
+      ++out;
+    }
+    rp[r + 1] = (int32_t)out;
+  }
+  free(mark);
+  free(cols);
+  free(acc);
+  C->n = nr;
+  C->nnz = out;
+  C->rp = rp;
+  C->ci = ci;
+  C->val = vv;
+  return ORC_OK;
+}
+
+/* transpose of an n x ncols CSR: row J lists the rows i holding column J,
+ * ascending i */
+static int csr_transpose(const orc_csr *A, int32_t ncols, orc_csr *T) {
+  int st = csr_alloc(T, ncols, A->nnz);
+  if (st) return st;
+  for (int32_t J = 0; J <= ncols; ++J) T->rp[J] = 0;
+  for (int64_t k = 0; k < A->nnz; ++k) T->rp[A->ci[k] + 1] += 1;
+  for (int32_t J = 0; J < ncols; ++J) T->rp[J + 1] += T->rp[J];
+  int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ncols > 0 ? ncols : 1));
+  for (int32_t J = 0; J < ncols; ++J) next[J] = T->rp[J];
+  for (int32_t i = 0; i < A->n; ++i)
+    for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+      int32_t J = A->ci[k];
+      T->ci[next[J]] = i;
+      T->val[next[J]] = A->val[k];
+      ++next[J];
+    }
+  free(next);
+  return ORC_OK;
+}
+
+/* A_c = Pbar^T A Pbar (Section 3.1's Galerkin product with the smoothed
+ * prolongator): first AP = A Pbar (row i: a_ij Pbar(j, :) over ascending j),
+ * then A_c(I, :) = sum over ascending i of Pbar(i, I) AP(i, :); the lower
+ * triangle is then replaced by the upper one, so A_c is bitwise symmetric. */
+int orc_galerkin_general(const orc_csr *A, const orc_csr *Pb, int32_t nc, orc_csr *Ac) {
+  orc_csr AP = {0}, PbT = {0};
+  int st = rowcomb(A->n, A->rp, A->ci, A->val, Pb, nc, &AP);
+  if (!st) st = csr_transpose(Pb, nc, &PbT);
+  if (!st) st = rowcomb(nc, PbT.rp, PbT.ci, PbT.val, &AP, nc, Ac);
+  orc_csr_free(&AP);
+  orc_csr_free(&PbT);
+  if (st) return st;
+  for (int32_t I = 0; I < nc; ++I)
+    for (int64_t k = Ac->rp[I]; k < Ac->rp[I + 1]; ++k) {
+      int32_t J = Ac->ci[k];
+      if (J < I) {
+        int64_t m = find_entry(Ac, J, I);
+        if (m < 0) return ORC_ERR_ARG; /* cannot happen: the pattern is symmetric */
+        Ac->val[k] = Ac->val[m];
+      }
+    }
   return ORC_OK;
 }
 
@@ -431,6 +625,10 @@ struct orc_hier {
   int32_t coarse_solver; /* 0: Cholesky; 1: orc_coarse_pcg */
   double coarse_rtol;
   int32_t coarse_maxit;
+  int32_t smooth;                 /* smoothed prolongators (Pbar) between levels */
+  orc_csr Pb[ORC_MAX_LEVELS];     /* level l -> l+1 Pbar, n_l x n_{l+1} */
+  orc_csr PbT[ORC_MAX_LEVELS];    /* its transpose */
+  double omega[ORC_MAX_LEVELS];
 };
 
 void orc_free(orc_hier *h) {
@@ -441,6 +639,8 @@ void orc_free(orc_hier *h) {
     free(h->agg[l]);
     free(h->p[l]);
     free(h->m[l]);
+    orc_csr_free(&h->Pb[l]);
+    orc_csr_free(&h->PbT[l]);
   }
   free(h->L);
   free(h);
@@ -480,6 +680,11 @@ static int64_t pairwise_sweep(const orc_csr *A, const double *w, orc_csr *Ac,
 
 int orc_setup(const orc_csr *A0, const double *w0, int32_t sweeps,
               int32_t max_coarse, int32_t max_levels, orc_hier **out) {
+  return orc_setup_opts(A0, w0, sweeps, max_coarse, max_levels, 0, out);
+}
+
+int orc_setup_opts(const orc_csr *A0, const double *w0, int32_t sweeps, int32_t max_coarse,
+                   int32_t max_levels, int32_t smooth, orc_hier **out) {
   *out = NULL;
   if (!A0 || sweeps < 1 || max_coarse < 1 || max_levels < 1) return ORC_ERR_ARG;
   if (max_levels > ORC_MAX_LEVELS) max_levels = ORC_MAX_LEVELS;
@@ -489,6 +694,7 @@ int orc_setup(const orc_csr *A0, const double *w0, int32_t sweeps,
     for (int32_t i = 0; i < A0->n; ++i)
       if (!(w0[i] != 0.0) || !isfinite(w0[i])) return ORC_ERR_ARG;
   orc_hier *h = (orc_hier *)calloc(1, sizeof(orc_hier));
+  h->smooth = smooth ? 1 : 0;
   csr_copy(A0, &h->A[0]);
   h->w[0] = (double *)malloc(sizeof(double) * (size_t)A0->n);
   for (int32_t i = 0; i < A0->n; ++i) h->w[0][i] = w0 ? w0[i] : 1.0;
@@ -545,8 +751,23 @@ int orc_setup(const orc_csr *A0, const double *w0, int32_t sweeps,
     h->agg[l] = agg_c;
     h->p[l] = p_c;
     h->nsweeps[l] = done;
-    h->A[l + 1] = cur;
     h->w[l + 1] = wcur;
+    if (h->smooth) {
+      /* the tentative product P_l only chose the aggregates and restricted
+       * w; the next level is the Galerkin product with Pbar_l */
+      int32_t nc = cur.n;
+      orc_csr_free(&cur);
+      h->omega[l] = orc_smoothing_omega(&h->A[l]);
+      st = orc_smooth_prolongator(&h->A[l], nc, agg_c, p_c, h->omega[l], &h->Pb[l]);
+      if (!st) st = csr_transpose(&h->Pb[l], nc, &h->PbT[l]);
+      if (!st) st = orc_galerkin_general(&h->A[l], &h->Pb[l], nc, &h->A[l + 1]);
+      if (st) {
+        orc_free(h);
+        return st;
+      }
+    } else {
+      h->A[l + 1] = cur;
+    }
     ++l;
   }
   h->nlev = l + 1;
@@ -598,6 +819,17 @@ void orc_level_l1diag(const orc_hier *h, int32_t l, double *m) {
 void orc_level_w(const orc_hier *h, int32_t l, double *w) {
   memcpy(w, h->w[l], sizeof(double) * (size_t)h->A[l].n);
 }
+
+int64_t orc_level_pbar_nnz(const orc_hier *h, int32_t l) { return h->Pb[l].nnz; }
+
+void orc_level_pbar(const orc_hier *h, int32_t l, int32_t *rp, int32_t *ci, double *val) {
+  const orc_csr *P = &h->Pb[l];
+  memcpy(rp, P->rp, sizeof(int32_t) * ((size_t)P->n + 1));
+  memcpy(ci, P->ci, sizeof(int32_t) * (size_t)P->nnz);
+  memcpy(val, P->val, sizeof(double) * (size_t)P->nnz);
+}
+
+double orc_level_omega(const orc_hier *h, int32_t l) { return h->omega[l]; }
 
 void orc_coarse_factor(const orc_hier *h, double *L) {
   memcpy(L, h->L, sizeof(double) * (size_t)h->nL * (size_t)h->nL);
@@ -687,10 +919,18 @@ static void cycle(const orc_hier *h, int32_t l, int32_t pre, int32_t post, int k
   /* residual, restriction, coarse correction, prolongation */
   orc_spmv(A, z, t);
   for (int32_t i = 0; i < n; ++i) t[i] = r[i] - t[i];
-  orc_restrict(n, nc, h->agg[l], h->p[l], t, rc);
+  if (h->smooth) csr_apply(&h->PbT[l], t, rc); /* rc = Pbar^T t */
+  else orc_restrict(n, nc, h->agg[l], h->p[l], t, rc);
   if (kcycle && l + 1 < L) fcg2(h, l + 1, pre, post, rc, zc);
   else cycle(h, l + 1, pre, post, kcycle, rc, zc);
-  for (int32_t i = 0; i < n; ++i) z[i] = z[i] + h->p[l][i] * zc[h->agg[l][i]];
+  if (h->smooth) {
+    double *u = (double *)malloc(sizeof(double) * (size_t)n);
+    csr_apply(&h->Pb[l], zc, u); /* u = Pbar zc */
+    for (int32_t i = 0; i < n; ++i) z[i] = z[i] + u[i];
+    free(u);
+  } else {
+    for (int32_t i = 0; i < n; ++i) z[i] = z[i] + h->p[l][i] * zc[h->agg[l][i]];
+  }
   /* post-smoothing */
   for (int32_t s = 0; s < post; ++s) {
     orc_spmv(A, z, t);

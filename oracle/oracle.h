@@ -99,6 +99,16 @@ int orc_galerkin_pairwise(const orc_csr *A, int32_t nc, const int32_t *agg,
 
 void orc_csr_free(orc_csr *A);
 
+/* Smoothed aggregation (the alternative to the K-cycle in Section 3.2):
+ * omega = 1 / ||D^-1 A||_inf with D = diag(A); the smoothed prolongator
+ * Pbar = (I - omega D^-1 A) P of the tentative P given as (agg, p), with nc
+ * columns (row order and sums as stated in oracle.c); and the Galerkin
+ * product A_c = Pbar^T A Pbar (lower triangle mirrored from the upper). */
+double orc_smoothing_omega(const orc_csr *A);
+int orc_smooth_prolongator(const orc_csr *A, int32_t nc, const int32_t *agg, const double *p,
+                           double omega, orc_csr *Pb);
+int orc_galerkin_general(const orc_csr *A, const orc_csr *Pb, int32_t nc, orc_csr *Ac);
+
 /* l1-Jacobi diagonal, eq. (l1weights) with nb = 1:
  * m_i = a_ii + (sum over j != i, ascending, of |a_ij|). */
 void orc_l1_diag(const orc_csr *A, double *m);
@@ -128,6 +138,12 @@ typedef struct orc_hier orc_hier;
  * (all ones). The input matrix is copied. */
 int orc_setup(const orc_csr *A, const double *w0, int32_t sweeps,
               int32_t max_coarse, int32_t max_levels, orc_hier **out);
+/* As orc_setup; smooth = 1 builds every next level with the smoothed
+ * prolongator Pbar_l instead of the tentative P_l (which still chooses the
+ * aggregates and restricts w), and the cycles restrict with Pbar^T and
+ * prolongate with Pbar. */
+int orc_setup_opts(const orc_csr *A, const double *w0, int32_t sweeps, int32_t max_coarse,
+                   int32_t max_levels, int32_t smooth, orc_hier **out);
 void orc_free(orc_hier *h);
 
 int32_t orc_num_levels(const orc_hier *h);
@@ -142,6 +158,11 @@ void orc_level_l1diag(const orc_hier *h, int32_t l, double *m);
 void orc_level_w(const orc_hier *h, int32_t l, double *w);
 /* number of pairwise sweeps actually run when building level l+1 */
 int32_t orc_level_sweeps(const orc_hier *h, int32_t l);
+/* smoothed prolongator of level l (smooth hierarchies): nnz, CSR copy
+ * (n_l + 1 offsets), and its omega */
+int64_t orc_level_pbar_nnz(const orc_hier *h, int32_t l);
+void orc_level_pbar(const orc_hier *h, int32_t l, int32_t *rp, int32_t *ci, double *val);
+double orc_level_omega(const orc_hier *h, int32_t l);
 /* coarsest Cholesky factor, row-major n_L x n_L */
 void orc_coarse_factor(const orc_hier *h, double *L);
 /* Coarsest solver of the hierarchy's cycles: solver 0 applies the dense

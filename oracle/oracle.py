@@ -30,6 +30,9 @@ __all__ = [
     "cholesky_solve",
     "smooth_w",
     "coarse_pcg",
+    "smoothing_omega",
+    "smooth_prolongator",
+    "galerkin_general",
     "Hierarchy",
 ]
 
@@ -98,6 +101,14 @@ def load():
         "orc_cholesky": (C.c_int, [C.c_int32, _F64P]),
         "orc_cholesky_solve": (None, [C.c_int32, _F64P, _F64P, _F64P]),
         "orc_coarse_pcg": (C.c_int32, [P, _F64P, _F64P, C.c_double, C.c_int32, _F64P]),
+        "orc_smoothing_omega": (C.c_double, [P]),
+        "orc_smooth_prolongator": (C.c_int, [P, C.c_int32, _I32P, _F64P, C.c_double, P]),
+        "orc_galerkin_general": (C.c_int, [P, P, C.c_int32, P]),
+        "orc_setup_opts": (C.c_int, [P, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                     C.POINTER(C.c_void_p)]),
+        "orc_level_pbar_nnz": (C.c_int64, [C.c_void_p, C.c_int32]),
+        "orc_level_pbar": (None, [C.c_void_p, C.c_int32, _I32P, _I32P, _F64P]),
+        "orc_level_omega": (C.c_double, [C.c_void_p, C.c_int32]),
         "orc_set_coarse_solver": (None, [C.c_void_p, C.c_int32, C.c_double, C.c_int32]),
         "orc_setup": (C.c_int, [P, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                 C.POINTER(C.c_void_p)]),
@@ -249,6 +260,51 @@ def coarse_pcg(A, m, b, rtol=1e-4, maxit=30):
     return x, int(it)
 
 
+def _take_csr(out, nrows):
+    """Copies a C-allocated CSR into numpy (rp, ci, val) and frees it."""
+    nnz = int(out.nnz)
+    rp = np.ctypeslib.as_array(out.rp, shape=(nrows + 1,)).copy()
+    ci = np.ctypeslib.as_array(out.ci, shape=(max(nnz, 1),))[:nnz].copy()
+    val = np.ctypeslib.as_array(out.val, shape=(max(nnz, 1),))[:nnz].copy()
+    load().orc_csr_free(C.byref(out))
+    return rp, ci, val
+
+
+class _RectCsr:
+    """A rows x cols CSR given as (rp, ci, val) (the struct holds rows only)."""
+
+    def __init__(self, rp, ci, val):
+        self.n = len(rp) - 1
+        self.row_ptr, self.col, self.val = rp, ci, val
+
+
+def smoothing_omega(A):
+    """1 / ||D^-1 A||_inf."""
+    return float(load().orc_smoothing_omega(_HostCsr(A).ref))
+
+
+def smooth_prolongator(A, nc, agg, p, omega):
+    """Pbar = (I - omega D^-1 A) P as (rp, ci, val), n x nc."""
+    out = _Csr()
+    st = load().orc_smooth_prolongator(_HostCsr(A).ref, int(nc), _i32(agg), _f64(p),
+                                       float(omega), C.byref(out))
+    if st:
+        raise RuntimeError("orc_smooth_prolongator failed: %d" % st)
+    return _take_csr(out, A.n)
+
+
+def galerkin_general(A, Pb, nc):
+    """Pbar^T A Pbar for Pbar = (rp, ci, val) with nc columns; returns a Csr."""
+    from paper_2006_16147_amd.inputs import Csr
+
+    out = _Csr()
+    st = load().orc_galerkin_general(_HostCsr(A).ref, _HostCsr(_RectCsr(*Pb)).ref, int(nc),
+                                     C.byref(out))
+    if st:
+        raise RuntimeError("orc_galerkin_general failed: %d" % st)
+    return Csr(int(nc), *_take_csr(out, int(nc)))
+
+
 def smooth_w(A, nu, w0=None):
     """nu l1-Jacobi iterations on A w = 0 from the sample w0 (ones if None)."""
     lib = load()
@@ -261,9 +317,11 @@ def smooth_w(A, nu, w0=None):
 class Hierarchy:
     """Oracle multilevel hierarchy (Sections 3.1-3.3)."""
 
-    def __init__(self, A, w=None, sweeps=3, max_coarse=200, max_levels=32, coarse=None):
+    def __init__(self, A, w=None, sweeps=3, max_coarse=200, max_levels=32, coarse=None,
+                 smooth=False):
         """coarse: None for the dense Cholesky coarsest solve, or (rtol, maxit)
-        for the iterative one (CG with the l1-Jacobi diagonal)."""
+        for the iterative one (CG with the l1-Jacobi diagonal). smooth: build
+        the levels with the smoothed prolongators."""
         lib = load()
         self._lib = lib
         self._h = C.c_void_p()
@@ -272,8 +330,8 @@ class Hierarchy:
         if w is not None:
             self._w = _f64(w)
             wv = self._w.ctypes.data_as(C.c_void_p)
-        self.status = lib.orc_setup(hc.ref, wv, sweeps, max_coarse, max_levels,
-                                    C.byref(self._h))
+        self.status = lib.orc_setup_opts(hc.ref, wv, sweeps, max_coarse, max_levels,
+                                         1 if smooth else 0, C.byref(self._h))
         if self.status != Status.OK:
             self._h = None
         elif coarse is not None:
@@ -333,6 +391,18 @@ class Hierarchy:
 
     def sweeps_run(self, l):
         return int(self._lib.orc_level_sweeps(self._h, l))
+
+    def pbar(self, l):
+        """Smoothed prolongator of level l as (rp, ci, val), n_l x n_{l+1}."""
+        n, nnz = self.level_n(l), int(self._lib.orc_level_pbar_nnz(self._h, l))
+        rp = np.empty(n + 1, dtype=np.int32)
+        ci = np.empty(max(nnz, 1), dtype=np.int32)
+        val = np.empty(max(nnz, 1))
+        self._lib.orc_level_pbar(self._h, l, rp, ci, val)
+        return rp, ci[:nnz], val[:nnz]
+
+    def omega(self, l):
+        return float(self._lib.orc_level_omega(self._h, l))
 
     def coarse_factor(self):
         nL = self.level_n(self.num_levels - 1)

@@ -22,6 +22,7 @@ PIN = "tests/test_oracle_paper_pins.py::"
 KC = "tests/test_oracle_kcycle.py::"
 SW = "tests/test_oracle_smooth_w.py::"
 CP = "tests/test_oracle_coarse_pcg.py::"
+SM = "tests/test_oracle_smoothed.py::"
 
 # (mistake, text in oracle.c, replacement, pin test that must reject it)
 MUTATIONS = [
@@ -124,6 +125,23 @@ MUTATIONS = [
     ("coarsest CG: the hierarchy keeps the Cholesky solve",
      "if (h->coarse_solver == 1)", "if (h->coarse_solver == 7)",
      CP + "test_vcycle_with_iterative_coarsest_solves_the_coarsest_system"),
+    ("smoothed P: tentative term dropped",
+     "double base = J == agg[i] ? p[i] : 0.0;", "double base = 0.0;",
+     SM + "test_pbar_is_the_dense_formula"),
+    ("smoothed P: D^-1 dropped",
+     "double t = acc[J] / aii;", "double t = acc[J];",
+     SM + "test_pbar_is_the_dense_formula"),
+    ("smoothed P: omega from the row sums without |.|",
+     "for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) s = s + fabs(A->val[k]);\n    double r",
+     "for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) s = s + A->val[k];\n    double r",
+     SM + "test_omega_is_the_inverse_inf_norm_of_the_scaled_matrix"),
+    ("general Galerkin: coefficient dropped in the row combination",
+     "double t = coef[k] * B->val[e];", "double t = B->val[e];",
+     SM + "test_galerkin_with_pbar_is_the_dense_product"),
+    ("smoothed cycle: prolongation by the tentative P",
+     "csr_apply(&h->Pb[l], zc, u); /* u = Pbar zc */",
+     "for (int32_t i = 0; i < n; ++i) u[i] = h->p[l][i] * zc[h->agg[l][i]];",
+     SM + "test_two_level_vcycle_is_the_error_propagation_product"),
 ]
 
 
