@@ -265,6 +265,60 @@ def bench_coarse(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_smoothed(args):
+    """160^3 Poisson (b = A u): smoothed aggregation (Pbar = (I - omega D^-1 A) P,
+    the alternative to the K-cycle in Section 3.2) against the unsmoothed
+    hierarchy; with 4 l1-Jacobi pre/post sweeps and the CG coarsest solve it
+    is the paper's GPU preconditioner (Section 5). Outer tolerance 1e-6
+    (Section 5) and 1e-8."""
+    import torch
+
+    from paper_2006_16147_amd import amg, inputs
+
+    dev = torch.device("cuda:0")
+    case = inputs.headline_case(args.N, seed=1)
+    A = case["A"]
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    ci = torch.from_numpy(A.col).to(dev)
+    va = torch.from_numpy(A.val).to(dev)
+    b = torch.from_numpy(case["b"]).to(dev)
+    out = {"mode": "smoothed", "workload": "poisson7_%d^3_b=Au_seed1" % args.N}
+    configs = [("V_unsmoothed_l1x1_cholesky", 0, 1, amg.COARSE_CHOLESKY, amg.FP64),
+               ("V_smoothed_l1x1_cholesky", 1, 1, amg.COARSE_CHOLESKY, amg.FP64),
+               ("V_smoothed_l1x4_cg", 1, 4, amg.COARSE_PCG, amg.FP64),
+               ("V_smoothed_l1x4_cg_fp32_prec", 1, 4, amg.COARSE_PCG, amg.FP32),
+               ("V_smoothed_l1x1_cholesky_fp32_prec", 1, 1, amg.COARSE_CHOLESKY, amg.FP32)]
+    for name, sm, sw, cs, prec in configs:
+        setup_ms = []
+        for _ in range(2):
+            h = amg.amg_setup(rp, ci, va, precision=prec, pre=sw, post=sw, coarse_solver=cs,
+                              smooth_p=sm)
+            setup_ms.append(h.setup_times()["total"])
+        res = {"setup_ms_min": round(min(setup_ms), 1), "levels": h.sizes(),
+               "opc": round(h.opc(), 4), "footprint_GB": round(h.footprint_bytes() / 1e9, 3)}
+        for rtol in (1e-6, 1e-8):
+            x = torch.zeros_like(b)
+            times = []
+            for k in range(args.warmup + args.steps):
+                x.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, info = amg.amg_pcg_solve(h, b, x, rtol=rtol, maxit=500)
+                if k >= args.warmup:
+                    times.append((time.perf_counter() - t0) * 1e3)
+            p50 = percentile(times, 50)
+            res["rtol%g" % rtol] = {
+                "p50_ms": round(p50, 3), "p99_ms": round(percentile(times, 99), 3),
+                "iterations": info["iterations"], "rel_res_true": info["rel_res_true"],
+                "ms_per_iteration": round(p50 / max(1, info["iterations"]), 4)}
+        ms, by = h.time_kernel(5, 0, reps=args.vcycles)
+        res["vcycle_ms"] = round(ms, 4)
+        res["vcycle_GBs"] = round(by / ms / 1e6, 1)
+        out[name] = res
+        h.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_variants(args):
     """160^3 Poisson (b = A u), V-cycle PCG in FP64: 3 or 4 pairwise sweeps
     per level, w = ones or an algebraically smooth w (4 l1-Jacobi sweeps on
@@ -434,7 +488,8 @@ def main():
     ap.add_argument("--vcycles", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="headline",
-                    choices=["headline", "aniso", "batch", "serve", "kcycle", "variants", "coarse"],
+                    choices=["headline", "aniso", "batch", "serve", "kcycle", "variants", "coarse",
+                             "smoothed"],
                     help="headline (default): the 160^3 benchmark line; the others print "
                          "their own JSON lines")
     ap.add_argument("--rates", default="10,50,200,500", help="serve mode: arrival rates /s")
@@ -457,7 +512,7 @@ def main():
         torch.cuda.set_device(0)
         {"aniso": bench_aniso, "batch": bench_batch, "serve": bench_serve,
          "kcycle": bench_kcycle, "variants": bench_variants,
-         "coarse": bench_coarse}[args.mode](args)
+         "coarse": bench_coarse, "smoothed": bench_smoothed}[args.mode](args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "

@@ -130,6 +130,13 @@ typedef struct {
   int32_t coarse_maxit;  /* AMG_COARSE_PCG: iteration cap, 1..10000; 30 (Section 5) */
   double coarse_rtol;    /* AMG_COARSE_PCG: relative residual target, >= 0 (0: run
                             coarse_maxit iterations); 1e-4 (Section 5) */
+  int32_t smooth_p;      /* 1: smoothed aggregation (the alternative to the K-cycle in
+                            Section 3.2): the next level is Pbar^T A Pbar with
+                            Pbar = (I - omega D^-1 A) P, omega = 1 / ||D^-1 A||_inf,
+                            D = diag(A), P the tentative prolongator of the matching
+                            sweeps (which still chooses the aggregates and restricts w);
+                            the V-cycle restricts with Pbar^T and prolongates with Pbar.
+                            V-cycle only. 0 */
 } amg_params;
 
 typedef struct {
@@ -206,6 +213,14 @@ amg_status amg_get_level_csr(const amg_hierarchy *h, int32_t l, int32_t *row_ptr
  * p_host[i] the entry P_l(i, agg_host[i]). Either pointer may be NULL. */
 amg_status amg_get_transfer(const amg_hierarchy *h, int32_t l, int32_t *agg_host,
                             double *p_host);
+/* Smoothed prolongator Pbar of level l (l < nlev - 1) of a hierarchy built
+ * with smooth_p = 1: *nnz its number of entries; when the arrays are given
+ * (host, n_l + 1 / nnz / nnz), its CSR with columns in level l + 1's
+ * numbering, ascending in each row; *omega (may be NULL) the omega used.
+ * AMG_ERR_ARG for a hierarchy without smoothing. */
+amg_status amg_get_prolongator(const amg_hierarchy *h, int32_t l, int64_t *nnz,
+                               int32_t *row_ptr_host, int32_t *col_host, double *val_host,
+                               double *omega);
 /* Copies the l1-Jacobi diagonal m of level l (l < nlev - 1; also the
  * coarsest level of an AMG_COARSE_PCG hierarchy, whose CG uses it). */
 amg_status amg_get_l1diag(const amg_hierarchy *h, int32_t l, double *m_host);

@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = (
     "amg_vcycle_apply", "amg_set_stream", "amg_free", "amg_num_levels", "amg_level_info", "amg_get_level_csr",
     "amg_get_transfer", "amg_get_l1diag", "amg_get_w", "amg_footprint_bytes",
     "amg_estimate_footprint", "amg_setup_times", "amg_matching_rounds", "amg_time_kernel",
-    "amg_batch_tile", "amg_status_string",
+    "amg_batch_tile", "amg_status_string", "amg_get_prolongator",
 )
 
 
@@ -66,7 +66,8 @@ class Params(C.Structure):
                 ("pre", C.c_int32), ("post", C.c_int32), ("precision", C.c_int32),
                 ("w", C.c_void_p), ("stream", C.c_void_p), ("flags", C.c_int32),
                 ("cycle", C.c_int32), ("w_sweeps", C.c_int32), ("coarse_solver", C.c_int32),
-                ("coarse_maxit", C.c_int32), ("coarse_rtol", C.c_double)]
+                ("coarse_maxit", C.c_int32), ("coarse_rtol", C.c_double),
+                ("smooth_p", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -110,6 +111,7 @@ def load_library():
         "amg_get_level_csr": (C.c_int, [V, I32, V, V, V]),
         "amg_get_transfer": (C.c_int, [V, I32, V, V]),
         "amg_get_l1diag": (C.c_int, [V, I32, V]),
+        "amg_get_prolongator": (C.c_int, [V, I32, P(I64), V, V, V, P(D)]),
         "amg_get_w": (C.c_int, [V, I32, V]),
         "amg_footprint_bytes": (C.c_size_t, [V]),
         "amg_estimate_footprint": (C.c_size_t, [I64, I64, P(Params)]),
@@ -230,6 +232,21 @@ class Hierarchy:
         self._check(load_library().amg_get_transfer(self._h, l, agg.ctypes.data, p.ctypes.data),
                     "amg_get_transfer")
         return agg, p
+
+    def prolongator(self, l):
+        """Smoothed prolongator of level l: ((rp, ci, val), omega)."""
+        L = load_library()
+        nnz, om = C.c_int64(), C.c_double()
+        self._check(L.amg_get_prolongator(self._h, l, C.byref(nnz), None, None, None, None),
+                    "amg_get_prolongator")
+        n, _ = self.level_info(l)
+        rp = np.empty(n + 1, dtype=np.int32)
+        ci = np.empty(max(nnz.value, 1), dtype=np.int32)
+        val = np.empty(max(nnz.value, 1))
+        self._check(L.amg_get_prolongator(self._h, l, C.byref(nnz), rp.ctypes.data,
+                                          ci.ctypes.data, val.ctypes.data, C.byref(om)),
+                    "amg_get_prolongator")
+        return (rp, ci[:nnz.value], val[:nnz.value]), om.value
 
     def l1diag(self, l):
         n, _ = self.level_info(l)

@@ -22,6 +22,7 @@ ARCH = os.environ.get("AMG_OFFLOAD_ARCH", "gfx950")
 SOURCES = {
     "api.hip": [],
     "setup.hip": ["-ffp-contract=off"],
+    "smooth.hip": ["-ffp-contract=off"],
     "solve.hip": [],
     "batch.hip": [],
 }

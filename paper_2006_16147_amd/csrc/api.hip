@@ -128,6 +128,8 @@ amg_status check_params(const amg_params *p) {
   if (p->w_sweeps < 0 || p->w_sweeps > 1000) return AMG_ERR_ARG;
   if (p->coarse_solver != AMG_COARSE_CHOLESKY && p->coarse_solver != AMG_COARSE_PCG)
     return AMG_ERR_ARG;
+  if (p->smooth_p != 0 && p->smooth_p != 1) return AMG_ERR_ARG;
+  if (p->smooth_p && p->cycle != AMG_CYCLE_V) return AMG_ERR_ARG;
   if (p->coarse_solver == AMG_COARSE_PCG &&
       (p->coarse_maxit < 1 || p->coarse_maxit > 10000 || !(p->coarse_rtol >= 0.0) ||
        !std::isfinite(p->coarse_rtol)))
@@ -165,6 +167,7 @@ void amg_params_default(amg_params *p) {
   p->coarse_solver = AMG_COARSE_CHOLESKY;
   p->coarse_maxit = 30;
   p->coarse_rtol = 1e-4;
+  p->smooth_p = 0;
 }
 
 amg_status amg_setup(const amg_csr *A, const amg_params *params, amg_hierarchy **out) {
@@ -224,7 +227,8 @@ amg_status amg_pcg_solve(amg_hierarchy *h, const double *b, double *x, double rt
 amg_status amg_pcg_solve_batch(amg_hierarchy *h, int32_t k, const double *B, double *X,
                                double rtol, int32_t maxit, amg_solve_info *info) {
   if (!h || k < 0 || !(rtol >= 0.0) || maxit < 0) return AMG_ERR_ARG;
-  if (h->params.cycle != AMG_CYCLE_V || h->params.coarse_solver != AMG_COARSE_CHOLESKY)
+  if (h->params.cycle != AMG_CYCLE_V || h->params.coarse_solver != AMG_COARSE_CHOLESKY ||
+      h->params.smooth_p)
     return AMG_ERR_ARG;
   if (k == 0) return AMG_OK;
   if (!B || !X) return AMG_ERR_ARG;
@@ -287,6 +291,19 @@ amg_status amg_get_transfer(const amg_hierarchy *h, int32_t l, int32_t *agg, dou
   const Level &L = h->lv[l];
   if (agg) AMG_TRY(d2h(h, agg, L.agg, sizeof(int32_t) * L.n));
   if (p) AMG_TRY(d2h(h, p, L.p64, sizeof(double) * L.n));
+  return AMG_OK;
+}
+
+amg_status amg_get_prolongator(const amg_hierarchy *h, int32_t l, int64_t *nnz,
+                               int32_t *rp, int32_t *ci, double *val, double *omega) {
+  if (!h || !nnz || l < 0 || l + 1 >= (int32_t)h->lv.size() || !h->params.smooth_p)
+    return AMG_ERR_ARG;
+  const Level &L = h->lv[l];
+  *nnz = L.pb_nnz;
+  if (omega) *omega = L.omega;
+  if (rp) AMG_TRY(d2h(h, rp, L.pb_rp, sizeof(int32_t) * (L.n + 1)));
+  if (ci) AMG_TRY(d2h(h, ci, L.pb_ci, sizeof(int32_t) * L.pb_nnz));
+  if (val) AMG_TRY(d2h(h, val, L.pb_val, sizeof(double) * L.pb_nnz));
   return AMG_OK;
 }
 

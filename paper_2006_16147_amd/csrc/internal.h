@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <vector>
 
@@ -109,6 +110,21 @@ struct Level {
   // coarsest): preconditioned residuals c1, c2, their products v1 = A c1,
   // v2 = A c2, and the second residual r1
   void *c1 = nullptr, *v1 = nullptr, *r1 = nullptr, *c2 = nullptr, *v2 = nullptr;
+  // smoothed aggregation: Pbar = (I - omega D^-1 A) P to the next level, in
+  // the setup numbering (CSR, n x n_{l+1}), and in the solve numbering as
+  // Pbar (rows by position, sp_*) and Pbar^T (rows by coarse position, st_*)
+  double omega = 0.0;
+  int32_t *pb_rp = nullptr, *pb_ci = nullptr;
+  double *pb_val = nullptr;
+  int64_t pb_nnz = 0;
+  int32_t *sp_rp = nullptr, *sp_ci = nullptr, *st_rp = nullptr, *st_ci = nullptr;
+  double *sp_v64 = nullptr, *st_v64 = nullptr;
+  float *sp_v32 = nullptr, *st_v32 = nullptr;
+  // levels with long rows (the denser coarse levels of smoothed aggregation):
+  // A in CSR in the solve numbering, for kernels with several lanes per row
+  int32_t *lr_rp = nullptr, *lr_ci = nullptr;
+  double *lr_v64 = nullptr;
+  float *lr_v32 = nullptr;
   int32_t sweeps = 0;
   int32_t rounds = 0;
 };
@@ -199,6 +215,17 @@ amg_status scan_exclusive_i32(const int32_t *in, int32_t *out, int32_t n, hipStr
 
 // setup (setup.hip)
 amg_status build_hierarchy(amg_hierarchy *h, const amg_csr *A);
+
+// smoothed aggregation (smooth.hip): Pbar of level F from its matrix and the
+// composed tentative prolongator (agg, p; nc columns), kept in F, and the next
+// level's matrix Pbar^T A Pbar in hierarchy-owned arrays
+amg_status smooth_level(amg_hierarchy *h, Level &F, int32_t nc, const int32_t *agg,
+                        const double *p, int32_t **rp, int32_t **ci, double **val,
+                        int64_t *nnz);
+// Pbar and Pbar^T of level l in the solve numbering (needs both levels' perms)
+amg_status smooth_solve_format(amg_hierarchy *h, int32_t l, bool fp32);
+// level l's A as CSR in the solve numbering (the long-row kernels' format)
+amg_status long_row_csr(amg_hierarchy *h, int32_t l, bool fp32);
 
 // solve-phase helpers (solve.hip)
 amg_status build_solve_formats(amg_hierarchy *h);

@@ -1046,8 +1046,30 @@ amg_status build_hierarchy(amg_hierarchy *h, const amg_csr *A) {
     AMG_HIP(hipMemcpyAsync(F.mptr, mptr, sizeof(int32_t) * (cur.n + 1), hipMemcpyDeviceToDevice,
                            s));
     AMG_HIP(hipMemcpyAsync(F.mem, mem, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
-    h->lv.emplace_back();
-    AMG_TRY(adopt_level(h, cur, h->lv[l + 1]));
+    if (P.smooth_p) {
+      // the tentative product chose the aggregates and restricted w; the
+      // next level is the Galerkin product with the smoothed prolongator
+      const double tr = now_ms();
+      int32_t *crp, *cci;
+      double *cval;
+      int64_t cnnz = 0;
+      const int32_t nc = cur.n;
+      AMG_TRY(smooth_level(h, F, nc, agg_c, p_c, &crp, &cci, &cval, &cnnz));
+      h->lv.emplace_back();
+      Level &Cn = h->lv[l + 1];
+      Cn.n = nc;
+      Cn.nnz = cnnz;
+      Cn.rp = crp;
+      Cn.ci = cci;
+      Cn.val = cval;
+      AMG_TRY(dalloc(h, &Cn.w, (size_t)nc));
+      AMG_HIP(hipMemcpyAsync(Cn.w, cur.w, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
+      tc += now_ms() - tr;  // counted as Galerkin time, not composition
+      t_rap += now_ms() - tr;
+    } else {
+      h->lv.emplace_back();
+      AMG_TRY(adopt_level(h, cur, h->lv[l + 1]));
+    }
     AMG_HIP(hipStreamSynchronize(s));
     delete prev_owner;
     t_compose += now_ms() - tc;

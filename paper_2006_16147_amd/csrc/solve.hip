@@ -428,6 +428,127 @@ __global__ void __launch_bounds__(kBlock) k_post(
   if (DOT) block_partial<1>(d, partials);
 }
 
+// ---- smoothed aggregation: unfused down and up steps (Pbar is not a
+// segment map, so restriction and prolongation are CSR products) ----
+
+// z = M^-1 r and t = r - A z = r - (A M^-1) r (the first sweep from zero)
+template <typename TV, typename TR>
+__global__ void __launch_bounds__(kBlock) k_pre_resid(
+    int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
+    const TV *__restrict__ sval, const TV *__restrict__ minv, const TR *__restrict__ r,
+    TV *__restrict__ z, TV *__restrict__ t, const int32_t *__restrict__ done) {
+  if (*done) return;
+  int32_t rb, re;
+  rows_of_block(n, chunk, &rb, &re);
+  for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
+    int32_t base, w;
+    sell_row(sptr, row, &base, &w);
+    const TV acc = sell_dot(col, sval, base, w, [&](int32_t c) { return (TV)r[c]; });
+    const TV ri = (TV)r[row];
+    z[row] = ri * minv[row];
+    t[row] = ri - acc;
+  }
+}
+
+// t = r - A z
+template <typename TV, typename TR, typename TA = TV>
+__global__ void __launch_bounds__(kBlock) k_resid(
+    int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
+    const TA *__restrict__ val, const TR *__restrict__ r, const TV *__restrict__ z,
+    TV *__restrict__ t, const int32_t *__restrict__ done) {
+  if (*done) return;
+  int32_t rb, re;
+  rows_of_block(n, chunk, &rb, &re);
+  for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
+    int32_t base, w;
+    sell_row(sptr, row, &base, &w);
+    const TV acc = sell_dot_t<TV, TA>(col, val, base, w, [&](int32_t c) { return z[c]; });
+    t[row] = (TV)r[row] - acc;
+  }
+}
+
+// sum over row i of a CSR matrix of val * x(col), with LPR consecutive lanes
+// per row: lane k takes the entries k, k + LPR, ..., then the lanes' sums
+// are added across the group (every lane of the group gets the total)
+template <typename TV, int LPR, typename TA, typename X>
+__device__ __forceinline__ TV csr_row_dot(int32_t i, int32_t nr, const int32_t *__restrict__ rp,
+                                          const int32_t *__restrict__ ci,
+                                          const TA *__restrict__ val, X x) {
+  const int lane = threadIdx.x % LPR;
+  TV acc = 0;
+  if (i < nr) {
+    const int32_t e1 = rp[i + 1];
+    for (int32_t e = rp[i] + lane; e < e1; e += LPR) acc += (TV)val[e] * x(ci[e]);
+  }
+  for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPR);
+  return acc;
+}
+
+// y = M x for a CSR M, or with ADD y += M x (LPR lanes per row)
+template <typename TV, bool ADD, int LPR>
+__global__ void __launch_bounds__(kBlock) k_csr_apply(int32_t nr, const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ ci,
+                                                      const TV *__restrict__ val,
+                                                      const TV *__restrict__ x, TV *__restrict__ y,
+                                                      const int32_t *__restrict__ done) {
+  if (*done) return;
+  const int32_t i = (int32_t)(((int64_t)blockIdx.x * kBlock + threadIdx.x) / LPR);
+  const TV acc = csr_row_dot<TV, LPR>(i, nr, rp, ci, val, [&](int32_t c) { return x[c]; });
+  if (i < nr && threadIdx.x % LPR == 0) y[i] = ADD ? y[i] + acc : acc;
+}
+
+// smoothing on a long-row level (CSR in the solve order, LPR lanes per row):
+// MODE 0: y = z + M^-1 (r - A z); MODE 1: y = r - A z (the residual)
+template <typename TV, typename TR, int MODE, int LPR>
+__global__ void __launch_bounds__(kBlock) k_smooth_rows(
+    int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const TV *__restrict__ val, const TV *__restrict__ minv, const TR *__restrict__ r,
+    const TV *__restrict__ z, TV *__restrict__ y, const int32_t *__restrict__ done) {
+  if (*done) return;
+  const int32_t i = (int32_t)(((int64_t)blockIdx.x * kBlock + threadIdx.x) / LPR);
+  const TV acc = csr_row_dot<TV, LPR>(i, n, rp, ci, val, [&](int32_t c) { return z[c]; });
+  if (i < n && threadIdx.x % LPR == 0) {
+    const TV res = (TV)r[i] - acc;
+    y[i] = MODE == 0 ? z[i] + res * minv[i] : res;
+  }
+}
+
+// lanes per row for rows of `avg` entries on average
+inline int lanes_for(double avg) {
+  return avg >= 96 ? 32 : avg >= 40 ? 16 : avg >= 12 ? 8 : avg >= 6 ? 4 : avg >= 3 ? 2 : 1;
+}
+
+template <typename TV, bool ADD>
+void csr_apply(hipStream_t s, int32_t nr, int64_t nnz, const int32_t *rp, const int32_t *ci,
+               const TV *val, const TV *x, TV *y, const int32_t *done) {
+  const int lpr = lanes_for(nr > 0 ? (double)nnz / nr : 1.0);
+  const int32_t g = ceil_div((int64_t)nr * lpr, kBlock);
+  switch (lpr) {
+    case 1: k_csr_apply<TV, ADD, 1><<<g, kBlock, 0, s>>>(nr, rp, ci, val, x, y, done); break;
+    case 2: k_csr_apply<TV, ADD, 2><<<g, kBlock, 0, s>>>(nr, rp, ci, val, x, y, done); break;
+    case 4: k_csr_apply<TV, ADD, 4><<<g, kBlock, 0, s>>>(nr, rp, ci, val, x, y, done); break;
+    case 8: k_csr_apply<TV, ADD, 8><<<g, kBlock, 0, s>>>(nr, rp, ci, val, x, y, done); break;
+    case 16: k_csr_apply<TV, ADD, 16><<<g, kBlock, 0, s>>>(nr, rp, ci, val, x, y, done); break;
+    default: k_csr_apply<TV, ADD, 32><<<g, kBlock, 0, s>>>(nr, rp, ci, val, x, y, done); break;
+  }
+}
+
+template <typename TV, typename TR, int MODE>
+void smooth_rows(hipStream_t s, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                 const TV *val, const TV *minv, const TR *r, const TV *z, TV *y,
+                 const int32_t *done) {
+  const int lpr = lanes_for(n > 0 ? (double)nnz / n : 1.0);
+  const int32_t g = ceil_div((int64_t)n * lpr, kBlock);
+  switch (lpr) {
+    case 1: k_smooth_rows<TV, TR, MODE, 1><<<g, kBlock, 0, s>>>(n, rp, ci, val, minv, r, z, y, done); break;
+    case 2: k_smooth_rows<TV, TR, MODE, 2><<<g, kBlock, 0, s>>>(n, rp, ci, val, minv, r, z, y, done); break;
+    case 4: k_smooth_rows<TV, TR, MODE, 4><<<g, kBlock, 0, s>>>(n, rp, ci, val, minv, r, z, y, done); break;
+    case 8: k_smooth_rows<TV, TR, MODE, 8><<<g, kBlock, 0, s>>>(n, rp, ci, val, minv, r, z, y, done); break;
+    case 16: k_smooth_rows<TV, TR, MODE, 16><<<g, kBlock, 0, s>>>(n, rp, ci, val, minv, r, z, y, done); break;
+    default: k_smooth_rows<TV, TR, MODE, 32><<<g, kBlock, 0, s>>>(n, rp, ci, val, minv, r, z, y, done); break;
+  }
+}
+
 // Up step: post-smoothing of the coarse level c for this block's kBlock
 // coarse rows, y = z_c + M^-1 (r_c - A_c z_c) (kept in LDS), then the
 // prolongation z_f += P y over the fine segments of those rows.
@@ -1224,6 +1345,25 @@ const double *ppv<double>(const Level &L) { return L.pp64; }
 template <>
 const float *ppv<float>(const Level &L) { return L.pp32; }
 
+template <typename TV>
+const TV *pbar_vals(const Level &L);
+template <>
+const double *pbar_vals<double>(const Level &L) { return L.sp_v64; }
+template <>
+const float *pbar_vals<float>(const Level &L) { return L.sp_v32; }
+template <typename TV>
+const TV *lr_vals(const Level &L);
+template <>
+const double *lr_vals<double>(const Level &L) { return L.lr_v64; }
+template <>
+const float *lr_vals<float>(const Level &L) { return L.lr_v32; }
+template <typename TV>
+const TV *pbart_vals(const Level &L);
+template <>
+const double *pbart_vals<double>(const Level &L) { return L.st_v64; }
+template <>
+const float *pbart_vals<float>(const Level &L) { return L.st_v32; }
+
 void finalize(amg_hierarchy *h, int32_t op, int32_t nparts, const int32_t *done) {
   k_finalize<<<1, 1024, 0, h->stream>>>(op, nparts, h->partials, h->scal, done);
 }
@@ -1334,46 +1474,15 @@ void one_level_cycle(amg_hierarchy *h, const double *r0, double *z0, bool dot, c
   }
 }
 
-// V-cycle z0 = B r0 on the aggregate-major vectors of level 0. With dot, the
-// last kernel also writes the block partials of (r0, z0), finalized into the
-// CG scalars, or, with a dot partner dv, of (dv, z0), left to the caller.
+// Level 0 after the coarse correction (z holds it): post - 1 extra sweeps,
+// then the last into z0, with dot the block partials of (r0, z0) finalized
+// into the CG scalars, or of (dv, z0) left to the caller.
 template <typename TV>
-void vcycle_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const double *dv,
-              const int32_t *done) {
+void level0_post(amg_hierarchy *h, const double *r0, TV *z, double *z0, bool dot,
+                 const double *dv, const int32_t *done) {
   hipStream_t s = h->stream;
-  const int32_t L = (int32_t)h->lv.size() - 1;
-  if (L == 0) {
-    one_level_cycle(h, r0, z0, dot, dv, done);
-    return;
-  }
-  std::vector<TV *> zb(L);
-  const bool tail = L >= 2 && h->params.pre == 1 && h->params.post == 1 &&
-                    h->lv[L - 1].n <= kTailMax && h->C.n <= kTailCoarseMax && !coarse_is_pcg(h);
-  const int32_t down_end = tail ? L - 1 : L;  // levels [0, down_end) take the down step
-  zb[0] = launch_down<TV, double>(h, 0, r0, done);
-  for (int32_t l = 1; l < down_end; ++l)
-    zb[l] = launch_down<TV, TV>(h, l, (const TV *)h->lv[l].r, done);
-  if (tail) {
-    Level &T = h->lv[L - 1];
-    Level &F = h->lv[L - 2];
-    k_tail<TV><<<1, 1024, 0, s>>>(T.n, T.S.sptr, T.S.col, svals<TV>(T), vals<TV>(T), minv<TV>(T),
-                                  (const TV *)T.r, T.seg, T.aggp, ppv<TV>(T), h->C.n, h->C.Ainv,
-                                  F.n, F.aggp, ppv<TV>(F), zb[L - 2], done);
-    for (int32_t c = L - 2; c >= 1; --c) launch_up<TV>(h, c, zb[c], zb[c - 1], done);
-  } else {
-    Level &F = h->lv[L - 1];
-    const int32_t nL = h->C.n;
-    if (coarse_is_pcg(h))
-      launch_coarse_pcg<TV, TV>(h, (const TV *)h->lv[L].r, nullptr, F.n, F.aggp, ppv<TV>(F),
-                                zb[L - 1], done);
-    else
-      k_coarse_prolong<TV><<<1, 1024, 2 * sizeof(double) * nL, s>>>(
-          nL, h->C.Ainv, (const TV *)h->lv[L].r, F.n, F.aggp, ppv<TV>(F), zb[L - 1], done);
-    for (int32_t c = L - 1; c >= 1; --c) launch_up<TV>(h, c, zb[c], zb[c - 1], done);
-  }
-  // level 0: extra post sweeps, then the last with the (r, z) partials
   Level &F = h->lv[0];
-  TV *z = zb[0], *tmp = (TV *)F.y;
+  TV *tmp = (TV *)F.y;
   if (tmp == z) tmp = (TV *)F.z;
   const Geom g = geom(F.n);
   // an FP64 hierarchy reads A from its exact FP32 copy when there is one
@@ -1405,6 +1514,145 @@ void vcycle_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const do
       k_post<TV, double, double, false><<<g.grid, kBlock, 0, s>>>(
           F.n, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), r0, z, z0, nullptr, done);
   }
+}
+
+// Down step of the smoothed-aggregation cycle on level l: z from the
+// pre-smoothing sweeps and the residual t = r - A z (both left in the level's
+// buffers); returns the buffer holding z.
+template <typename TV, typename TR>
+TV *down_sa(amg_hierarchy *h, int32_t l, const TR *r, const int32_t *done) {
+  hipStream_t s = h->stream;
+  Level &F = h->lv[l];
+  TV *z = (TV *)F.z, *y = (TV *)F.y, *t = (TV *)F.t;
+  const Geom g = geom(F.n);
+  if (F.lr_rp) {  // long rows: several lanes per row
+    k_jacobi0<TV, TR><<<grid1(F.n), kBlock, 0, s>>>(F.n, minv<TV>(F), r, z, done);
+    for (int32_t k = 1; k < h->params.pre; ++k) {
+      smooth_rows<TV, TR, 0>(s, F.n, F.nnz, F.lr_rp, F.lr_ci, lr_vals<TV>(F), minv<TV>(F), r, z,
+                             y, done);
+      std::swap(z, y);
+    }
+    smooth_rows<TV, TR, 1>(s, F.n, F.nnz, F.lr_rp, F.lr_ci, lr_vals<TV>(F), minv<TV>(F), r, z, t,
+                           done);
+    return z;
+  }
+  if (h->params.pre == 1) {
+    k_pre_resid<TV, TR><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col, svals<TV>(F),
+                                                  minv<TV>(F), r, z, t, done);
+    return z;
+  }
+  const bool a32 = reads32<TV>(F, l);
+  k_jacobi0<TV, TR><<<grid1(F.n), kBlock, 0, s>>>(F.n, minv<TV>(F), r, z, done);
+  for (int32_t k = 1; k < h->params.pre; ++k) {
+    if (a32)
+      k_post<TV, TR, TV, false, float><<<g.grid, kBlock, 0, s>>>(
+          F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), r, z, y, nullptr, done);
+    else
+      k_post<TV, TR, TV, false><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
+                                                         vals<TV>(F), minv<TV>(F), r, z, y,
+                                                         nullptr, done);
+    std::swap(z, y);
+  }
+  if (a32)
+    k_resid<TV, TR, float><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, r,
+                                                     z, t, done);
+  else
+    k_resid<TV, TR><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), r, z,
+                                              t, done);
+  return z;
+}
+
+// The V-cycle with smoothed prolongators (L >= 1): per level the down step,
+// r_{l+1} = Pbar^T t; the coarsest solve; then per level z_l += Pbar z_{l+1}
+// and the post-smoothing sweeps.
+template <typename TV>
+void vcycle_sa_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const double *dv,
+                 const int32_t *done) {
+  hipStream_t s = h->stream;
+  const int32_t L = (int32_t)h->lv.size() - 1;
+  std::vector<TV *> zb(L);
+  for (int32_t l = 0; l < L; ++l) {
+    Level &F = h->lv[l];
+    Level &C = h->lv[l + 1];
+    zb[l] = l == 0 ? down_sa<TV, double>(h, 0, r0, done)
+                   : down_sa<TV, TV>(h, l, (const TV *)F.r, done);
+    csr_apply<TV, false>(s, C.n, F.pb_nnz, F.st_rp, F.st_ci, pbart_vals<TV>(F), (const TV *)F.t,
+                         (TV *)C.r, done);
+  }
+  Level &Cl = h->lv[L];
+  TV *zc = (TV *)Cl.z;
+  const int32_t nL = h->C.n;
+  if (coarse_is_pcg(h))
+    launch_coarse_pcg<TV, TV>(h, (const TV *)Cl.r, zc, 0, nullptr, nullptr, nullptr, done);
+  else
+    k_coarse_solve<TV, TV><<<ceil_div(nL, kCoarseWaves), kWave * kCoarseWaves, 0, s>>>(
+        nL, h->C.Ainv, (const TV *)Cl.r, zc, done);
+  for (int32_t l = L - 1; l >= 1; --l) {
+    Level &F = h->lv[l];
+    csr_apply<TV, true>(s, F.n, F.pb_nnz, F.sp_rp, F.sp_ci, pbar_vals<TV>(F), zc, zb[l], done);
+    TV *z = zb[l], *tmp = z == (TV *)F.z ? (TV *)F.y : (TV *)F.z;
+    const Geom g = geom(F.n);
+    for (int32_t k = 0; k < h->params.post; ++k) {
+      if (F.lr_rp)
+        smooth_rows<TV, TV, 0>(s, F.n, F.nnz, F.lr_rp, F.lr_ci, lr_vals<TV>(F), minv<TV>(F),
+                               (const TV *)F.r, z, tmp, done);
+      else
+        k_post<TV, TV, TV, false><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
+                                                           vals<TV>(F), minv<TV>(F),
+                                                           (const TV *)F.r, z, tmp, nullptr,
+                                                           done);
+      std::swap(z, tmp);
+    }
+    zc = z;
+  }
+  Level &F0 = h->lv[0];
+  csr_apply<TV, true>(s, F0.n, F0.pb_nnz, F0.sp_rp, F0.sp_ci, pbar_vals<TV>(F0), zc, zb[0],
+                      done);
+  level0_post<TV>(h, r0, zb[0], z0, dot, dv, done);
+}
+
+// V-cycle z0 = B r0 on the aggregate-major vectors of level 0. With dot, the
+// last kernel also writes the block partials of (r0, z0), finalized into the
+// CG scalars, or, with a dot partner dv, of (dv, z0), left to the caller.
+template <typename TV>
+void vcycle_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const double *dv,
+              const int32_t *done) {
+  hipStream_t s = h->stream;
+  const int32_t L = (int32_t)h->lv.size() - 1;
+  if (L == 0) {
+    one_level_cycle(h, r0, z0, dot, dv, done);
+    return;
+  }
+  if (h->params.smooth_p) {
+    vcycle_sa_t<TV>(h, r0, z0, dot, dv, done);
+    return;
+  }
+  std::vector<TV *> zb(L);
+  const bool tail = L >= 2 && h->params.pre == 1 && h->params.post == 1 &&
+                    h->lv[L - 1].n <= kTailMax && h->C.n <= kTailCoarseMax && !coarse_is_pcg(h);
+  const int32_t down_end = tail ? L - 1 : L;  // levels [0, down_end) take the down step
+  zb[0] = launch_down<TV, double>(h, 0, r0, done);
+  for (int32_t l = 1; l < down_end; ++l)
+    zb[l] = launch_down<TV, TV>(h, l, (const TV *)h->lv[l].r, done);
+  if (tail) {
+    Level &T = h->lv[L - 1];
+    Level &F = h->lv[L - 2];
+    k_tail<TV><<<1, 1024, 0, s>>>(T.n, T.S.sptr, T.S.col, svals<TV>(T), vals<TV>(T), minv<TV>(T),
+                                  (const TV *)T.r, T.seg, T.aggp, ppv<TV>(T), h->C.n, h->C.Ainv,
+                                  F.n, F.aggp, ppv<TV>(F), zb[L - 2], done);
+    for (int32_t c = L - 2; c >= 1; --c) launch_up<TV>(h, c, zb[c], zb[c - 1], done);
+  } else {
+    Level &F = h->lv[L - 1];
+    const int32_t nL = h->C.n;
+    if (coarse_is_pcg(h))
+      launch_coarse_pcg<TV, TV>(h, (const TV *)h->lv[L].r, nullptr, F.n, F.aggp, ppv<TV>(F),
+                                zb[L - 1], done);
+    else
+      k_coarse_prolong<TV><<<1, 1024, 2 * sizeof(double) * nL, s>>>(
+          nL, h->C.Ainv, (const TV *)h->lv[L].r, F.n, F.aggp, ppv<TV>(F), zb[L - 1], done);
+    for (int32_t c = L - 1; c >= 1; --c) launch_up<TV>(h, c, zb[c], zb[c - 1], done);
+  }
+  level0_post<TV>(h, r0, zb[0], z0, dot, dv, done);
 }
 
 // ---- K-cycle (Section 3.1) ----
@@ -1526,6 +1774,10 @@ amg_status alloc_level_vectors(amg_hierarchy *h, Level &L, size_t vbytes) {
 
 }  // namespace
 
+// average row length from which a level of a smoothed hierarchy is smoothed
+// with several lanes per row
+constexpr double kLongRow = 48.0;
+
 amg_status build_solve_formats(amg_hierarchy *h) {
   hipStream_t s = h->stream;
   const bool fp32 = h->params.precision == AMG_FP32;
@@ -1643,6 +1895,13 @@ amg_status build_solve_formats(amg_hierarchy *h) {
     }
   }
   if (h->params.cycle == AMG_CYCLE_K) AMG_TRY(dalloc(h, &h->kscal, (size_t)kKScal * nlev));
+  if (h->params.smooth_p)
+    for (int32_t l = 0; l + 1 < nlev; ++l) {
+      AMG_TRY(smooth_solve_format(h, l, fp32));
+      // the denser coarse levels: CSR for the kernels with several lanes per row
+      if (l > 0 && (double)h->lv[l].nnz > kLongRow * (double)h->lv[l].n)
+        AMG_TRY(long_row_csr(h, l, fp32));
+    }
   // outer CG vectors and scalars (aggregate-major order of level 0)
   const int32_t n0 = h->lv[0].n;
   AMG_TRY(dalloc(h, &h->x, (size_t)n0));
@@ -1917,6 +2176,28 @@ amg_status time_vcycle(amg_hierarchy *h, int32_t reps, double *ms, double *bytes
   const int32_t L = (int32_t)h->lv.size() - 1;
   const double V = h->params.precision == AMG_FP32 ? 4.0 : 8.0;
   const double nL = h->C.n;
+  if (h->params.smooth_p && L > 0) {
+    // smoothed prolongators, per level l < L: down step z(V+4) + 4(n+1) +
+    // n(Vr+3V); restriction by Pbar^T p(V+4) + 4(n_c+1) + V(n + n_c);
+    // prolongation by Pbar p(V+4) + 4(n+1) + V(n_c + 2n); post-smoothing of
+    // 0 < l < L z(V+4) + 4(n+1) + 4Vn; the coarsest (Cholesky) 8 n_L^2 +
+    // 2V n_L; the level-0 post-smoothing as above
+    double b = coarse_is_pcg(h) ? 0.0 : 8.0 * nL * nL + 2.0 * V * nL;
+    for (int32_t l = 0; l < L; ++l) {
+      const Level &F = h->lv[l];
+      const double n = F.n, z = (double)F.nnz, nc = h->lv[l + 1].n, p = (double)F.pb_nnz;
+      const double Vr = l == 0 ? 8.0 : V;
+      b += z * (V + 4) + 4 * (n + 1) + n * (Vr + 3 * V);
+      b += p * (V + 4) + 4 * (nc + 1) + V * (n + nc);
+      b += p * (V + 4) + 4 * (n + 1) + V * (nc + 2 * n);
+      if (l > 0) b += z * (V + 4) + 4 * (n + 1) + 4 * V * n;
+    }
+    const double n0 = h->lv[0].n, z0 = (double)h->lv[0].nnz;
+    const double Va = V == 8.0 && h->lv[0].S.exact32 ? 4.0 : V;
+    b += z0 * (Va + 4) + 4 * (n0 + 1) + n0 * (16 + 2 * V);
+    *bytes = b;
+    return AMG_OK;
+  }
   double b = coarse_is_pcg(h) ? 0.0 : 8.0 * nL * nL + (L == 0 ? 16.0 : V) * nL;
   for (int32_t l = 0; l < L; ++l) {
     const double n = h->lv[l].n, z = (double)h->lv[l].nnz, nc = h->lv[l + 1].n;
@@ -1941,6 +2222,8 @@ amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t 
   if (kernel == 5) return time_vcycle(h, reps, ms, bytes);
   if (level < 0 || level >= L || reps < 1 || kernel < 0 || kernel > 4) return AMG_ERR_ARG;
   if (kernel == 4 && level != 0) return AMG_ERR_ARG;
+  // the fused down and up kernels are those of the tentative prolongator
+  if (h->params.smooth_p && (kernel == 0 || kernel == 2 || kernel == 3)) return AMG_ERR_ARG;
   if ((kernel == 2 || kernel == 3) && level + 1 >= L) return AMG_ERR_ARG;
   hipStream_t s = h->stream;
   Level &F = h->lv[level];

@@ -52,7 +52,8 @@ def test_host_only_calls(lib):
     assert (p.sweeps, p.max_coarse, p.pre, p.post, p.precision) == (3, 200, 1, 1, 0)
     assert (p.cycle, p.w_sweeps, p.coarse_solver) == (amg.CYCLE_V, 0, amg.COARSE_CHOLESKY)
     assert (p.coarse_rtol, p.coarse_maxit) == (1e-4, 30)  # Section 5's coarsest CG stop
-    assert ctypes.sizeof(amg.Params) == 72  # the C struct, field for field
+    assert p.smooth_p == 0
+    assert ctypes.sizeof(amg.Params) == 80  # the C struct, field for field
     assert amg.amg_status_string(amg.Status.ERR_STALL).startswith("coarsening")
     est = amg.amg_estimate_footprint(4096000, 28518400, p)
     assert 1e9 < est < 8e9
