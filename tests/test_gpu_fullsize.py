@@ -129,3 +129,28 @@ def test_batch_128_k32_sampled_against_oracle(orc):
         # both solutions within the conditioning bound of the exact one
         assert np.linalg.norm(Xh[:, j] - xo) / np.linalg.norm(xo) < 1e-8 * 1.2e4
     h.close()
+
+
+def test_smoothed_hierarchy_and_paper_gpu_preconditioner_at_160(orc, headline):
+    """Smoothed aggregation at the benchmark size: the GPU hierarchy (levels,
+    every coarse matrix, every Pbar) bit-exact with the oracle's, and Section
+    5's GPU preconditioner (Pbar, 4 l1-Jacobi pre/post sweeps, CG coarsest)
+    reaching 1e-6 in 7 flexible-CG iterations, equal to the oracle's iterate."""
+    from paper_2006_16147_amd import amg
+
+    A, b = headline["A"], headline["b"]
+    h = setup(A, smooth_p=1, pre=4, post=4, coarse_solver=amg.COARSE_PCG)
+    ho = orc.Hierarchy(A, smooth=True, coarse=(1e-4, 30))
+    assert h.sizes() == ho.sizes() and h.nnzs() == ho.nnzs()
+    for l in range(1, ho.num_levels):
+        _, _, val = h.level_csr(l)
+        np.testing.assert_array_equal(val.view(np.uint64), ho.level_csr(l).val.view(np.uint64))
+    for l in range(ho.num_levels - 1):
+        (_, _, pv), om = h.prolongator(l)
+        assert om == ho.omega(l)
+        np.testing.assert_array_equal(pv.view(np.uint64), ho.pbar(l)[2].view(np.uint64))
+    st, info, x = solve(h, b, rtol=1e-6, maxit=100)
+    assert st == 0 and info["iterations"] == 7 and info["rel_res_true"] <= 1.001e-6
+    xo, _ = ho.fcg(b, rtol=0.0, maxit=7, pre=4, post=4, cycle="V")
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8
+    h.close()
