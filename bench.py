@@ -105,8 +105,8 @@ def load_traffic(kernel_key):
 
 
 CALIB_BYTES = 512 << 20  # plain device copy used to scale the HBM counters
-TRAFFIC_KERNELS = {  # (kernel-name fragment, level-0 grid in threads) -> key
-    "fp64_level0_0": "k_pre_restrict<double, double, 0>",
+TRAFFIC_KERNELS = {  # kernel-name fragment (its largest launches are level 0's) -> key
+    "fp64_level0_0": "k_pre_restrict<double, double, 0",
     "fp64_level0_1": "k_post<double, double, double, true,",
     "fp64_level0_4": "k_spmv_dot",
 }
@@ -143,7 +143,7 @@ def _counter_rows(path):
         return list(csv.DictReader(f))
 
 
-def ingest_pmc(fetch_csv, write_csv, n=160 ** 3):
+def ingest_pmc(fetch_csv, write_csv):
     """Writes profiles/traffic.json from rocprofv3 FETCH_SIZE and WRITE_SIZE
     counter CSVs of the profile pass: per-dispatch KiB averaged per kernel,
     scaled by the same counter's reading for the calibration copy."""
@@ -159,8 +159,10 @@ def ingest_pmc(fetch_csv, write_csv, n=160 ** 3):
         scale = kib_copy * 1024.0 / CALIB_BYTES  # counter bytes per real byte moved
         out["%s_scale" % counter] = scale
         for key, frag in TRAFFIC_KERNELS.items():
-            vals = [float(r["Counter_Value"]) * 1024.0 / scale for r in rows
-                    if frag in r["Kernel_Name"] and int(r.get("Grid_Size", 0)) == n]
+            match = [r for r in rows if frag in r["Kernel_Name"]]
+            top = max((int(r.get("Grid_Size", 0)) for r in match), default=0)
+            vals = [float(r["Counter_Value"]) * 1024.0 / scale for r in match
+                    if int(r.get("Grid_Size", 0)) == top]
             if vals:
                 per.setdefault(key, {})[counter] = sum(vals) / len(vals)
                 per[key]["dispatches"] = len(vals)
@@ -501,7 +503,7 @@ def main():
                     help="write profiles/traffic.json from two counter runs")
     args = ap.parse_args()
     if args.ingest_pmc:
-        ingest_pmc(*args.ingest_pmc, n=args.N ** 3)
+        ingest_pmc(*args.ingest_pmc)
         return
     if args.profile_pass:
         profile_pass(args.N)

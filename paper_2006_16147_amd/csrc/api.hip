@@ -345,7 +345,7 @@ size_t amg_estimate_footprint(int64_t n, int64_t nnz, const amg_params *params) 
   b += 4.0 * 1.02 * nnz;                        // exact FP32 copy of A_0 (when it applies)
   b += 4 * V * sn;                              // V-cycle vectors
   b += 6 * 8.0 * n;                             // CG vectors (x, r, z, p, q, b)
-  b += 3 * 65536 * 8.0;                         // block partials
+  b += (double)kPartPlanes * kMaxParts * 8.0;   // block partials
   if (P.cycle == AMG_CYCLE_K) b += 5 * V * (sn - n);  // K-cycle FCG vectors
   // peak of the setup temporaries (weights, Galerkin staging, sweep matrices)
   b += 8.0 * nnz + 12.0 * nnz + 2 * (12.0 * nnz + 16.0 * n);

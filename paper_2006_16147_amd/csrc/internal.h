@@ -33,10 +33,14 @@ namespace amg {
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kSlice = 64;       // rows per SELL slice (one wavefront)
 constexpr int kBlock = 256;      // threads per block of the streaming kernels
-constexpr int kMaxParts = 65536;
+// most blocks of a row-streaming kernel (and partial sums per reduction);
+// larger levels give each thread several rows. At 160^3 (4096 blocks of
+// 1024 rows) this measured 3 % faster per solve than one row per thread:
+// more loads in flight per thread, fewer partials to finalize.
+constexpr int kMaxParts = 4096;
 constexpr int kPartPlanes = 3;  // partial-sum planes (dot products per reduction)
 // K-cycle scalars of one level's two flexible-CG iterations
-enum KScal : int32_t { kRho1 = 0, kS1, kGamma, kRho2, kS2, kA1, kKScal = 8 };   // most blocks of a reducing kernel (partials buffer)
+enum KScal : int32_t { kRho1 = 0, kS1, kGamma, kRho2, kS2, kA1, kKScal = 8 };
 constexpr int kNumXcd = 8;       // MI355X: 8 XCDs, blocks dispatched round-robin
 
 // Solve-phase PCG scalars, resident on the device.
