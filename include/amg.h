@@ -136,7 +136,11 @@ typedef struct {
                             D = diag(A), P the tentative prolongator of the matching
                             sweeps (which still chooses the aggregates and restricts w);
                             the V-cycle restricts with Pbar^T and prolongates with Pbar.
-                            V-cycle only. 0 */
+                            V-cycle only. The setup's sort buffers come from a workspace
+                            per device that is kept, and reused, until the process ends
+                            (about twice the largest setup's temporaries: ~30 GB for
+                            4.1 M unknowns); smoothed setups on one device take turns.
+                            0 */
 } amg_params;
 
 typedef struct {

@@ -351,6 +351,12 @@ size_t amg_estimate_footprint(int64_t n, int64_t nnz, const amg_params *params) 
   b += 8.0 * nnz + 12.0 * nnz + 2 * (12.0 * nnz + 16.0 * n);
   const double nL = P.max_coarse;
   b += 3 * 8.0 * nL * nL;
+  if (P.smooth_p) {
+    // denser coarse levels (operator complexity up to ~2.2 on 7-point rows,
+    // CSR + SELL), Pbar three times (~4 entries per fine row), long-row CSR
+    b += 1.4 * nnz * (2 * 12.0 + 8 + 2 * X);
+    b += 3 * 4.0 * n * (12.0 + X) + 4 * 3 * sn;
+  }
   return (size_t)(b + (1 << 20));
 }
 

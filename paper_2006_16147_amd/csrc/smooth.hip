@@ -12,6 +12,9 @@
 // same bit for bit on every run (built with -ffp-contract=off).
 
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "internal.h"
 
@@ -35,23 +38,55 @@ int bits_for(int64_t n) {
   return b;
 }
 
-// temporaries of one call, released in stream order
+// Temporaries of the smoothed setup: carved from one workspace per device
+// that grows on demand (blocks of at least twice the previous size) and is
+// kept until the process ends; a Scratch holds the device's workspace lock
+// for its lifetime, so smoothed setups on one device take turns. A product
+// takes a dozen buffers of up to several GiB; allocating and freeing them per
+// call (through the stream-ordered pool or hipMalloc/hipFree) cost far more
+// than the kernels, up to seconds per call once such blocks had been freed.
+struct Workspace {
+  std::mutex m;
+  std::vector<std::pair<char *, size_t>> blocks;
+};
+
+Workspace &workspace(int device) {
+  static std::mutex guard;
+  static std::map<int, Workspace *> all;
+  std::lock_guard<std::mutex> g(guard);
+  Workspace *&w = all[device];
+  if (!w) w = new Workspace();  // process lifetime
+  return *w;
+}
+
 struct Scratch {
-  int device;
   hipStream_t s;
-  std::vector<void *> ptrs;
-  explicit Scratch(const amg_hierarchy *h) : device(h->device), s(h->stream) {}
+  Workspace &ws;
+  std::unique_lock<std::mutex> lock;
+  size_t block = 0, used = 0;  // current block and bytes taken from it
+  explicit Scratch(const amg_hierarchy *h)
+      : s(h->stream), ws(workspace(h->device)), lock(ws.m) {}
   Scratch(const Scratch &) = delete;
   Scratch &operator=(const Scratch &) = delete;
-  ~Scratch() {
-    for (void *p : ptrs) stream_free(device, s, p);
-  }
+  ~Scratch() { (void)hipStreamSynchronize(s); }  // the next user may be another stream
   template <typename T>
   amg_status get(T **p, size_t count) {
-    void *q = nullptr;
-    AMG_TRY(stream_alloc(device, s, &q, count * sizeof(T) + 16));
-    ptrs.push_back(q);
-    *p = reinterpret_cast<T *>(q);
+    const size_t bytes = (count * sizeof(T) + 16 + 255) & ~size_t(255);
+    while (block < ws.blocks.size() && used + bytes > ws.blocks[block].second) {
+      ++block;
+      used = 0;
+    }
+    if (block == ws.blocks.size()) {
+      size_t sz = size_t(256) << 20;
+      for (const auto &b : ws.blocks) sz = b.second * 2 > sz ? b.second * 2 : sz;
+      if (bytes > sz) sz = bytes;
+      void *q = nullptr;
+      AMG_HIP(hipMalloc(&q, sz));
+      ws.blocks.emplace_back(reinterpret_cast<char *>(q), sz);
+      used = 0;
+    }
+    *p = reinterpret_cast<T *>(ws.blocks[block].first + used);
+    used += bytes;
     return AMG_OK;
   }
 };
@@ -306,23 +341,58 @@ __global__ void k_entry_rows(int32_t nr, const int32_t *__restrict__ xp,
   for (int32_t k = xp[r]; k < xp[r + 1]; ++k) row[k] = r;
 }
 
-// the terms coef_k * B(src_k, e) of entry k at off[k] ..: in the order k
-// ascending, then e ascending (entries of one row are consecutive in k)
-__global__ void k_comb_terms(int64_t nk, const int32_t *__restrict__ row,
-                             const int32_t *__restrict__ src, const double *__restrict__ coef,
-                             const int32_t *__restrict__ brp, const int32_t *__restrict__ bci,
-                             const double *__restrict__ bval, const int32_t *__restrict__ off,
-                             int cb, uint64_t *__restrict__ key, double *__restrict__ term) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nk) return;
-  const int32_t j = src[k];
-  const double c = coef[k];
-  const uint64_t rk = (uint64_t)row[k] << cb;
-  int32_t o = off[k];
-  for (int32_t e = brp[j]; e < brp[j + 1]; ++e) {
-    key[o] = rk | (uint64_t)bci[e];
-    term[o] = c * bval[e];
-    ++o;
+// The terms coef_k * B(src_k, e): entry k's terms occupy [off[k], off[k+1])
+// in the order k ascending, then e ascending (entries of one row are
+// consecutive in k). Each block writes one tile of consecutive terms
+// (coalesced); a term finds its entry by binary search among the offsets of
+// the tile's entries, staged in LDS (every entry brings at least one term,
+// so a tile spans at most kCombTile + 1 entries).
+constexpr int kCombPer = 8;
+constexpr int kCombTile = kBlock * kCombPer;
+__global__ void __launch_bounds__(kBlock) k_comb_terms(
+    int32_t count, int32_t nk, const int32_t *__restrict__ row, const int32_t *__restrict__ src,
+    const double *__restrict__ coef, const int32_t *__restrict__ brp,
+    const int32_t *__restrict__ bci, const double *__restrict__ bval,
+    const int32_t *__restrict__ off, int cb, uint64_t *__restrict__ key,
+    double *__restrict__ term) {
+  __shared__ int32_t so[kCombTile + 2];
+  __shared__ int32_t kfirst, kcount;
+  const int32_t T0 = blockIdx.x * kCombTile;
+  const int32_t T1 = min(count, T0 + kCombTile);
+  if (threadIdx.x == 0) {
+    // last entry with off <= T0, and last entry with off <= T1 - 1
+    int32_t lo = 0, hi = nk - 1;
+    while (lo < hi) {
+      const int32_t mid = lo + (hi - lo + 1) / 2;
+      if (off[mid] <= T0) lo = mid;
+      else hi = mid - 1;
+    }
+    int32_t lo2 = lo, hi2 = nk - 1;
+    while (lo2 < hi2) {
+      const int32_t mid = lo2 + (hi2 - lo2 + 1) / 2;
+      if (off[mid] <= T1 - 1) lo2 = mid;
+      else hi2 = mid - 1;
+    }
+    kfirst = lo;
+    kcount = lo2 - lo + 1;
+  }
+  __syncthreads();
+  const int32_t k0 = kfirst, nkt = kcount;
+  for (int32_t q = threadIdx.x; q <= nkt; q += kBlock) so[q] = off[k0 + q];
+  __syncthreads();
+  for (int u = 0; u < kCombPer; ++u) {
+    const int32_t t = T0 + u * kBlock + (int32_t)threadIdx.x;
+    if (t >= T1) break;
+    int32_t lo = 0, hi = nkt - 1;  // last local entry with so <= t
+    while (lo < hi) {
+      const int32_t mid = lo + (hi - lo + 1) / 2;
+      if (so[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const int32_t k = k0 + lo;
+    const int32_t e = brp[src[k]] + (t - so[lo]);
+    key[t] = ((uint64_t)row[k] << cb) | (uint64_t)bci[e];
+    term[t] = coef[k] * bval[e];
   }
 }
 
@@ -420,8 +490,9 @@ amg_status row_combination(Scratch &S, int32_t nr, const int32_t *xp, const int3
   AMG_TRY(S.get(&key, (size_t)count + 1));
   AMG_TRY(S.get(&term, (size_t)count + 1));
   const int cb = bits_for(ncols);
-  k_comb_terms<<<grid(nk), kBlock, 0, s>>>(nk, row, src, coef, brp, bci, bval, off, cb, key,
-                                           term);
+  if (count > 0)
+    k_comb_terms<<<ceil_div(count, kCombTile), kBlock, 0, s>>>(count, nk, row, src, coef, brp,
+                                                               bci, bval, off, cb, key, term);
   AMG_TRY(radix_sort(S, count, cb + bits_for(nr), &key, &term));
   return reduce_sorted(S, count, key, term, nr, cb, alloc, out);
 }
