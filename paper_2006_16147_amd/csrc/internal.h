@@ -33,11 +33,17 @@ namespace amg {
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kSlice = 64;       // rows per SELL slice (one wavefront)
 constexpr int kBlock = 256;      // threads per block of the streaming kernels
-// most blocks of a row-streaming kernel (and partial sums per reduction);
-// larger levels give each thread several rows. At 160^3 (4096 blocks of
-// 1024 rows) this measured 3 % faster per solve than one row per thread:
-// more loads in flight per thread, fewer partials to finalize.
-constexpr int kMaxParts = 4096;
+// most blocks of a reducing kernel (the partials buffer)
+constexpr int kMaxParts = 65536;
+// Row-streaming kernels on levels of fewer than kManyRows rows give each
+// thread 1 to 4 rows, aiming at about kTargetBlocks blocks: at 160^3 (4000
+// blocks of 1024 rows) a solve measured 3 % faster than with one row per
+// thread (more loads in flight, fewer partials to finalize); 16 rows per
+// thread was 16 % slower. Larger levels keep one row per thread: on the
+// anisotropic 256^3 problem (16.7 M rows) 4 rows were 5 % slower.
+constexpr int kTargetBlocks = 4096;
+constexpr int kMaxRowsPerThread = 4;
+constexpr int64_t kManyRows = int64_t(1) << 23;
 constexpr int kPartPlanes = 3;  // partial-sum planes (dot products per reduction)
 // K-cycle scalars of one level's two flexible-CG iterations
 enum KScal : int32_t { kRho1 = 0, kS1, kGamma, kRho2, kS2, kA1, kKScal = 8 };

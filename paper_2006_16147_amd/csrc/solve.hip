@@ -43,8 +43,9 @@ double now_ms() {
 inline int32_t grid1(int64_t n) { return ceil_div(n > 0 ? n : 1, kBlock); }
 
 // ---------------------------------------------------------------------------
-// launch geometry of the row-streaming kernels: one row per thread, each
-// block a contiguous chunk (more rows per thread only beyond kMaxParts blocks)
+// launch geometry of the row-streaming kernels: each block a contiguous
+// chunk of 1 to kMaxRowsPerThread rows per thread, about kTargetBlocks
+// blocks (more rows per thread only beyond kMaxParts blocks)
 // ---------------------------------------------------------------------------
 
 struct Geom {
@@ -53,13 +54,16 @@ struct Geom {
 };
 
 Geom geom(int64_t n) {
-  int64_t blocks = (n + kBlock - 1) / kBlock;
+  int64_t rows = (n + (int64_t)kBlock * kTargetBlocks - 1) / ((int64_t)kBlock * kTargetBlocks);
+  rows = rows < 1 || n >= kManyRows ? 1 : (rows > kMaxRowsPerThread ? kMaxRowsPerThread : rows);
+  int64_t chunk = kBlock * rows;
+  int64_t blocks = (n + chunk - 1) / chunk;
   if (blocks < 1) blocks = 1;
   if (blocks > kMaxParts) {
-    int64_t chunk = ((n + kMaxParts - 1) / kMaxParts + kBlock - 1) / kBlock * kBlock;
-    return {ceil_div(n, chunk), (int32_t)chunk};
+    chunk = ((n + kMaxParts - 1) / kMaxParts + kBlock - 1) / kBlock * kBlock;
+    blocks = (n + chunk - 1) / chunk;
   }
-  return {(int32_t)blocks, kBlock};
+  return {(int32_t)blocks, (int32_t)chunk};
 }
 
 __device__ __forceinline__ void rows_of_block(int32_t n, int32_t chunk, int32_t *b, int32_t *e) {
@@ -1385,12 +1389,13 @@ int32_t coarse_per_block(const amg_hierarchy *h) {
 }
 
 // Down step of level F into C with R fine rows per thread: 2 on levels of
-// at least 2^21 rows (160^3 level 0: 79.4 -> 78.1 us; 4 rows: 83 us).
+// 2^21 to kManyRows rows (160^3 level 0: 79.4 -> 78.1 us; 4 rows: 83 us;
+// on 16.7 M rows 2 rows were slower).
 template <typename TV, typename TR, int MODE, typename TA>
 void pre_restrict(const amg_hierarchy *h, const Level &F, const Level &C, const TA *val,
                   const TV *mv, const TV *pp, const TR *r, TV *z, TV *rc, const int32_t *done) {
   hipStream_t s = h->stream;
-  const int R = F.n >= (1 << 21) ? 2 : 1;
+  const int R = F.n >= (1 << 21) && F.n < kManyRows ? 2 : 1;
   const int32_t G = coarse_per_block(h) * R;
   const int32_t grid = ceil_div(C.n, G);
   if (R == 4)
