@@ -61,7 +61,7 @@ MUTATIONS = [
      "double t = p[i] * v[i];", "double t = v[i];",
      INV + "test_numbering_and_prolongator"),
     ("l1-Jacobi: absolute value dropped",
-     "s = s + fabs(A->val[k]);", "s = s + A->val[k];",
+     "} else {\n        s = s + fabs(A->val[k]);", "} else {\n        s = s + A->val[k];",
      PIN + "test_table1_l1_jacobi"),
     ("l1-Jacobi: plain diagonal",
      "m[i] = aii + s;", "m[i] = aii;",
