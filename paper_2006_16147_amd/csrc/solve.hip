@@ -484,8 +484,28 @@ __device__ __forceinline__ TV csr_row_dot(int32_t i, int32_t nr, const int32_t *
   const int lane = threadIdx.x % LPR;
   TV acc = 0;
   if (i < nr) {
+    // a lane's entries in batches of kRowBatch: all index and value loads,
+    // then all gathers, then the products in order
     const int32_t e1 = rp[i + 1];
-    for (int32_t e = rp[i] + lane; e < e1; e += LPR) acc += (TV)val[e] * x(ci[e]);
+    for (int32_t e0 = rp[i] + lane; e0 < e1; e0 += LPR * kRowBatch) {
+      int32_t c[kRowBatch];
+      TV v[kRowBatch], g[kRowBatch];
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        const int32_t e = e0 + u * LPR;
+        c[u] = 0;
+        v[u] = 0;
+        if (e < e1) {
+          c[u] = ci[e];
+          v[u] = (TV)val[e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) g[u] = e0 + u * LPR < e1 ? x(c[u]) : TV(0);
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u)
+        if (e0 + u * LPR < e1) acc += v[u] * g[u];
+    }
   }
   for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPR);
   return acc;
