@@ -546,7 +546,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_rows(
 // levels' products up to 30 % slower; the small levels' twice as fast.
 inline int lanes_for(int64_t nr, int64_t nnz) {
   const double avg = nr > 0 ? (double)nnz / nr : 1.0;
-  int l = avg >= 96 ? 32 : avg >= 40 ? 16 : avg >= 12 ? 8 : avg >= 6 ? 4 : avg >= 3 ? 2 : 1;
+  int l = avg >= 96 ? 32 : avg >= 40 ? 16 : avg >= 12 ? 8 : avg >= 6 ? 4 : 1;
   while (l < 64 && (double)nr * l < (double)(1 << 19) && l < avg) l *= 2;
   return l;
 }
