@@ -540,10 +540,12 @@ __global__ void __launch_bounds__(kBlock) k_smooth_rows(
   }
 }
 
-// lanes per row for nr rows of nnz entries: two to three entries per lane,
-// and more lanes (up to a wavefront) while fewer than 2^19 threads would be
-// in flight. At 160^3 (smoothed hierarchy) one lane per entry made the big
-// levels' products up to 30 % slower; the small levels' twice as fast.
+// lanes per row for nr rows of nnz entries: two to three entries per lane
+// (rows shorter than 6 entries: one lane, a single batch of loads), and more
+// lanes (up to a wavefront) while fewer than 2^19 threads would be in
+// flight. At 160^3 (smoothed hierarchy) one lane per entry made the big
+// levels' products up to 30 % slower, about 8 entries per lane 7 % slower
+// per iteration; whole wavefronts made the small levels' twice as fast.
 inline int lanes_for(int64_t nr, int64_t nnz) {
   const double avg = nr > 0 ? (double)nnz / nr : 1.0;
   int l = avg >= 96 ? 32 : avg >= 40 ? 16 : avg >= 12 ? 8 : avg >= 6 ? 4 : 1;
