@@ -925,18 +925,18 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dots(
   block_partial<NV>(d, partials);
 }
 
-// One block: the level's flexible-CG scalars from the block partials.
-// op 1 (after c1): rho1 = (c1, v1), s1 = (c1, b) / rho1 (0 if rho1 <= 0).
-// op 2 (after c2): gamma = (c2, v1), rho2 = (c2, v2) - gamma^2 / rho1,
-// s2 = (c2, r1) / rho2, a1 = s1 - s2 (gamma / rho1); x = a1 c1 + s2 c2.
-// rho1 <= 0 gives x = 0, rho2 <= 0 gives x = s1 c1.
-__global__ void __launch_bounds__(1024) k_kfin(int32_t op, int32_t nparts,
+// One block: the level's second flexible-CG step scalars from the block
+// partials (rho1 and s1 = (c1, b) / rho1 come from k_kresid): gamma =
+// (c2, v1), rho2 = (c2, v2) - gamma^2 / rho1, s2 = (c2, r1) / rho2,
+// a1 = s1 - s2 (gamma / rho1); x = a1 c1 + s2 c2. rho1 <= 0 gives x = 0,
+// rho2 <= 0 gives x = s1 c1.
+__global__ void __launch_bounds__(1024) k_kfin(int32_t nparts,
                                                const double *__restrict__ partials,
                                                double *__restrict__ ks,
                                                const int32_t *__restrict__ done) {
   const int32_t stop = *done;
   __shared__ double sh[3][1024 / kWave];
-  const int nv = op == 1 ? 2 : 3;
+  constexpr int nv = 3;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   for (int q = 0; q < nv; ++q) {
     const double *src = partials + (int64_t)q * kMaxParts;
@@ -962,12 +962,6 @@ __global__ void __launch_bounds__(1024) k_kfin(int32_t op, int32_t nparts,
     double t = sh[q][0];
     for (int k = 1; k < (int)(blockDim.x / kWave); ++k) t += sh[q][k];
     tot[q] = t;
-  }
-  if (op == 1) {
-    const double rho1 = tot[0];
-    ks[kRho1] = rho1;
-    ks[kS1] = rho1 > 0.0 ? tot[1] / rho1 : 0.0;
-    return;
   }
   const double rho1 = ks[kRho1], s1 = ks[kS1];
   const double beta = tot[0], gamma = tot[1], a2 = tot[2];
@@ -1327,15 +1321,48 @@ inline int32_t coarse_pcg_threads(int32_t nL) {
   return t < kWave ? kWave : (t > 1024 ? 1024 : t);
 }
 
-// r1 = b - s1 v1
+// r1 = b - s1 v1, with s1 = (c1, b) / (c1, v1) from the first step's partials
 template <typename TV>
-__global__ void k_kresid(int32_t n, const TV *__restrict__ b, const TV *__restrict__ v1,
-                         const double *__restrict__ ks, TV *__restrict__ r1,
-                         const int32_t *__restrict__ done) {
+__global__ void __launch_bounds__(kBlock) k_kresid(
+    int32_t n, const TV *__restrict__ b, const TV *__restrict__ v1,
+    const double *__restrict__ partials, int32_t nparts, double *__restrict__ ks,
+    TV *__restrict__ r1, const int32_t *__restrict__ done) {
   if (*done) return;
-  const TV s1 = (TV)ks[kS1];
+  // rho1 = (c1, v1) and (c1, b) from the block partials, summed by every
+  // block in the same order (so all blocks hold the same s1); block 0 keeps
+  // them for the second step and the prolongation
+  __shared__ double sh[2][kBlock / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  for (int q = 0; q < 2; ++q) {
+    const double *src = partials + (int64_t)q * kMaxParts;
+    double a = 0.0;
+    for (int32_t b0 = threadIdx.x; b0 < nparts; b0 += 16 * kBlock) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int32_t bb = b0 + u * kBlock;
+        v[u] = bb < nparts ? src[bb] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (b0 + u * kBlock < nparts) a += v[u];
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) a += __shfl_down(a, o, kWave);
+    if (lane == 0) sh[q][wid] = a;
+  }
+  __syncthreads();
+  double rho1 = sh[0][0], cb = sh[1][0];
+  for (int k = 1; k < kBlock / kWave; ++k) {
+    rho1 += sh[0][k];
+    cb += sh[1][k];
+  }
+  const double s1 = rho1 > 0.0 ? cb / rho1 : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ks[kRho1] = rho1;
+    ks[kS1] = s1;
+  }
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) r1[i] = b[i] - s1 * v1[i];
+  if (i < n) r1[i] = b[i] - (TV)s1 * v1[i];
 }
 
 // z_f += P x with x = a1 c1 + s2 c2 formed per coarse position
@@ -1793,14 +1820,14 @@ void fcg2_t(amg_hierarchy *h, int32_t m, const int32_t *done) {
   k_spmv_dots<TV, 2><<<g.grid, kBlock, 0, s>>>(n, g.chunk, M.S.sptr, M.S.col, vals<TV>(M),
                                                (const TV *)M.c1, (TV *)M.v1, b, nullptr,
                                                h->partials, done);
-  k_kfin<<<1, 1024, 0, s>>>(1, g.grid, h->partials, ks, done);
-  k_kresid<TV><<<grid1(n), kBlock, 0, s>>>(n, b, (const TV *)M.v1, ks, (TV *)M.r1, done);
+  k_kresid<TV><<<grid1(n), kBlock, 0, s>>>(n, b, (const TV *)M.v1, h->partials, g.grid, ks,
+                                           (TV *)M.r1, done);
   kcycle_t<TV, TV, TV>(h, m, (const TV *)M.r1, (TV *)M.c2, nullptr, done);
   k_spmv_dots<TV, 3><<<g.grid, kBlock, 0, s>>>(n, g.chunk, M.S.sptr, M.S.col, vals<TV>(M),
                                                (const TV *)M.c2, (TV *)M.v2,
                                                (const TV *)M.v1, (const TV *)M.r1,
                                                h->partials, done);
-  k_kfin<<<1, 1024, 0, s>>>(2, g.grid, h->partials, ks, done);
+  k_kfin<<<1, 1024, 0, s>>>(g.grid, h->partials, ks, done);
 }
 
 // z0 = K r0 on the aggregate-major level-0 vectors (with dv: the partials of
