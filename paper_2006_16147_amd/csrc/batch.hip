@@ -13,6 +13,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -310,9 +311,11 @@ __global__ void __launch_bounds__(kBlock) kb_spmv(
     int32_t n, int32_t k, const int32_t *__restrict__ sptr,
     const int32_t *__restrict__ col, const double *__restrict__ val,
     const double *__restrict__ Xin, const double *__restrict__ B, double *__restrict__ Out,
-    double *__restrict__ partials, int32_t mode, const int32_t *__restrict__ stop) {
+    float *__restrict__ OutF, double *__restrict__ partials, int32_t mode,
+    const int32_t *__restrict__ stop) {
   // mode 0: Out = A Xin, partials (Xin, Out)         (q = A p, (p, q))
-  // mode 1: Out = B - A Xin, partials (B, B), (Out, Out)   (initial residual)
+  // mode 1: Out = B - A Xin, partials (B, B), (Out, Out)   (initial residual);
+  //         OutF (if not null) = float(Out)
   // mode 2: partials (B - A Xin)^2 only               (true residual)
   if (stop && *stop) return;
   const int32_t j0 = blockIdx.y * (KT * kCpt) + threadIdx.x % KT;
@@ -347,6 +350,7 @@ __global__ void __launch_bounds__(kBlock) kb_spmv(
           const double bi = B[o], ri = bi - acc[q];
           if (mode == 1) {
             Out[o] = ri;
+            if (OutF) OutF[o] = (float)ri;
             d0[q] += bi * bi;
             d1[q] += ri * ri;
           } else {
@@ -392,6 +396,7 @@ template <int KT>
 __global__ void __launch_bounds__(kBlock) kb_update(int32_t n, int32_t k,
                                                     double *__restrict__ X,
                                                     double *__restrict__ R,
+                                                    float *__restrict__ Rf,
                                                     const double *__restrict__ P,
                                                     const double *__restrict__ Q,
                                                     const double *__restrict__ colv,
@@ -412,6 +417,7 @@ __global__ void __launch_bounds__(kBlock) kb_update(int32_t n, int32_t k,
       X[o] += alpha * P[o];
       const double ri = R[o] - alpha * Q[o];
       R[o] = ri;
+      if (Rf) Rf[o] = (float)ri;
       d += ri * ri;
     }
   }
@@ -611,12 +617,21 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
   // further sweeps alternating z and y, then the residual of the last one;
   // restriction of the residual t. zc[l] is the buffer holding z_l.
   const int32_t pre = h->params.pre, post = h->params.post;
+  // The FP32 hierarchy's level-0 kernels use the residual only rounded to
+  // FP32 (except the final sweep's CG dot product): they read B.Rf, which
+  // holds float(B.R), and gather 4-byte entries instead of 8-byte ones.
+  const TV *R0v = std::is_same<TV, float>::value && R0 == B.R && B.Rf
+                      ? reinterpret_cast<const TV *>(B.Rf)
+                      : nullptr;
   std::vector<TV *> zc(L), yout(L + 1);
   for (int32_t l = 0; l < L; ++l) {
     Level &F = h->lv[l];
     const BGeom g = bgeom(F.n, k, KT);
     TV *z = (TV *)B.z[l], *y = (TV *)B.y[l], *t = (TV *)B.t[l];
-    if (l == 0)
+    if (l == 0 && R0v)
+      kb_pre_residual<TV, TV, KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+          F.n, k, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), R0v, z, t, stop);
+    else if (l == 0)
       kb_pre_residual<TV, double, KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(
           F.n, k, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), R0, z, t, stop);
     else
@@ -624,7 +639,10 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
           F.n, k, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), (const TV *)B.r[l], z,
           t, stop);
     for (int32_t sw = 1; sw < pre; ++sw) {
-      if (l == 0)
+      if (l == 0 && R0v)
+        kb_post<TV, TV, TV, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+            F.n, k, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0v, z, y, nullptr, stop);
+      else if (l == 0)
         kb_post<TV, double, TV, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
             F.n, k, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, y, nullptr,
             stop);
@@ -635,7 +653,10 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
       std::swap(z, y);
     }
     if (pre > 1) {
-      if (l == 0)
+      if (l == 0 && R0v)
+        kb_resid<TV, TV, KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+            F.n, k, F.S.sptr, F.S.col, vals<TV>(F), R0v, z, t, stop);
+      else if (l == 0)
         kb_resid<TV, double, KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(
             F.n, k, F.S.sptr, F.S.col, vals<TV>(F), R0, z, t, stop);
       else
@@ -677,9 +698,14 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
         if (last) yout[l] = out;
       } else if (!last) {
         TV *out = other(z);
-        kb_post<TV, double, TV, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
-            F.n, k, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, out, nullptr,
-            stop);
+        if (R0v)
+          kb_post<TV, TV, TV, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+              F.n, k, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0v, z, out, nullptr,
+              stop);
+        else
+          kb_post<TV, double, TV, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+              F.n, k, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, out, nullptr,
+              stop);
         z = out;
       } else if (rz_op >= 0) {
         kb_post<TV, double, double, KT, true><<<tgrid(g, k, KT), kBlock, 0, s>>>(
@@ -695,6 +721,33 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
   }
 }
 
+// The CG update streams whole rows, so its column tile is chosen from k
+// alone (the smallest tile covering k, at most 64): one block then writes all
+// of a row's k-wide slice of R, X and the FP32 residual copy, whose rows
+// (4k bytes) a narrower tile would leave as partial cache lines written by
+// two blocks.
+int32_t update_tile(int32_t k) { return k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; }
+
+template <int KU>
+int32_t launch_update(amg_hierarchy *h, const int32_t *stop) {
+  Batch &B = *h->batch;
+  const int32_t n = h->lv[0].n, k = B.k;
+  const BGeom g = bgeom(n, k, KU);
+  kb_update<KU><<<g.grid, kBlock, 0, h->stream>>>(n, k, B.X, B.R, B.Rf, B.P, B.Q, B.col,
+                                                  B.done, B.partials, stop);
+  return (int32_t)g.grid.x;
+}
+
+int32_t cg_update(amg_hierarchy *h, const int32_t *stop) {
+  switch (update_tile(h->batch->k)) {
+    case 4: return launch_update<4>(h, stop);
+    case 8: return launch_update<8>(h, stop);
+    case 16: return launch_update<16>(h, stop);
+    case 32: return launch_update<32>(h, stop);
+    default: return launch_update<64>(h, stop);
+  }
+}
+
 template <typename TV, int KT>
 void iteration_b(amg_hierarchy *h, int32_t maxit) {
   hipStream_t s = h->stream;
@@ -705,11 +758,9 @@ void iteration_b(amg_hierarchy *h, int32_t maxit) {
   const int32_t *stop = B.all_done;
   const BGeom g = bgeom(n, k, KT);
   kb_spmv<KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(n, k, L0.S.sptr, L0.S.col, L0.S.v64, B.P,
-                                        nullptr, B.Q, B.partials, 0, stop);
+                                        nullptr, B.Q, nullptr, B.partials, 0, stop);
   bfinalize(h, bPq, (int32_t)g.grid.x, maxit, stop);
-  kb_update<KT><<<g.grid, kBlock, 0, s>>>(n, k, B.X, B.R, B.P, B.Q, B.col, B.done,
-                                          B.partials, stop);
-  bfinalize(h, bRr, (int32_t)g.grid.x, maxit, stop);
+  bfinalize(h, bRr, cg_update(h, stop), maxit, stop);
   kb_all_done<<<1, 64, 0, s>>>(k, B.done, B.all_done);
   vcycle_b<TV, KT>(h, B.R, B.Z, bRz, maxit, stop);
   kb_xpay<KT><<<egrid(n, k, KT), kBlock, 0, s>>>(n, k, B.Z, B.P, B.col, B.done, 0, stop);
@@ -745,8 +796,9 @@ void launch_spmv_mode(amg_hierarchy *h, const double *Xin, const double *Bv, dou
   Level &L0 = h->lv[0];
   const BGeom g = bgeom(L0.n, B.k, KT);
   kb_spmv<KT><<<tgrid(g, B.k, KT), kBlock, 0, h->stream>>>(L0.n, B.k, L0.S.sptr, L0.S.col,
-                                                L0.S.v64, Xin, Bv, Out, B.partials, mode,
-                                                nullptr);
+                                                L0.S.v64, Xin, Bv, Out,
+                                                mode == 1 && Out == B.R ? B.Rf : nullptr,
+                                                B.partials, mode, nullptr);
   *nparts = (int32_t)g.grid.x;
 }
 
@@ -821,6 +873,7 @@ amg_status ensure_batch(amg_hierarchy *h, int32_t k) {
   AMG_TRY(balloc(h, (void **)&B.Z, e0));
   AMG_TRY(balloc(h, (void **)&B.P, e0));
   AMG_TRY(balloc(h, (void **)&B.Q, e0));
+  if (fp32) AMG_TRY(balloc(h, (void **)&B.Rf, (size_t)h->lv[0].n * k * sizeof(float)));
   AMG_TRY(balloc(h, (void **)&B.partials, sizeof(double) * 2 * kBatchBlocks * (size_t)k));
   AMG_TRY(balloc(h, (void **)&B.col, sizeof(double) * kColFields * (size_t)k));
   AMG_TRY(balloc(h, (void **)&B.iter, sizeof(int32_t) * (size_t)k));

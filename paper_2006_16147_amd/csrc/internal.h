@@ -153,6 +153,9 @@ struct Batch {
   std::vector<void *> r, z, t, y;  // per level, hierarchy precision
   // level-0 CG blocks, rows in the aggregate-major order of level 0
   double *X = nullptr, *Bp = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr;
+  // FP32 hierarchy only: float(R), kept by whichever kernel writes R, so the
+  // level-0 kernels that only use R rounded to FP32 gather 4-byte entries
+  float *Rf = nullptr;
   double *partials = nullptr;  // 2 x kBatchBlocks x k
   double *col = nullptr;       // per-column scalars, 8 x k (see batch.hip)
   int32_t *iter = nullptr, *done = nullptr, *all_done = nullptr;
