@@ -665,8 +665,11 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
     }
     zc[l] = z;
     const Level &C = h->lv[l + 1];
-    kb_restrict<TV, KT><<<egrid(C.n, k, KT), kBlock, 0, s>>>(C.n, k, F.seg, ppv<TV>(F), t,
-                                                            (TV *)B.r[l + 1], stop);
+    with_row_tile(k, [&](auto kt) {
+      constexpr int KE = decltype(kt)::value;
+      kb_restrict<TV, KE><<<egrid(C.n, k, KE), kBlock, 0, s>>>(C.n, k, F.seg, ppv<TV>(F), t,
+                                                              (TV *)B.r[l + 1], stop);
+    });
   }
   const int32_t nL = h->C.n;
   yout[L] = (TV *)B.y[L];
@@ -677,8 +680,11 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
   // yout[l] records where the last one (l > 0) left y_l.
   for (int32_t l = L - 1; l >= 0; --l) {
     Level &F = h->lv[l];
-    kb_prolong<TV, KT><<<egrid(F.n, k, KT), kBlock, 0, s>>>(F.n, k, F.aggp, ppv<TV>(F),
-                                                           yout[l + 1], zc[l], stop);
+    with_row_tile(k, [&](auto kt) {
+      constexpr int KE = decltype(kt)::value;
+      kb_prolong<TV, KE><<<egrid(F.n, k, KE), kBlock, 0, s>>>(F.n, k, F.aggp, ppv<TV>(F),
+                                                             yout[l + 1], zc[l], stop);
+    });
     const BGeom g = bgeom(F.n, k, KT);
     TV *bufs[3] = {(TV *)B.y[l], (TV *)B.z[l], (TV *)B.t[l]};
     TV *z = zc[l];
@@ -721,12 +727,24 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
   }
 }
 
-// The CG update streams whole rows, so its column tile is chosen from k
-// alone (the smallest tile covering k, at most 64): one block then writes all
-// of a row's k-wide slice of R, X and the FP32 residual copy, whose rows
-// (4k bytes) a narrower tile would leave as partial cache lines written by
-// two blocks.
-int32_t update_tile(int32_t k) { return k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; }
+// The kernels that take one thread per element (the CG update, p = z + b p,
+// restriction, prolongation) choose their column tile from k alone: the
+// smallest tile covering k, at most 64. One block then reads and writes whole
+// rows; with a narrower tile an FP32 row (4k bytes) is split into partial
+// cache lines that two blocks fetch and write separately, and the restriction
+// and prolongation fetched twice their bytes that way.
+int32_t row_tile(int32_t k) { return k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; }
+
+template <typename F>
+void with_row_tile(int32_t k, F &&f) {
+  switch (row_tile(k)) {
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    case 32: f(std::integral_constant<int, 32>{}); break;
+    default: f(std::integral_constant<int, 64>{}); break;
+  }
+}
 
 template <int KU>
 int32_t launch_update(amg_hierarchy *h, const int32_t *stop) {
@@ -739,13 +757,9 @@ int32_t launch_update(amg_hierarchy *h, const int32_t *stop) {
 }
 
 int32_t cg_update(amg_hierarchy *h, const int32_t *stop) {
-  switch (update_tile(h->batch->k)) {
-    case 4: return launch_update<4>(h, stop);
-    case 8: return launch_update<8>(h, stop);
-    case 16: return launch_update<16>(h, stop);
-    case 32: return launch_update<32>(h, stop);
-    default: return launch_update<64>(h, stop);
-  }
+  int32_t nparts = 0;
+  with_row_tile(h->batch->k, [&](auto kt) { nparts = launch_update<decltype(kt)::value>(h, stop); });
+  return nparts;
 }
 
 template <typename TV, int KT>
@@ -763,7 +777,10 @@ void iteration_b(amg_hierarchy *h, int32_t maxit) {
   bfinalize(h, bRr, cg_update(h, stop), maxit, stop);
   kb_all_done<<<1, 64, 0, s>>>(k, B.done, B.all_done);
   vcycle_b<TV, KT>(h, B.R, B.Z, bRz, maxit, stop);
-  kb_xpay<KT><<<egrid(n, k, KT), kBlock, 0, s>>>(n, k, B.Z, B.P, B.col, B.done, 0, stop);
+  with_row_tile(k, [&](auto kt) {
+    constexpr int KE = decltype(kt)::value;
+    kb_xpay<KE><<<egrid(n, k, KE), kBlock, 0, s>>>(n, k, B.Z, B.P, B.col, B.done, 0, stop);
+  });
 }
 
 template <typename TV>
