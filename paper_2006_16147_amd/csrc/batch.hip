@@ -13,6 +13,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <type_traits>
 
 #include "internal.h"
@@ -222,6 +223,45 @@ __global__ void __launch_bounds__(kBlock) kb_resid(
   }
 }
 
+// VW consecutive values of a block row as one 16-byte vector: the
+// prolongation, the CG update and p = z + b p have a form with VW columns per
+// thread for k a multiple of VW and 16-byte aligned blocks (kv = k / VW
+// vectors per row), with a quarter (FP32) or half (FP64) of the threads and
+// memory instructions.
+template <typename TV>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using T = float4;
+  static constexpr int width = 4;
+};
+template <>
+struct Vec16<double> {
+  using T = double2;
+  static constexpr int width = 2;
+};
+
+// The kernels that take one thread per element (the CG update, p = z + b p,
+// restriction, prolongation) choose their column tile from k alone: the
+// smallest tile covering k, at most 64. One block then reads and writes whole
+// rows; with a narrower tile an FP32 row (4k bytes) is split into partial
+// cache lines that two blocks fetch and write separately, and the restriction
+// and prolongation fetched twice their bytes that way.
+bool aligned16(const void *p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; }
+
+int32_t row_tile(int32_t k) { return k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; }
+
+template <typename F>
+void with_row_tile(int32_t k, F &&f) {
+  switch (row_tile(k)) {
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    case 32: f(std::integral_constant<int, 32>{}); break;
+    default: f(std::integral_constant<int, 64>{}); break;
+  }
+}
+
 // R_c(J) = sum over the segment of J (aggregate-major positions), in order,
 // of p_m T(m)
 template <typename TV, int KT>
@@ -260,6 +300,28 @@ __global__ void kb_prolong(int32_t n, int32_t k, const int32_t *__restrict__ agg
   const int64_t i = (int64_t)blockIdx.x * (kBlock / KT) + threadIdx.x / KT;
   if (j >= k || i >= n) return;
   Z[i * k + j] += pp[i] * Zc[(int64_t)aggp[i] * k + j];
+}
+
+// the prolongation with VW consecutive columns per thread
+template <typename TV, int KT>
+__global__ void kb_prolong_v(int32_t n, int32_t kv, const int32_t *__restrict__ aggp,
+                             const TV *__restrict__ pp, const TV *__restrict__ Zc,
+                             TV *__restrict__ Z, const int32_t *__restrict__ stop) {
+  using V = typename Vec16<TV>::T;
+  constexpr int VW = Vec16<TV>::width;
+  if (*stop) return;
+  const int32_t jv = blockIdx.y * KT + threadIdx.x % KT;
+  const int64_t i = (int64_t)blockIdx.x * (kBlock / KT) + threadIdx.x / KT;
+  if (jv >= kv || i >= n) return;
+  const TV p = pp[i];
+  const V c = reinterpret_cast<const V *>(Zc)[(int64_t)aggp[i] * kv + jv];
+  V *zp = reinterpret_cast<V *>(Z) + i * kv + jv;
+  V z = *zp;
+  const TV *cv = reinterpret_cast<const TV *>(&c);
+  TV *zv = reinterpret_cast<TV *>(&z);
+#pragma unroll
+  for (int q = 0; q < VW; ++q) zv[q] += p * cv[q];
+  *zp = z;
 }
 
 // row permutation of an n x k block: Dst(q) = Src(perm q) (IN) or
@@ -435,6 +497,80 @@ __global__ void kb_xpay(int32_t n, int32_t k, const double *__restrict__ Z,
   if (j >= k || i >= n || done[j]) return;
   const int64_t o = i * k + j;
   P[o] = copy ? Z[o] : Z[o] + colv[cBeta * k + j] * P[o];
+}
+
+// the CG update with two columns per thread (k even, blocks 16-byte
+// aligned); a converged column's half of each vector is stored back
+// unchanged, and its partial sum is zero as in the one-value form
+template <int KT>
+__global__ void __launch_bounds__(kBlock) kb_update_v(int32_t n, int32_t kv,
+                                                      double *__restrict__ X,
+                                                      double *__restrict__ R,
+                                                      float *__restrict__ Rf,
+                                                      const double *__restrict__ P,
+                                                      const double *__restrict__ Q,
+                                                      const double *__restrict__ colv,
+                                                      const int32_t *__restrict__ done,
+                                                      double *__restrict__ partials,
+                                                      const int32_t *__restrict__ stop) {
+  if (*stop) return;
+  const int32_t jv = blockIdx.y * KT + threadIdx.x % KT;
+  const int32_t k = 2 * kv, j = 2 * jv;
+  const bool valid = jv < kv;
+  const bool live0 = valid && done[j] == 0, live1 = valid && done[j + 1] == 0;
+  const double a0 = live0 ? colv[cAlpha * k + j] : 0.0;
+  const double a1 = live1 ? colv[cAlpha * k + j + 1] : 0.0;
+  double d0 = 0.0, d1 = 0.0;
+  if (live0 || live1) {
+    double2 *X2 = reinterpret_cast<double2 *>(X), *R2 = reinterpret_cast<double2 *>(R);
+    const double2 *P2 = reinterpret_cast<const double2 *>(P);
+    const double2 *Q2 = reinterpret_cast<const double2 *>(Q);
+    float2 *Rf2 = reinterpret_cast<float2 *>(Rf);
+    for (int64_t grp = first_group(); grp * (kBlock / KT) < n; grp += gridDim.x) {
+      const int32_t row = (int32_t)(grp * (kBlock / KT)) + (int32_t)threadIdx.x / KT;
+      if (row >= n) continue;
+      const int64_t o = (int64_t)row * kv + jv;
+      double2 x = X2[o], r = R2[o];
+      const double2 p = P2[o], q = Q2[o];
+      if (live0) {
+        x.x += a0 * p.x;
+        r.x = r.x - a0 * q.x;
+        d0 += r.x * r.x;
+      }
+      if (live1) {
+        x.y += a1 * p.y;
+        r.y = r.y - a1 * q.y;
+        d1 += r.y * r.y;
+      }
+      X2[o] = x;
+      R2[o] = r;
+      if (Rf) Rf2[o] = make_float2((float)r.x, (float)r.y);
+    }
+  }
+  column_partial<KT>(d0, valid, j, k, partials);
+  __syncthreads();
+  column_partial<KT>(d1, valid, j + 1, k, partials);
+}
+
+// p = z + beta p with two columns per thread (k even, blocks 16-byte
+// aligned); a converged column's half of the vector is stored back unchanged
+template <int KT>
+__global__ void kb_xpay_v(int32_t n, int32_t kv, const double *__restrict__ Z,
+                          double *__restrict__ P, const double *__restrict__ colv,
+                          const int32_t *__restrict__ done, const int32_t *__restrict__ stop) {
+  if (*stop) return;
+  const int32_t jv = blockIdx.y * KT + threadIdx.x % KT;
+  const int64_t i = (int64_t)blockIdx.x * (kBlock / KT) + threadIdx.x / KT;
+  if (jv >= kv || i >= n) return;
+  const int32_t k = 2 * kv, j = 2 * jv;
+  const bool live0 = done[j] == 0, live1 = done[j + 1] == 0;
+  if (!live0 && !live1) return;
+  const int64_t o = i * kv + jv;
+  const double2 z = reinterpret_cast<const double2 *>(Z)[o];
+  double2 v = reinterpret_cast<double2 *>(P)[o];
+  if (live0) v.x = z.x + colv[cBeta * k + j] * v.x;
+  if (live1) v.y = z.y + colv[cBeta * k + j + 1] * v.y;
+  reinterpret_cast<double2 *>(P)[o] = v;
 }
 
 template <int KT>
@@ -680,11 +816,19 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
   // yout[l] records where the last one (l > 0) left y_l.
   for (int32_t l = L - 1; l >= 0; --l) {
     Level &F = h->lv[l];
-    with_row_tile(k, [&](auto kt) {
-      constexpr int KE = decltype(kt)::value;
-      kb_prolong<TV, KE><<<egrid(F.n, k, KE), kBlock, 0, s>>>(F.n, k, F.aggp, ppv<TV>(F),
-                                                             yout[l + 1], zc[l], stop);
-    });
+    constexpr int VW = Vec16<TV>::width;
+    if (k % VW == 0 && aligned16(yout[l + 1]) && aligned16(zc[l]))
+      with_row_tile(k / VW, [&](auto kt) {
+        constexpr int KE = decltype(kt)::value;
+        kb_prolong_v<TV, KE><<<egrid(F.n, k / VW, KE), kBlock, 0, s>>>(
+            F.n, k / VW, F.aggp, ppv<TV>(F), yout[l + 1], zc[l], stop);
+      });
+    else
+      with_row_tile(k, [&](auto kt) {
+        constexpr int KE = decltype(kt)::value;
+        kb_prolong<TV, KE><<<egrid(F.n, k, KE), kBlock, 0, s>>>(F.n, k, F.aggp, ppv<TV>(F),
+                                                               yout[l + 1], zc[l], stop);
+      });
     const BGeom g = bgeom(F.n, k, KT);
     TV *bufs[3] = {(TV *)B.y[l], (TV *)B.z[l], (TV *)B.t[l]};
     TV *z = zc[l];
@@ -727,25 +871,6 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
   }
 }
 
-// The kernels that take one thread per element (the CG update, p = z + b p,
-// restriction, prolongation) choose their column tile from k alone: the
-// smallest tile covering k, at most 64. One block then reads and writes whole
-// rows; with a narrower tile an FP32 row (4k bytes) is split into partial
-// cache lines that two blocks fetch and write separately, and the restriction
-// and prolongation fetched twice their bytes that way.
-int32_t row_tile(int32_t k) { return k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; }
-
-template <typename F>
-void with_row_tile(int32_t k, F &&f) {
-  switch (row_tile(k)) {
-    case 4: f(std::integral_constant<int, 4>{}); break;
-    case 8: f(std::integral_constant<int, 8>{}); break;
-    case 16: f(std::integral_constant<int, 16>{}); break;
-    case 32: f(std::integral_constant<int, 32>{}); break;
-    default: f(std::integral_constant<int, 64>{}); break;
-  }
-}
-
 template <int KU>
 int32_t launch_update(amg_hierarchy *h, const int32_t *stop) {
   Batch &B = *h->batch;
@@ -757,8 +882,21 @@ int32_t launch_update(amg_hierarchy *h, const int32_t *stop) {
 }
 
 int32_t cg_update(amg_hierarchy *h, const int32_t *stop) {
+  Batch &B = *h->batch;
+  const int32_t n = h->lv[0].n, k = B.k;
   int32_t nparts = 0;
-  with_row_tile(h->batch->k, [&](auto kt) { nparts = launch_update<decltype(kt)::value>(h, stop); });
+  if (k % 2 == 0 && aligned16(B.X) && aligned16(B.R) && aligned16(B.P) && aligned16(B.Q) &&
+      (!B.Rf || reinterpret_cast<uintptr_t>(B.Rf) % 8 == 0)) {
+    with_row_tile(k / 2, [&](auto kt) {
+      constexpr int KU = decltype(kt)::value;
+      const BGeom g = bgeom(n, k / 2, KU);
+      kb_update_v<KU><<<g.grid, kBlock, 0, h->stream>>>(n, k / 2, B.X, B.R, B.Rf, B.P, B.Q,
+                                                        B.col, B.done, B.partials, stop);
+      nparts = (int32_t)g.grid.x;
+    });
+  } else {
+    with_row_tile(k, [&](auto kt) { nparts = launch_update<decltype(kt)::value>(h, stop); });
+  }
   return nparts;
 }
 
@@ -777,10 +915,17 @@ void iteration_b(amg_hierarchy *h, int32_t maxit) {
   bfinalize(h, bRr, cg_update(h, stop), maxit, stop);
   kb_all_done<<<1, 64, 0, s>>>(k, B.done, B.all_done);
   vcycle_b<TV, KT>(h, B.R, B.Z, bRz, maxit, stop);
-  with_row_tile(k, [&](auto kt) {
-    constexpr int KE = decltype(kt)::value;
-    kb_xpay<KE><<<egrid(n, k, KE), kBlock, 0, s>>>(n, k, B.Z, B.P, B.col, B.done, 0, stop);
-  });
+  if (k % 2 == 0 && aligned16(B.Z) && aligned16(B.P))
+    with_row_tile(k / 2, [&](auto kt) {
+      constexpr int KE = decltype(kt)::value;
+      kb_xpay_v<KE><<<egrid(n, k / 2, KE), kBlock, 0, s>>>(n, k / 2, B.Z, B.P, B.col, B.done,
+                                                            stop);
+    });
+  else
+    with_row_tile(k, [&](auto kt) {
+      constexpr int KE = decltype(kt)::value;
+      kb_xpay<KE><<<egrid(n, k, KE), kBlock, 0, s>>>(n, k, B.Z, B.P, B.col, B.done, 0, stop);
+    });
 }
 
 template <typename TV>
