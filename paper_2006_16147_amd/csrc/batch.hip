@@ -99,6 +99,63 @@ __device__ __forceinline__ void sell_dot_cols(const int32_t *__restrict__ col,
   }
 }
 
+// VW consecutive values of a block row as one 16-byte vector: the down step,
+// the outer SpMV, the prolongation, the CG update and p = z + b p have a form
+// with VW columns per thread for k a multiple of VW and 16-byte aligned blocks
+// (kv = k / VW vectors per row), with a quarter (FP32) or half (FP64) of the
+// threads or gathers and memory instructions.
+template <typename TV>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using T = float4;
+  static constexpr int width = 4;
+};
+template <>
+struct Vec16<double> {
+  using T = double2;
+  static constexpr int width = 2;
+};
+
+// N consecutive values at p (N values 16-byte aligned when N fills whole
+// 16-byte vectors of T)
+template <typename T, int N>
+__device__ __forceinline__ void ld_vals(const T *p, T (&out)[N]) {
+  using V = typename Vec16<T>::T;
+  constexpr int W = Vec16<T>::width;
+  if constexpr (N % W == 0) {
+#pragma unroll
+    for (int c = 0; c < N / W; ++c) {
+      const V v = reinterpret_cast<const V *>(p)[c];
+      const T *e = reinterpret_cast<const T *>(&v);
+#pragma unroll
+      for (int q = 0; q < W; ++q) out[c * W + q] = e[q];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < N; ++q) out[q] = p[q];
+  }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void st_vals(T *p, const T (&in)[N]) {
+  using V = typename Vec16<T>::T;
+  constexpr int W = Vec16<T>::width;
+  if constexpr (N % W == 0) {
+#pragma unroll
+    for (int c = 0; c < N / W; ++c) {
+      V v;
+      T *e = reinterpret_cast<T *>(&v);
+#pragma unroll
+      for (int q = 0; q < W; ++q) e[q] = in[c * W + q];
+      reinterpret_cast<V *>(p)[c] = v;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < N; ++q) p[q] = in[q];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // V-cycle kernels on n x k blocks
 // ---------------------------------------------------------------------------
@@ -137,6 +194,70 @@ __global__ void __launch_bounds__(kBlock) kb_pre_residual(
       Z[o] = ri * mi;
       T[o] = ri - acc[q];
     }
+  }
+}
+
+// kb_pre_residual for a residual block already in the hierarchy precision,
+// with VW consecutive columns per lane and each gathered block row entry
+// loaded as one 16-byte vector (k a multiple of VW, blocks 16-byte aligned,
+// kv = k / VW); the same sums in the same order
+template <typename TV, int KT>
+__global__ void __launch_bounds__(kBlock) kb_pre_residual_v(
+    int32_t n, int32_t kv, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
+    const TV *__restrict__ val, const TV *__restrict__ minv, const TV *__restrict__ R,
+    TV *__restrict__ Z, TV *__restrict__ T, const int32_t *__restrict__ stop) {
+  using V = typename Vec16<TV>::T;
+  constexpr int VW = Vec16<TV>::width;
+  if (*stop) return;
+  const int32_t jv = blockIdx.y * KT + threadIdx.x % KT;
+  if (jv >= kv) return;
+  const V *Rv = reinterpret_cast<const V *>(R);
+  for (int64_t grp = first_group(); grp * (kBlock / KT) < n; grp += gridDim.x) {
+    const int32_t row = (int32_t)(grp * (kBlock / KT)) + (int32_t)threadIdx.x / KT;
+    if (row >= n) continue;
+    int32_t base, w;
+    sell_row(sptr, row, &base, &w);
+    TV acc[VW];
+#pragma unroll
+    for (int q = 0; q < VW; ++q) acc[q] = 0;
+    for (int32_t k0 = 0; k0 < w; k0 += kRowBatch) {
+      int32_t c[kRowBatch];
+      TV v[kRowBatch];
+      V g[kRowBatch];
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        c[u] = 0;
+        v[u] = 0;
+        if (k0 + u < w) {
+          const int32_t idx = base + (k0 + u) * kSlice;
+          c[u] = ld_stream(&col[idx]);
+          v[u] = ld_stream(&val[idx]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u)
+        if (k0 + u < w) g[u] = Rv[(int64_t)c[u] * kv + jv];
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u)
+        if (k0 + u < w) {
+          const TV *gu = reinterpret_cast<const TV *>(&g[u]);
+#pragma unroll
+          for (int q = 0; q < VW; ++q) acc[q] += v[u] * gu[q];
+        }
+    }
+    const TV mi = minv[row];
+    const int64_t o = (int64_t)row * kv + jv;
+    const V r = Rv[o];
+    const TV *ri = reinterpret_cast<const TV *>(&r);
+    V z, t;
+    TV *zo = reinterpret_cast<TV *>(&z), *to = reinterpret_cast<TV *>(&t);
+#pragma unroll
+    for (int q = 0; q < VW; ++q) {
+      zo[q] = ri[q] * mi;
+      to[q] = ri[q] - acc[q];
+    }
+    reinterpret_cast<V *>(Z)[o] = z;
+    reinterpret_cast<V *>(T)[o] = t;
   }
 }
 
@@ -189,6 +310,83 @@ __global__ void __launch_bounds__(kBlock) kb_post(
   }
 }
 
+// kb_post with VW = Vec16<TV>::width consecutive columns per lane and each
+// gathered entry of Z loaded as one 16-byte vector (k a multiple of VW, blocks
+// 16-byte aligned, kv = k / VW); the same sums in the same order
+template <typename TV, typename TR, typename TO, int KT, bool DOT>
+__global__ void __launch_bounds__(kBlock) kb_post_v(
+    int32_t n, int32_t kv, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
+    const TV *__restrict__ val, const TV *__restrict__ minv, const TR *__restrict__ R,
+    const TV *__restrict__ Z, TO *__restrict__ Y, double *__restrict__ partials,
+    const int32_t *__restrict__ stop) {
+  using V = typename Vec16<TV>::T;
+  constexpr int VW = Vec16<TV>::width;
+  if (*stop) return;
+  const int32_t jv = blockIdx.y * KT + threadIdx.x % KT;
+  const int32_t k = VW * kv, j = VW * jv;
+  const bool ok = jv < kv;
+  const V *Zv = reinterpret_cast<const V *>(Z);
+  double d[VW];
+#pragma unroll
+  for (int q = 0; q < VW; ++q) d[q] = 0.0;
+  if (ok) {
+    for (int64_t grp = first_group(); grp * (kBlock / KT) < n; grp += gridDim.x) {
+      const int32_t row = (int32_t)(grp * (kBlock / KT)) + (int32_t)threadIdx.x / KT;
+      if (row >= n) continue;
+      int32_t base, w;
+      sell_row(sptr, row, &base, &w);
+      TV acc[VW];
+#pragma unroll
+      for (int q = 0; q < VW; ++q) acc[q] = 0;
+      for (int32_t k0 = 0; k0 < w; k0 += kRowBatch) {
+        int32_t c[kRowBatch];
+        TV v[kRowBatch];
+        V g[kRowBatch];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) {
+          c[u] = 0;
+          v[u] = 0;
+          if (k0 + u < w) {
+            const int32_t idx = base + (k0 + u) * kSlice;
+            c[u] = ld_stream(&col[idx]);
+            v[u] = ld_stream(&val[idx]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u)
+          if (k0 + u < w) g[u] = Zv[(int64_t)c[u] * kv + jv];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u)
+          if (k0 + u < w) {
+            const TV *gu = reinterpret_cast<const TV *>(&g[u]);
+#pragma unroll
+            for (int q = 0; q < VW; ++q) acc[q] += v[u] * gu[q];
+          }
+      }
+      const TV mi = minv[row];
+      const int64_t o = (int64_t)row * k + j;
+      TR rr[VW];
+      TV zz[VW];
+      TO yo[VW];
+      ld_vals(R + o, rr);
+      ld_vals(Z + o, zz);
+#pragma unroll
+      for (int q = 0; q < VW; ++q) {
+        yo[q] = (TO)(zz[q] + ((TV)rr[q] - acc[q]) * mi);
+        if (DOT) d[q] += (double)rr[q] * (double)yo[q];
+      }
+      st_vals(Y + o, yo);
+    }
+  }
+  if (DOT) {
+#pragma unroll
+    for (int q = 0; q < VW; ++q) {
+      if (q) __syncthreads();
+      column_partial<KT>(d[q], ok, j + q, k, partials);
+    }
+  }
+}
+
 // T = R - A Z (the residual after extra pre-smoothing sweeps)
 template <typename TV, typename TR, int KT>
 __global__ void __launch_bounds__(kBlock) kb_resid(
@@ -223,23 +421,6 @@ __global__ void __launch_bounds__(kBlock) kb_resid(
   }
 }
 
-// VW consecutive values of a block row as one 16-byte vector: the
-// prolongation, the CG update and p = z + b p have a form with VW columns per
-// thread for k a multiple of VW and 16-byte aligned blocks (kv = k / VW
-// vectors per row), with a quarter (FP32) or half (FP64) of the threads and
-// memory instructions.
-template <typename TV>
-struct Vec16;
-template <>
-struct Vec16<float> {
-  using T = float4;
-  static constexpr int width = 4;
-};
-template <>
-struct Vec16<double> {
-  using T = double2;
-  static constexpr int width = 2;
-};
 
 // The kernels that take one thread per element (the CG update, p = z + b p,
 // restriction, prolongation) choose their column tile from k alone: the
@@ -430,6 +611,87 @@ __global__ void __launch_bounds__(kBlock) kb_spmv(
     if (mode == 1) {
       __syncthreads();
       column_partial<KT>(d1[q], ok[q], jc[q], k, partials + plane);
+    }
+  }
+}
+
+// kb_spmv with two consecutive columns per lane, each gathered block row
+// entry loaded as one 16-byte vector (k even, blocks 16-byte aligned, kv =
+// k / 2): half the gather instructions; the same sums in the same order
+template <int KT>
+__global__ void __launch_bounds__(kBlock) kb_spmv_v(
+    int32_t n, int32_t kv, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
+    const double *__restrict__ val, const double *__restrict__ Xin,
+    const double *__restrict__ B, double *__restrict__ Out, float *__restrict__ OutF,
+    double *__restrict__ partials, int32_t mode, const int32_t *__restrict__ stop) {
+  if (stop && *stop) return;
+  const int32_t jv = blockIdx.y * KT + threadIdx.x % KT;
+  const int32_t k = 2 * kv, j = 2 * jv;
+  const bool ok = jv < kv;
+  const double2 *X2 = reinterpret_cast<const double2 *>(Xin);
+  double d0[2] = {0.0, 0.0}, d1[2] = {0.0, 0.0};
+  if (ok) {
+    for (int64_t grp = first_group(); grp * (kBlock / KT) < n; grp += gridDim.x) {
+      const int32_t row = (int32_t)(grp * (kBlock / KT)) + (int32_t)threadIdx.x / KT;
+      if (row >= n) continue;
+      int32_t base, w;
+      sell_row(sptr, row, &base, &w);
+      double a0 = 0.0, a1 = 0.0;
+      for (int32_t k0 = 0; k0 < w; k0 += kRowBatch) {
+        int32_t c[kRowBatch];
+        double v[kRowBatch];
+        double2 g[kRowBatch];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) {
+          c[u] = 0;
+          v[u] = 0.0;
+          if (k0 + u < w) {
+            const int32_t idx = base + (k0 + u) * kSlice;
+            c[u] = ld_stream(&col[idx]);
+            v[u] = ld_stream(&val[idx]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u)
+          g[u] = k0 + u < w ? X2[(int64_t)c[u] * kv + jv] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u)
+          if (k0 + u < w) {
+            a0 += v[u] * g[u].x;
+            a1 += v[u] * g[u].y;
+          }
+      }
+      const int64_t o = (int64_t)row * kv + jv;
+      if (mode == 0) {
+        reinterpret_cast<double2 *>(Out)[o] = make_double2(a0, a1);
+        const double2 xo = X2[o];
+        d0[0] += xo.x * a0;
+        d0[1] += xo.y * a1;
+      } else {
+        const double2 bi = reinterpret_cast<const double2 *>(B)[o];
+        const double r0 = bi.x - a0, r1 = bi.y - a1;
+        if (mode == 1) {
+          reinterpret_cast<double2 *>(Out)[o] = make_double2(r0, r1);
+          if (OutF) reinterpret_cast<float2 *>(OutF)[o] = make_float2((float)r0, (float)r1);
+          d0[0] += bi.x * bi.x;
+          d0[1] += bi.y * bi.y;
+          d1[0] += r0 * r0;
+          d1[1] += r1 * r1;
+        } else {
+          d0[0] += r0 * r0;
+          d0[1] += r1 * r1;
+        }
+      }
+    }
+  }
+  const int64_t plane = (int64_t)kBatchBlocks * k;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    if (q) __syncthreads();
+    column_partial<KT>(d0[q], ok, j + q, k, partials);
+    if (mode == 1) {
+      __syncthreads();
+      column_partial<KT>(d1[q], ok, j + q, k, partials + plane);
     }
   }
 }
@@ -764,7 +1026,21 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
     Level &F = h->lv[l];
     const BGeom g = bgeom(F.n, k, KT);
     TV *z = (TV *)B.z[l], *y = (TV *)B.y[l], *t = (TV *)B.t[l];
-    if (l == 0 && R0v)
+    // the residual of this level in the hierarchy precision, if there is one
+    const TV *Rl = l > 0 ? (const TV *)B.r[l]
+                         : (R0v ? R0v
+                                : (std::is_same<TV, double>::value
+                                       ? reinterpret_cast<const TV *>(R0)
+                                       : nullptr));
+    constexpr int VW = Vec16<TV>::width;
+    if (Rl && k % VW == 0 && aligned16(Rl) && aligned16(z) && aligned16(t))
+      with_row_tile(k / VW, [&](auto kt) {
+        constexpr int KV = decltype(kt)::value;
+        const BGeom gv = bgeom(F.n, k / VW, KV);
+        kb_pre_residual_v<TV, KV><<<gv.grid, kBlock, 0, s>>>(
+            F.n, k / VW, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), Rl, z, t, stop);
+      });
+    else if (l == 0 && R0v)
       kb_pre_residual<TV, TV, KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(
           F.n, k, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), R0v, z, t, stop);
     else if (l == 0)
@@ -858,10 +1134,24 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
               stop);
         z = out;
       } else if (rz_op >= 0) {
-        kb_post<TV, double, double, KT, true><<<tgrid(g, k, KT), kBlock, 0, s>>>(
-            F.n, k, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, Z0, B.partials,
-            stop);
-        bfinalize(h, rz_op, (int32_t)g.grid.x, maxit, stop);
+        constexpr int VW = Vec16<TV>::width;
+        if (k % VW == 0 && aligned16(R0) && aligned16(z) && aligned16(Z0)) {
+          int32_t np = 0;
+          with_row_tile(k / VW, [&](auto kt) {
+            constexpr int KV = decltype(kt)::value;
+            const BGeom gv = bgeom(F.n, k / VW, KV);
+            kb_post_v<TV, double, double, KV, true><<<gv.grid, kBlock, 0, s>>>(
+                F.n, k / VW, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, Z0,
+                B.partials, stop);
+            np = (int32_t)gv.grid.x;
+          });
+          bfinalize(h, rz_op, np, maxit, stop);
+        } else {
+          kb_post<TV, double, double, KT, true><<<tgrid(g, k, KT), kBlock, 0, s>>>(
+              F.n, k, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, Z0, B.partials,
+              stop);
+          bfinalize(h, rz_op, (int32_t)g.grid.x, maxit, stop);
+        }
       } else {
         kb_post<TV, double, double, KT, false><<<tgrid(g, k, KT), kBlock, 0, s>>>(
             F.n, k, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, Z0, nullptr,
@@ -869,6 +1159,28 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
       }
     }
   }
+}
+
+// Launches the vector form of the block SpMV when k and the blocks allow it;
+// returns the number of partial rows it wrote, or 0 if it did not launch.
+int32_t spmv_vec(amg_hierarchy *h, const double *Xin, const double *Bv, double *Out,
+                 float *OutF, int32_t mode, const int32_t *stop) {
+  Batch &B = *h->batch;
+  Level &L0 = h->lv[0];
+  const int32_t n = L0.n, k = B.k;
+  if (k % 2 != 0 || !aligned16(Xin) || (Bv && !aligned16(Bv)) || (Out && !aligned16(Out)) ||
+      (OutF && reinterpret_cast<uintptr_t>(OutF) % 8 != 0))
+    return 0;
+  int32_t nparts = 0;
+  with_row_tile(k / 2, [&](auto kt) {
+    constexpr int KV = decltype(kt)::value;
+    const BGeom g = bgeom(n, k / 2, KV);
+    kb_spmv_v<KV><<<g.grid, kBlock, 0, h->stream>>>(n, k / 2, L0.S.sptr, L0.S.col, L0.S.v64,
+                                                    Xin, Bv, Out, OutF, B.partials, mode,
+                                                    stop);
+    nparts = (int32_t)g.grid.x;
+  });
+  return nparts;
 }
 
 template <int KU>
@@ -909,9 +1221,13 @@ void iteration_b(amg_hierarchy *h, int32_t maxit) {
   const int32_t n = L0.n;
   const int32_t *stop = B.all_done;
   const BGeom g = bgeom(n, k, KT);
-  kb_spmv<KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(n, k, L0.S.sptr, L0.S.col, L0.S.v64, B.P,
-                                        nullptr, B.Q, nullptr, B.partials, 0, stop);
-  bfinalize(h, bPq, (int32_t)g.grid.x, maxit, stop);
+  int32_t np = spmv_vec(h, B.P, nullptr, B.Q, nullptr, 0, stop);
+  if (np == 0) {
+    kb_spmv<KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(n, k, L0.S.sptr, L0.S.col, L0.S.v64, B.P,
+                                          nullptr, B.Q, nullptr, B.partials, 0, stop);
+    np = (int32_t)g.grid.x;
+  }
+  bfinalize(h, bPq, np, maxit, stop);
   bfinalize(h, bRr, cg_update(h, stop), maxit, stop);
   kb_all_done<<<1, 64, 0, s>>>(k, B.done, B.all_done);
   vcycle_b<TV, KT>(h, B.R, B.Z, bRz, maxit, stop);
@@ -966,6 +1282,9 @@ void launch_spmv_mode(amg_hierarchy *h, const double *Xin, const double *Bv, dou
 
 void spmv_mode(amg_hierarchy *h, const double *Xin, const double *Bv, double *Out, int32_t mode,
                int32_t *nparts) {
+  Batch &B = *h->batch;
+  *nparts = spmv_vec(h, Xin, Bv, Out, mode == 1 && Out == B.R ? B.Rf : nullptr, mode, nullptr);
+  if (*nparts) return;
   switch (h->batch->kt) {
     case 4: launch_spmv_mode<4>(h, Xin, Bv, Out, mode, nparts); break;
     case 8: launch_spmv_mode<8>(h, Xin, Bv, Out, mode, nparts); break;
