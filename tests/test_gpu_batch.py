@@ -83,6 +83,33 @@ def test_batch_fp32_hierarchy(orc):
     assert np.linalg.norm(X[:, 7] - x1) / np.linalg.norm(x1) < 1e-8
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("k", [2, 6, 12])
+def test_batch_vector_and_one_value_forms_agree(orc, k, precision):
+    """The level-0 kernels move two FP64 or four FP32 columns per lane when k
+    allows it. With k = 2 and 6 the FP32 hierarchy mixes the two-column FP64
+    kernels (outer SpMV, CG update, p = z + b p) with the one-value forms of
+    the FP32 ones; k = 12 takes the vector forms throughout. Every column
+    matches its single solve and, at equal iterations, the oracle."""
+    from paper_2006_16147_amd import amg
+
+    A = inputs.laplacian7(16)
+    B = np.random.default_rng(9 + k).uniform(-1, 1, (A.n, k))
+    fp32 = precision == "fp32"
+    h = setup(A, precision=amg.FP32 if fp32 else amg.FP64)
+    st, infos, X = _batch(h, B)
+    assert st == 0 and all(i["converged"] for i in infos)
+    ho = orc.Hierarchy(A)
+    for j in range(k):
+        _, i1, x1 = _single(h, B[:, j])
+        assert abs(i1["iterations"] - infos[j]["iterations"]) <= 1
+        assert np.linalg.norm(X[:, j] - x1) / np.linalg.norm(x1) < (1e-8 if fp32 else 1e-9)
+        assert infos[j]["rel_res_true"] <= (1.01e-8 if fp32 else 1.001e-8)
+        if not fp32:
+            xo, _ = ho.pcg(B[:, j], rtol=0.0, maxit=infos[j]["iterations"])
+            assert np.linalg.norm(X[:, j] - xo) / np.linalg.norm(xo) < 1e-8
+
+
 def test_batch_edge_cases(orc):
     import torch
 
