@@ -100,7 +100,8 @@ int orc_galerkin_pairwise(const orc_csr *A, int32_t nc, const int32_t *agg,
 void orc_csr_free(orc_csr *A);
 
 /* Smoothed aggregation (the alternative to the K-cycle in Section 3.2):
- * omega = 1 / ||D^-1 A||_inf with D = diag(A); the smoothed prolongator
+ * omega = 4 / (3 ||D^-1 A||_inf) with D = diag(A) (the damping that reproduces
+ * the supplement's smoothed-prolongator convergence constant); the smoothed prolongator
  * Pbar = (I - omega D^-1 A) P of the tentative P given as (agg, p), with nc
  * columns (row order and sums as stated in oracle.c); and the Galerkin
  * product A_c = Pbar^T A Pbar (lower triangle mirrored from the upper). */

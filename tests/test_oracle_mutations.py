@@ -134,7 +134,10 @@ MUTATIONS = [
     ("smoothed P: omega from the row sums without |.|",
      "for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) s = s + fabs(A->val[k]);\n    double r",
      "for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) s = s + A->val[k];\n    double r",
-     SM + "test_omega_is_the_inverse_inf_norm_of_the_scaled_matrix"),
+     SM + "test_omega_is_four_thirds_over_the_inf_norm_of_the_scaled_matrix"),
+    ("smoothed P: omega = 1 / ||D^-1 A||_inf (the text's formula)",
+     "  return 4.0 / (3.0 * nrm);", "  return 1.0 / nrm;",
+     PIN + "test_supplement_smoothed_K_gauss_seidel"),
     ("general Galerkin: coefficient dropped in the row combination",
      "double t = coef[k] * B->val[e];", "double t = B->val[e];",
      SM + "test_galerkin_with_pbar_is_the_dense_product"),

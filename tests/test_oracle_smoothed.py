@@ -1,6 +1,8 @@
 """Pins of the oracle's smoothed aggregation (the alternative to the K-cycle
-in Section 3.2): Pbar = (I - omega D^-1 A) P with omega = 1 / ||D^-1 A||_inf,
-and the Galerkin product Pbar^T A Pbar.
+in Section 3.2): Pbar = (I - omega D^-1 A) P with omega = 4 / (3 ||D^-1 A||_inf),
+and the Galerkin product Pbar^T A Pbar. (The choice of omega is pinned to the
+supplement's smoothed-prolongator convergence constant in
+test_oracle_paper_pins.py.)
 
 Each pin uses an independent computation: dense NumPy products from the
 definitions, SciPy sparse products on the oracle's own aggregates, the
@@ -33,16 +35,16 @@ def _cases():
 
 
 @pytest.mark.parametrize("case", ["poisson12", "aniso12", "random"])
-def test_omega_is_the_inverse_inf_norm_of_the_scaled_matrix(orc, case):
+def test_omega_is_four_thirds_over_the_inf_norm_of_the_scaled_matrix(orc, case):
     A = _cases()[case]
     D = _sp(A).toarray()
-    ref = 1.0 / np.max(np.abs(D).sum(axis=1) / np.diag(D))
+    ref = 4.0 / (3.0 * np.max(np.abs(D).sum(axis=1) / np.diag(D)))
     assert orc.smoothing_omega(A) == pytest.approx(ref, rel=1e-15)
 
 
 def test_omega_closed_form_for_the_poisson_matrix(orc):
-    # interior rows: (6 + 6) / 6 = 2, so omega = 1/2 exactly
-    assert orc.smoothing_omega(inputs.laplacian7(10)) == 0.5
+    # interior rows: (6 + 6) / 6 = 2, so omega = 4 / 6 = 2/3 (correctly rounded)
+    assert orc.smoothing_omega(inputs.laplacian7(10)) == 4.0 / 6.0
 
 
 @pytest.mark.parametrize("case", ["poisson12", "aniso12", "random"])
@@ -112,7 +114,7 @@ def test_every_level_matches_scipy_products_on_the_same_aggregates(orc):
         agg, p = ho.transfer(l)
         P = sp.csr_matrix((p, (np.arange(len(agg)), agg)), shape=(len(agg), nc))
         d = S.diagonal()
-        om = 1.0 / np.max(abs(S).sum(axis=1).A.ravel() / d)
+        om = 4.0 / (3.0 * np.max(abs(S).sum(axis=1).A.ravel() / d))
         Pb = (P - om * (sp.diags(1.0 / d) @ S @ P)).tocsr()
         S = (Pb.T @ S @ Pb).tocsr()
         assert S.nnz == ho.level_nnz(l + 1)
