@@ -177,6 +177,66 @@ def ingest_pmc(fetch_csv, write_csv):
     print(json.dumps(out))
 
 
+def _grid(r):
+    for key in ("Grid_Size", "Grid_Size_X"):
+        if r.get(key) not in (None, ""):
+            return int(r[key])
+    return 0
+
+
+def _short(name):
+    """Kernel name without return type, namespaces and argument list."""
+    if name.startswith("void "):
+        name = name[5:]
+    depth, cut, ns = 0, len(name), 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0 and not name.startswith("(anonymous", i):
+            cut = i
+            break
+        elif ch == ":" and depth == 0 and name[i:i + 2] == "::":
+            ns = i + 2
+    return name[ns:cut] if ns < cut else name[:cut]
+
+
+def kernel_summary(trace_csv):
+    """Markdown summary of a rocprofv3 kernel trace: per kernel the calls and
+    the average / min / max duration, and, for the level-0 solve kernels, the
+    average over their full launches only (largest grid, and not the early
+    exits that the iterations queued past convergence take, which last a few
+    microseconds: durations below half the median of those launches)."""
+    rows = _counter_rows(trace_csv)
+    per = {}
+    for r in rows:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3  # us
+        per.setdefault(r["Kernel_Name"], []).append((d, _grid(r)))
+    tot = sum(d for v in per.values() for d, _ in v)
+    out = ["| kernel | calls | avg us | min us | max us | total ms | % |",
+           "|---|---|---|---|---|---|---|"]
+    for name, v in sorted(per.items(), key=lambda kv: -sum(d for d, _ in kv[1]))[:40]:
+        ds = [d for d, _ in v]
+        out.append("| `%s` | %d | %.1f | %.1f | %.1f | %.2f | %.1f |" % (
+            _short(name), len(ds), sum(ds) / len(ds), min(ds), max(ds), sum(ds) / 1e3, 100 * sum(ds) / tot))
+    out += ["", "Level-0 solve kernels, full launches only (largest grid, early exits left out):",
+            "", "| kernel | full launches | avg us | min us | max us |", "|---|---|---|---|---|"]
+    for frag in ("k_pre_restrict<double, double, 0", "k_post<double, double, double, true,",
+                 "k_spmv_dot<float>", "k_pre_restrict<float, double, 0",
+                 "k_post<float, double, double, true,"):
+        for name, v in per.items():
+            if frag not in name:
+                continue
+            top = max(g for _, g in v)
+            ds = sorted(d for d, g in v if g == top)
+            med = ds[len(ds) // 2]
+            full = [d for d in ds if d >= 0.5 * med]
+            out.append("| `%s` | %d | %.2f | %.1f | %.1f |" % (
+                _short(name), len(full), sum(full) / len(full), min(full), max(full)))
+    print("\n".join(out))
+
+
 def bench_kcycle(args):
     """160^3 Poisson (b = A u): flexible CG with the K-cycle (Section 3.1)
     against CG with the V-cycle, both hierarchy precisions, same run."""
@@ -458,7 +518,47 @@ def bench_serve(args):
                 str(max(0, args.count // 10)), "--slots", str(args.slots)])
 
 
-def cpu_baseline(case, gpu_iters):
+def physical_cores():
+    """Physical cores of the host (lscpu's CORE,SOCKET pairs), else None."""
+    import subprocess
+
+    try:
+        out = subprocess.run(["lscpu", "-p=CORE,SOCKET"], capture_output=True, text=True,
+                             timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    pairs = {l for l in out.splitlines() if l and not l.startswith("#")}
+    return len(pairs) or None
+
+
+_NATIVE_TIMING = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import oracle
+from paper_2006_16147_amd import inputs
+case = inputs.headline_case(int(sys.argv[2]), seed=1)
+t0 = time.perf_counter()
+ho = oracle.Hierarchy(case["A"])
+t_setup = time.perf_counter() - t0
+t0 = time.perf_counter()
+x, info = ho.pcg(case["b"], rtol=case["rtol"], maxit=1000)
+t_solve = time.perf_counter() - t0
+print(json.dumps({"setup_ms": t_setup * 1e3, "solve_ms": t_solve * 1e3,
+                  "iterations": info["iterations"], "x_sha": __import__("hashlib").sha256(
+                      x.tobytes()).hexdigest()}))
+"""
+
+
+def cpu_baseline(case, gpu_iters, N):
+    """The FP64 oracle's solve of the same system on the host, serial (one
+    thread): the -O3 -march=native timing build (built here for this host,
+    run in a child process) is the reported value; the -O2 test build is
+    timed beside it in this process and its solution kept for the
+    comparisons. Both builds give the same bits (checked by hash)."""
+    import hashlib
+    import subprocess
+
     import oracle
 
     t0 = time.perf_counter()
@@ -467,15 +567,32 @@ def cpu_baseline(case, gpu_iters):
     t0 = time.perf_counter()
     x, info = ho.pcg(case["b"], rtol=case["rtol"], maxit=1000)
     t_solve = time.perf_counter() - t0
+    native = None
+    try:
+        lib = oracle.build_oracle(native=True)
+        env = dict(os.environ, ORACLE_LIB=lib, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", _NATIVE_TIMING, ROOT, str(N)], env=env,
+                           capture_output=True, text=True, timeout=300)
+        if r.returncode == 0:
+            native = json.loads(r.stdout.strip().splitlines()[-1])
+    except (OSError, subprocess.SubprocessError, ValueError):
+        native = None
+    same = native is not None and native["x_sha"] == hashlib.sha256(x.tobytes()).hexdigest()
+    value = native["solve_ms"] if native and same else t_solve * 1e3
+    build = "gcc -O3 -march=native -ffp-contract=off" if native and same else "gcc -O2"
     return {
-        "value": round(t_solve * 1e3, 1),
+        "value": round(value, 1),
         "unit": "ms",
         "cores": 1,
         "kind": "oracle",
         "sample": ("one complete FP64 oracle PCG solve of the same 160^3 system to rtol 1e-8 "
-                   "(%d iterations; GPU: %d); oracle setup %.0f ms, not included"
-                   % (info["iterations"], gpu_iters, t_setup * 1e3)),
-        "setup_ms": round(t_setup * 1e3, 1),
+                   "(%d iterations; GPU: %d), serial, %s; oracle setup not included"
+                   % (info["iterations"], gpu_iters, build)),
+        "host_physical_cores": physical_cores(),
+        "setup_ms": round(native["setup_ms"] if native and same else t_setup * 1e3, 1),
+        "O2_solve_ms": round(t_solve * 1e3, 1),
+        "O2_setup_ms": round(t_setup * 1e3, 1),
+        "native_bit_identical": same,
         "iterations": info["iterations"],
         "rel_res_true": info["rel_res_true"],
     }, x
@@ -501,7 +618,12 @@ def main():
                     help="short run for rocprofv3 counter collection")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two counter runs")
+    ap.add_argument("--kernel-summary", metavar="KERNEL_TRACE_CSV",
+                    help="print a markdown summary of a rocprofv3 kernel trace")
     args = ap.parse_args()
+    if args.kernel_summary:
+        kernel_summary(args.kernel_summary)
+        return
     if args.ingest_pmc:
         ingest_pmc(*args.ingest_pmc)
         return
@@ -616,33 +738,64 @@ def main():
         log(name, "V-cycle %.3f ms, %.0f GB/s algorithmic (apply call %.3f ms)" % (
             ms, by / ms / 1e6, ms_apply))
 
-    # dominant level-0 kernel of the FP64 solve, timed with HIP events on the
-    # hierarchy's stream
+    # dominant level-0 kernel of the FP64 solve: each of the three level-0
+    # kernels that launch once per iteration timed inside the CG iterations
+    # as the solve runs them (HIP events right before and after its launch on
+    # the hierarchy's stream, as many iterations as the solve takes); the
+    # back-to-back loop of the same kernel is reported beside it
     h = hier["fp64"]
-    kt = {}
+    one_solve(h)  # the in-solve timing starts from this right-hand side
+    iters = res["fp64"]["iterations"]
+    kt, kt_loop = {}, {}
     for k in KERNEL_NAMES:
-        ms, by = h.time_kernel(k, 0, reps=20)
-        kt[k] = (ms, by)
-    per_solve = {k: kt[k][0] for k in (0, 1, 4)}  # each launches once per iteration
-    dom = max(per_solve, key=per_solve.get)
+        kt_loop[k] = h.time_kernel(k, 0, reps=20)
+        if k != 2:
+            kt[k] = h.time_kernel(k | amg.TIME_IN_SOLVE, 0, reps=iters)
+    dom = max(kt, key=lambda k: kt[k][0])
     ms, by = kt[dom]
     achieved = by / ms / 1e6
     traffic = load_traffic("fp64_level0_%d" % dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": KERNEL_NAMES[dom] + " (level 0, FP64)",
-                "kernel_ms": round(ms, 4), "algorithmic_bytes": by}
-    res["level0_kernels"] = {KERNEL_NAMES[k]: {"ms": round(v[0], 4),
-                                               "GB/s": round(v[1] / v[0] / 1e6, 1)}
-                             for k, v in kt.items()}
+                "kernel_ms": round(ms, 4), "kernel_ms_timing": "in solve, %d iterations" % iters,
+                "kernel_ms_back_to_back": round(kt_loop[dom][0], 4), "algorithmic_bytes": by}
+    res["level0_kernels"] = {KERNEL_NAMES[k]: {
+        "ms_in_solve": round(kt[k][0], 4) if k in kt else None,
+        "GB/s_in_solve": round(kt[k][1] / kt[k][0] / 1e6, 1) if k in kt else None,
+        "ms_back_to_back": round(v[0], 4), "GB/s_back_to_back": round(v[1] / v[0] / 1e6, 1)}
+        for k, v in kt_loop.items()}
     log("dominant kernel:", roofline)
+
+    # the FP64 hierarchy without the exact FP32 copy of level 0's values
+    # (AMG_FLAG_NO_VALUE_COMPRESSION): same bits, FP64 value traffic
+    hn = amg.amg_setup(rp, ci, va, precision=amg.FP64, flags=amg.FLAG_NO_VALUE_COMPRESSION)
+    for _ in range(args.warmup):
+        one_solve(hn)
+    times = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        info = one_solve(hn)
+        times.append((time.perf_counter() - t0) * 1e3)
+    res["fp64_fp64_values_level0"] = {"p50_ms": round(percentile(times, 50), 3),
+                                      "p99_ms": round(percentile(times, 99), 3),
+                                      "iterations": info["iterations"],
+                                      "same_solution": bool(np.array_equal(
+                                          x.cpu().numpy(), res["fp64"]["_x"]))}
+    hn.close()
+    log("fp64 without the FP32 copy of A_0:", res["fp64_fp64_values_level0"])
 
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
-        cpu, xo = cpu_baseline(case, res["fp64"]["iterations"])
-        xg = res["fp64"]["_x"]
-        res["fp64"]["rel_diff_vs_oracle"] = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+        cpu, xo = cpu_baseline(case, res["fp64"]["iterations"], args.N)
+        for name in ("fp64", "fp32_prec"):
+            xg = res[name]["_x"]
+            res[name]["rel_diff_vs_oracle"] = float(np.linalg.norm(xg - xo) /
+                                                    np.linalg.norm(xo))
+        res["fp32_prec"]["rel_diff_vs_oracle_note"] = (
+            "FP32 hierarchy and V-cycle, FP64 CG, against the FP64 oracle's solution of the "
+            "same system to the same rtol")
         log("cpu baseline:", cpu)
     for name in ("fp64", "fp32_prec"):
         res[name].pop("_x", None)
@@ -662,12 +815,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": "poisson7_%d^3_b=Au_seed1_rtol1e-8" % args.N, "n": A.n,
                    "nnz": A.nnz, "rtol": rtol,
-                   "hierarchy": "matching, 3 sweeps, w=1, l1-Jacobi 1+1, dense Cholesky <=200"},
+                   "hierarchy": "matching, 3 sweeps, w=1, l1-Jacobi 1+1, dense Cholesky <=200",
+                   "level0_values": ("FP64 products of level 0 read A from an exact FP32 "
+                                     "copy (every value of this A is an FP32 number; same "
+                                     "bits): see fp64_fp64_values_level0 for the solve "
+                                     "without it")},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64": res["fp64"],
         "fp32_prec": res["fp32_prec"],
         "fp32_prec_speedup_p50": round(res["fp64"]["p50_ms"] / res["fp32_prec"]["p50_ms"], 3),
+        "fp64_fp64_values_level0": res["fp64_fp64_values_level0"],
         "level0_kernels": res["level0_kernels"],
         "source_hash": source_hash(),
     }

@@ -25,15 +25,23 @@
  * and the library reproduces it bit for bit on every run.
  *
  * Conventions shared by every entry point:
+ *   - A hierarchy lives on one device: amg_params.device, or the current
+ *     device (hipGetDevice) at amg_setup when that is -1. Every call on it
+ *     works on that device and leaves the caller's current device as it was.
  *   - All array arguments named "device" are HIP device pointers on the
- *     current device (hipGetDevice at the time of the call); arrays named
- *     "host" are host pointers. The library never takes ownership of caller
- *     arrays; it owns only what it allocates inside a hierarchy.
+ *     hierarchy's device (amg_setup: on the device it builds on); a pointer
+ *     the runtime reports on another device, or not as device memory, is
+ *     rejected with AMG_ERR_ARG, and so is one whose allocation ends before
+ *     the extent the call reads or writes. Arrays named "host" are host
+ *     pointers. The library never takes ownership of caller arrays; it owns
+ *     only what it allocates inside a hierarchy.
  *   - Indices are 0-based int32. CSR rows hold strictly ascending columns,
  *     the diagonal is stored and positive, and A is bitwise symmetric.
- *   - Calls are ordered on the hierarchy's stream (amg_params.stream; NULL
- *     is the device's default stream). Every call returns after its results
- *     are complete on the device.
+ *   - Calls are ordered after the work already queued on the hierarchy's
+ *     caller stream (amg_params.stream, or amg_set_stream; NULL is the
+ *     device's default stream). Every call returns after its results are
+ *     complete on the device, except the solves of a hierarchy built with
+ *     AMG_ASYNC (see amg_wait).
  *   - One hierarchy is used by one host thread at a time. Distinct
  *     hierarchies may be used concurrently from different threads.
  *   - No call aborts or throws; failures return a status code and leave the
@@ -94,7 +102,15 @@ enum {
    * an FP32 number, the FP64 products of level 0 (outer CG SpMV, level-0
    * post-smoothing) read an FP32 copy of A: the same numbers, half the value
    * bytes, bit-identical results. */
-  AMG_FLAG_NO_VALUE_COMPRESSION = 4
+  AMG_FLAG_NO_VALUE_COMPRESSION = 4,
+  /* non-blocking solves: amg_pcg_solve and amg_pcg_solve_batch check their
+   * arguments, order the solve after the caller stream's queued work and
+   * return AMG_OK at once; the solve itself (its kernels and its host-side
+   * convergence checks) proceeds on a host thread of the hierarchy. b, x, B,
+   * X and info must stay valid, and x / X unread, until amg_wait returns the
+   * solve's status (info written by then). amg_query tests for completion.
+   * Any other call on the hierarchy first waits for the solve in flight. */
+  AMG_ASYNC = 8
 };
 
 /* Largest coarsest level the dense Cholesky accepts (AMG_ERR_STALL above). */
@@ -120,7 +136,9 @@ typedef struct {
                          no zero entry; NULL = ones */
   void *stream;       /* hipStream_t for every call on this hierarchy; NULL = the
                          device's default stream */
-  int32_t flags;      /* AMG_FLAG_* */
+  int32_t device;     /* HIP device ordinal the hierarchy lives on; -1 = the current
+                         device at amg_setup. -1 */
+  int32_t flags;      /* AMG_FLAG_* and AMG_ASYNC */
   int32_t cycle;      /* AMG_CYCLE_V or AMG_CYCLE_K; AMG_CYCLE_V */
   int32_t w_sweeps;   /* smooth vector: w = (I - M^-1 A)^w_sweeps w0, with M the l1-Jacobi
                          diagonal of A and w0 = w (NULL: ones), i.e. w_sweeps iterations of
@@ -132,7 +150,10 @@ typedef struct {
                             coarse_maxit iterations); 1e-4 (Section 5) */
   int32_t smooth_p;      /* 1: smoothed aggregation (the alternative to the K-cycle in
                             Section 3.2): the next level is Pbar^T A Pbar with
-                            Pbar = (I - omega D^-1 A) P, omega = 1 / ||D^-1 A||_inf,
+                            Pbar = (I - omega D^-1 A) P, omega = 4 / (3 ||D^-1 A||_inf)
+                            (the damping 4 / (3 rho(D^-1 A)), rho estimated by the
+                            infinity norm: the value that reproduces the supplement's
+                            convergence constant K of the smoothed prolongator),
                             D = diag(A), P the tentative prolongator of the matching
                             sweeps (which still chooses the aggregates and restricts w);
                             the V-cycle restricts with Pbar^T and prolongates with Pbar.
@@ -144,11 +165,12 @@ typedef struct {
 } amg_params;
 
 typedef struct {
-  int32_t iterations;  /* CG iterations performed */
-  int32_t converged;   /* 1 if ||r_k||_2 <= rtol ||b||_2 */
-  double rel_res;      /* recursive residual ||r_k|| / ||b|| */
-  double rel_res_true; /* ||b - A x|| / ||b|| recomputed at exit */
-  double ms;           /* wall time of the call */
+  int32_t iterations;       /* CG iterations performed */
+  double rel_res_recursive; /* ||r_k|| / ||b|| of the CG recurrence at exit */
+  double rel_res_true;      /* ||b - A x|| / ||b|| recomputed at exit */
+  int32_t converged;        /* 1 if ||r_k||_2 <= rtol ||b||_2 */
+  double ms;                /* wall time of the solve (AMG_ASYNC: from the call to the
+                               end of the solve, not to amg_wait) */
 } amg_solve_info;
 
 /* Fills the defaults listed beside each field above. */
@@ -196,6 +218,16 @@ amg_status amg_pcg_solve_batch(amg_hierarchy *h, int32_t k, const double *B, dou
  * r, z: device, n. */
 amg_status amg_vcycle_apply(amg_hierarchy *h, const double *r, double *z);
 
+/* Waits for the solve in flight on a hierarchy built with AMG_ASYNC and
+ * returns its status: what the blocking call would have returned (AMG_OK,
+ * AMG_NOT_CONVERGED, AMG_ERR_BREAKDOWN, ...); its info is written by then.
+ * AMG_OK at once when no solve is in flight; AMG_ERR_ARG for h = NULL. */
+amg_status amg_wait(amg_hierarchy *h);
+
+/* Non-blocking completion test: *done = 1 when no solve is in flight or the
+ * one in flight has finished (amg_wait then returns without waiting), else 0. */
+amg_status amg_query(amg_hierarchy *h, int32_t *done);
+
 /* Rebinds the hierarchy to another caller stream (hipStream_t, NULL = the
  * device's default stream): later calls are ordered after the work queued
  * on it. Lets a serving loop reuse a cached hierarchy from any slot. */
@@ -212,6 +244,11 @@ amg_status amg_level_info(const amg_hierarchy *h, int32_t l, int64_t *n, int64_t
 /* Copies level l's CSR (FP64 values) to host arrays of n + 1, nnz, nnz. */
 amg_status amg_get_level_csr(const amg_hierarchy *h, int32_t l, int32_t *row_ptr_host,
                              int32_t *col_host, double *val_host);
+/* Copies the aggregate map of level l (l < nlev - 1) to a host array of n_l:
+ * agg_host[i] is the level-(l+1) unknown that fine unknown i belongs to, the
+ * composition of the `sweeps` pairwise matchings of Section 3.2; aggregates
+ * are numbered by their smallest member. */
+amg_status amg_get_aggregates(const amg_hierarchy *h, int32_t l, int32_t *agg_host);
 /* Copies the composed aggregate map and prolongator values of level l
  * (l < nlev - 1): agg_host[i] is the level-(l+1) index of fine row i and
  * p_host[i] the entry P_l(i, agg_host[i]). Either pointer may be NULL. */
@@ -253,7 +290,17 @@ amg_status amg_matching_rounds(const amg_hierarchy *h, int32_t l, int32_t *round
  * 5 = one whole V-cycle as inside the solve (level ignored; *bytes its
  *     algorithmic total, without the coarsest solve when it is the
  *     iterative one, whose L2-resident traffic depends on its iteration
- *     count; AMG_ERR_ARG for a K-cycle hierarchy). */
+ *     count; AMG_ERR_ARG for a K-cycle hierarchy).
+ * kernel | AMG_TIME_IN_SOLVE, for kernels 0, 1 and 4 on level 0: the kernel
+ * timed where the solve runs it, inside `reps` (1..10000) CG iterations
+ * from x = 0 on the right-hand side of the last amg_pcg_solve (launched
+ * without the graph, rtol 0, so every launch does its full work); *ms is
+ * the mean of its dispatches' own start-to-end times, which the runtime
+ * stamps into events given to the launch (hipExtLaunchKernelGGL), as a
+ * profiler's kernel trace measures them. AMG_ERR_ARG before any solve, and
+ * for a hierarchy with the K-cycle, the iterative coarsest solve, smoothed
+ * prolongators, or more than one pre- or post-sweep. */
+#define AMG_TIME_IN_SOLVE 16
 amg_status amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
                            double *ms, double *bytes);
 

@@ -52,16 +52,26 @@ class Status:
     NOT_CONVERGED = 8
 
 
-def build_oracle(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (strict IEEE: no FP contraction)."""
-    if not force and os.path.exists(_LIB_PATH):
-        return _LIB_PATH
-    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+NATIVE_LIB_PATH = os.path.join(_HERE, "liboracle_native.so")
+
+
+def build_oracle(force: bool = True, native: bool = False) -> str:
+    """Compile liboracle.so with gcc (strict IEEE: no FP contraction).
+
+    native=True compiles the copy used to time the oracle on a host,
+    liboracle_native.so, with -O3 -march=native for that host's CPU. It keeps
+    -ffp-contract=off and no fast-math, so no operation is fused or
+    reassociated and its results are the same bits (a test checks this)."""
+    path = NATIVE_LIB_PATH if native else _LIB_PATH
+    if not force and os.path.exists(path):
+        return path
+    tmp = path + ".tmp%d" % os.getpid()
+    opt = ["-O3", "-march=native"] if native else ["-O2"]
+    cmd = ["gcc", *opt, "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
            "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True, cwd=_HERE)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    os.replace(tmp, path)
+    return path
 
 
 class _Csr(C.Structure):

@@ -18,14 +18,15 @@ __all__ = [
     "lib_path", "load_library", "Params", "SolveInfo", "Hierarchy",
     "amg_params_default", "amg_setup", "amg_pcg_solve", "amg_pcg_solve_batch",
     "amg_vcycle_apply", "amg_free", "amg_estimate_footprint", "amg_status_string",
-    "EXPORTED_SYMBOLS",
+    "amg_wait", "amg_query", "FLAG_ASYNC", "EXPORTED_SYMBOLS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 FP64, FP32 = 0, 1
 CYCLE_V, CYCLE_K = 0, 1
 COARSE_CHOLESKY, COARSE_PCG = 0, 1
-FLAG_NO_GRAPH, FLAG_SKIP_CHECKS, FLAG_NO_VALUE_COMPRESSION = 1, 2, 4
+FLAG_NO_GRAPH, FLAG_SKIP_CHECKS, FLAG_NO_VALUE_COMPRESSION, FLAG_ASYNC = 1, 2, 4, 8
+TIME_IN_SOLVE = 16  # amg_time_kernel: time the kernel inside the CG iterations
 MAX_DENSE = 4096
 
 EXPORTED_SYMBOLS = (
@@ -33,7 +34,8 @@ EXPORTED_SYMBOLS = (
     "amg_vcycle_apply", "amg_set_stream", "amg_free", "amg_num_levels", "amg_level_info", "amg_get_level_csr",
     "amg_get_transfer", "amg_get_l1diag", "amg_get_w", "amg_footprint_bytes",
     "amg_estimate_footprint", "amg_setup_times", "amg_matching_rounds", "amg_time_kernel",
-    "amg_batch_tile", "amg_status_string", "amg_get_prolongator",
+    "amg_batch_tile", "amg_status_string", "amg_get_prolongator", "amg_get_aggregates",
+    "amg_wait", "amg_query",
 )
 
 
@@ -64,20 +66,21 @@ class Csr(C.Structure):
 class Params(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("max_coarse", C.c_int32), ("max_levels", C.c_int32),
                 ("pre", C.c_int32), ("post", C.c_int32), ("precision", C.c_int32),
-                ("w", C.c_void_p), ("stream", C.c_void_p), ("flags", C.c_int32),
+                ("w", C.c_void_p), ("stream", C.c_void_p), ("device", C.c_int32),
+                ("flags", C.c_int32),
                 ("cycle", C.c_int32), ("w_sweeps", C.c_int32), ("coarse_solver", C.c_int32),
                 ("coarse_maxit", C.c_int32), ("coarse_rtol", C.c_double),
                 ("smooth_p", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
-    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("rel_res", C.c_double),
-                ("rel_res_true", C.c_double), ("ms", C.c_double)]
+    _fields_ = [("iterations", C.c_int32), ("rel_res_recursive", C.c_double),
+                ("rel_res_true", C.c_double), ("converged", C.c_int32), ("ms", C.c_double)]
 
     def as_dict(self):
         return {"iterations": int(self.iterations), "converged": bool(self.converged),
-                "rel_res": float(self.rel_res), "rel_res_true": float(self.rel_res_true),
-                "ms": float(self.ms)}
+                "rel_res_recursive": float(self.rel_res_recursive),
+                "rel_res_true": float(self.rel_res_true), "ms": float(self.ms)}
 
 
 _lib = None
@@ -105,6 +108,9 @@ def load_library():
         "amg_pcg_solve_batch": (C.c_int, [V, I32, V, V, D, I32, P(SolveInfo)]),
         "amg_vcycle_apply": (C.c_int, [V, V, V]),
         "amg_set_stream": (C.c_int, [V, V]),
+        "amg_wait": (C.c_int, [V]),
+        "amg_query": (C.c_int, [V, P(I32)]),
+        "amg_get_aggregates": (C.c_int, [V, I32, V]),
         "amg_free": (None, [V]),
         "amg_num_levels": (C.c_int, [V, P(I32)]),
         "amg_level_info": (C.c_int, [V, I32, P(I64), P(I64)]),
@@ -170,9 +176,12 @@ def amg_estimate_footprint(n: int, nnz: int, params: Params | None = None) -> in
 class Hierarchy:
     """Owner of an amg_hierarchy handle (amg_free on close/deletion)."""
 
-    def __init__(self, handle, n):
+    def __init__(self, handle, n, device=0, is_async=False):
         self._h = C.c_void_p(handle)
         self.n = int(n)
+        self.device = int(device)
+        self.is_async = bool(is_async)
+        self._pending = None  # (info, keep-alive references) of an AMG_ASYNC solve
 
     @property
     def handle(self):
@@ -180,8 +189,9 @@ class Hierarchy:
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
-            load_library().amg_free(self._h)
+            load_library().amg_free(self._h)  # waits for a solve in flight
             self._h = C.c_void_p(0)
+            self._pending = None
 
     def __del__(self):
         try:
@@ -224,6 +234,13 @@ class Hierarchy:
                                                      ci.ctypes.data, val.ctypes.data),
                     "amg_get_level_csr")
         return rp, ci, val
+
+    def aggregates(self, l):
+        n, _ = self.level_info(l)
+        agg = np.empty(n, dtype=np.int32)
+        self._check(load_library().amg_get_aggregates(self._h, l, agg.ctypes.data),
+                    "amg_get_aggregates")
+        return agg
 
     def transfer(self, l):
         n, _ = self.level_info(l)
@@ -307,17 +324,34 @@ def amg_setup(row_ptr, col, val, params: Params | None = None, **kw) -> Hierarch
     st = load_library().amg_setup(C.byref(A), C.byref(p), C.byref(out))
     if st != Status.OK:
         raise AmgError(st, "amg_setup")
-    return Hierarchy(out.value, n)
+    device = p.device if p.device >= 0 else torch.cuda.current_device()
+    return Hierarchy(out.value, n, device, bool(p.flags & FLAG_ASYNC))
+
+
+def _check_vectors(h: Hierarchy, shape, **tensors):
+    """Rejects, before any launch, tensors whose shape or device does not
+    match the hierarchy (the library would read or write past them)."""
+    for name, t in tensors.items():
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError("%s has shape %s, the hierarchy needs %s"
+                             % (name, tuple(t.shape), tuple(shape)))
+        if t.is_cuda and t.device.index != h.device:
+            raise ValueError("%s is on cuda:%s, the hierarchy on cuda:%d"
+                             % (name, t.device.index, h.device))
 
 
 def amg_pcg_solve(h: Hierarchy, b, x, rtol=1e-8, maxit=1000, raise_on_error=True):
     """Solves into x (torch float64 on the GPU, in: x0); returns (status, info)."""
     import torch
 
+    _check_vectors(h, (h.n,), b=b, x=x)
     info = SolveInfo()
     st = load_library().amg_pcg_solve(h.handle, _ptr(b, torch.float64, "b"),
                                       _ptr(x, torch.float64, "x"), float(rtol), int(maxit),
                                       C.byref(info))
+    if h.is_async and st == Status.OK:
+        h._pending = (lambda: info.as_dict(), (info, b, x))
+        return st, None  # amg_wait(h) gives the status and info
     if raise_on_error and st not in (Status.OK, Status.NOT_CONVERGED):
         raise AmgError(st, "amg_pcg_solve")
     return st, info.as_dict()
@@ -327,19 +361,45 @@ def amg_pcg_solve_batch(h: Hierarchy, B, X, rtol=1e-8, maxit=1000, raise_on_erro
     """Solves the k columns of the n x k row-major blocks B, X; returns (status, [info])."""
     import torch
 
-    k = B.shape[1] if B.dim() == 2 else 1
+    if B.dim() != 2:
+        raise ValueError("B must be a 2-D n x k tensor, got shape %s" % (tuple(B.shape),))
+    k = B.shape[1]
+    _check_vectors(h, (h.n, k), B=B, X=X)
     infos = (SolveInfo * max(k, 1))()
     st = load_library().amg_pcg_solve_batch(h.handle, k, _ptr(B, torch.float64, "B"),
                                             _ptr(X, torch.float64, "X"), float(rtol), int(maxit),
                                             infos)
+    if h.is_async and st == Status.OK and k > 0:
+        h._pending = (lambda: [infos[j].as_dict() for j in range(k)], (infos, B, X))
+        return st, None  # amg_wait(h) gives the status and the infos
     if raise_on_error and st not in (Status.OK, Status.NOT_CONVERGED):
         raise AmgError(st, "amg_pcg_solve_batch")
     return st, [infos[j].as_dict() for j in range(k)]
 
 
+def amg_wait(h: Hierarchy, raise_on_error=True):
+    """Waits for the AMG_ASYNC solve in flight on h; returns (status, info)
+    as the blocking call would have (info None when nothing was in flight)."""
+    st = load_library().amg_wait(h.handle)
+    pending, h._pending = h._pending, None
+    if raise_on_error and st not in (Status.OK, Status.NOT_CONVERGED):
+        raise AmgError(st, "amg_wait")
+    return st, (pending[0]() if pending else None)
+
+
+def amg_query(h: Hierarchy) -> bool:
+    """True when no AMG_ASYNC solve is in flight on h or it has finished."""
+    done = C.c_int32()
+    st = load_library().amg_query(h.handle, C.byref(done))
+    if st != Status.OK:
+        raise AmgError(st, "amg_query")
+    return bool(done.value)
+
+
 def amg_vcycle_apply(h: Hierarchy, r, z):
     import torch
 
+    _check_vectors(h, (h.n,), r=r, z=z)
     st = load_library().amg_vcycle_apply(h.handle, _ptr(r, torch.float64, "r"),
                                          _ptr(z, torch.float64, "z"))
     if st != Status.OK:

@@ -6,6 +6,8 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <system_error>
+#include <thread>
 
 #include "internal.h"
 
@@ -102,8 +104,59 @@ double now_ms() {
       .count();
 }
 
+// Makes `device` current for the guard's lifetime and then restores the
+// caller's current device.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int device) {
+    if (hipGetDevice(&prev) != hipSuccess) {
+      (void)hipGetLastError();
+      prev = -1;
+      return;
+    }
+    ok = prev == device || hipSetDevice(device) == hipSuccess;
+    if (!ok) (void)hipGetLastError();
+  }
+  ~DeviceGuard() {
+    if (ok && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// Joins the solve in flight (AMG_ASYNC); its status stays in async_status
+// for amg_wait.
+void join_async(const amg_hierarchy *hc) {
+  amg_hierarchy *h = const_cast<amg_hierarchy *>(hc);
+  if (h->async_pending) {
+    if (h->worker.joinable()) h->worker.join();
+    h->async_pending = false;
+  }
+}
+
+// True when p is device memory on `device` and, where the runtime reports
+// the allocation's range, [p, p + bytes) lies inside it.
+bool device_range(const void *p, size_t bytes, int device) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged) return false;
+  if (a.device != device) return false;
+  void *base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void *>(p)) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;  // range unknown to the runtime: nothing more to check
+  }
+  const uintptr_t lo = reinterpret_cast<uintptr_t>(base), q = reinterpret_cast<uintptr_t>(p);
+  return q >= lo && bytes <= size - (q - lo);
+}
+
 void destroy(amg_hierarchy *h) {
   if (!h) return;
+  join_async(h);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   if (h->iter_exec) (void)hipGraphExecDestroy(h->iter_exec);
   if (h->iter_graph) (void)hipGraphDestroy(h->iter_graph);
@@ -129,6 +182,10 @@ amg_status check_params(const amg_params *p) {
   if (p->coarse_solver != AMG_COARSE_CHOLESKY && p->coarse_solver != AMG_COARSE_PCG)
     return AMG_ERR_ARG;
   if (p->smooth_p != 0 && p->smooth_p != 1) return AMG_ERR_ARG;
+  if (p->device < -1) return AMG_ERR_ARG;
+  if (p->flags & ~(AMG_FLAG_NO_GRAPH | AMG_FLAG_SKIP_CHECKS | AMG_FLAG_NO_VALUE_COMPRESSION |
+                   AMG_ASYNC))
+    return AMG_ERR_ARG;
   if (p->smooth_p && p->cycle != AMG_CYCLE_V) return AMG_ERR_ARG;
   if (p->coarse_solver == AMG_COARSE_PCG &&
       (p->coarse_maxit < 1 || p->coarse_maxit > 10000 || !(p->coarse_rtol >= 0.0) ||
@@ -137,14 +194,23 @@ amg_status check_params(const amg_params *p) {
   return AMG_OK;
 }
 
-bool on_device(const void *p) {
-  if (!p) return false;
-  hipPointerAttribute_t a;
-  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
+// Starts `solve` on the hierarchy's worker thread (AMG_ASYNC) or runs it.
+template <typename F>
+amg_status run_solve(amg_hierarchy *h, F solve) {
+  if (!(h->params.flags & AMG_ASYNC)) return solve();
+  h->async_status = AMG_OK;
+  h->async_finished.store(0);
+  try {
+    h->worker = std::thread([h, solve]() {
+      amg_status st = hipSetDevice(h->device) == hipSuccess ? solve() : AMG_ERR_HIP;
+      h->async_status = st;
+      h->async_finished.store(1);
+    });
+  } catch (const std::system_error &) {
+    return AMG_ERR_HIP;
   }
-  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+  h->async_pending = true;
+  return AMG_OK;
 }
 
 }  // namespace
@@ -168,6 +234,7 @@ void amg_params_default(amg_params *p) {
   p->coarse_maxit = 30;
   p->coarse_rtol = 1e-4;
   p->smooth_p = 0;
+  p->device = -1;
 }
 
 amg_status amg_setup(const amg_csr *A, const amg_params *params, amg_hierarchy **out) {
@@ -175,20 +242,31 @@ amg_status amg_setup(const amg_csr *A, const amg_params *params, amg_hierarchy *
   *out = nullptr;
   if (!A || A->n < 1 || A->n > INT32_MAX - 1 || A->nnz < A->n || A->nnz > INT32_MAX)
     return AMG_ERR_ARG;
-  if (!on_device(A->row_ptr) || !on_device(A->col) || !on_device(A->val)) return AMG_ERR_ARG;
   amg_params P;
   if (params) P = *params;
   else amg_params_default(&P);
   AMG_TRY(check_params(&P));
-  if (P.w && !on_device(P.w)) return AMG_ERR_ARG;
+  int device = P.device;
+  if (device < 0) {
+    if (hipGetDevice(&device) != hipSuccess) return AMG_ERR_HIP;
+  } else {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess) return AMG_ERR_HIP;
+    if (device >= count) return AMG_ERR_ARG;
+  }
+  DeviceGuard guard(device);
+  if (!guard.ok) return AMG_ERR_HIP;
+  const size_t n1 = (size_t)A->n + 1, nz = (size_t)A->nnz;
+  if (!device_range(A->row_ptr, 4 * n1, device) || !device_range(A->col, 4 * nz, device) ||
+      !device_range(A->val, 8 * nz, device))
+    return AMG_ERR_ARG;
+  if (P.w && !device_range(P.w, 8 * (size_t)A->n, device)) return AMG_ERR_ARG;
   amg_hierarchy *h = new (std::nothrow) amg_hierarchy();
   if (!h) return AMG_ERR_OOM;
   h->params = P;
   h->params.w = nullptr;  // not retained after setup
-  if (hipGetDevice(&h->device) != hipSuccess) {
-    delete h;
-    return AMG_ERR_HIP;
-  }
+  h->params.device = device;
+  h->device = device;
   // all work runs on the library's own stream (default priority), ordered
   // after the caller's stream (NULL: the device's default stream) at every
   // entry point; every entry point returns after its work has completed
@@ -219,9 +297,14 @@ amg_status amg_setup(const amg_csr *A, const amg_params *params, amg_hierarchy *
 amg_status amg_pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol,
                          int32_t maxit, amg_solve_info *info) {
   if (!h || !b || !x || !(rtol >= 0.0) || maxit < 0) return AMG_ERR_ARG;
-  if (hipSetDevice(h->device) != hipSuccess) return AMG_ERR_HIP;
+  join_async(h);
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return AMG_ERR_HIP;
+  const size_t bytes = sizeof(double) * (size_t)h->lv[0].n;
+  if (!device_range(b, bytes, h->device) || !device_range(x, bytes, h->device))
+    return AMG_ERR_ARG;
   AMG_TRY(join_user_stream(h));
-  return pcg(h, b, x, rtol, maxit, info);
+  return run_solve(h, [=]() { return pcg(h, b, x, rtol, maxit, info); });
 }
 
 amg_status amg_pcg_solve_batch(amg_hierarchy *h, int32_t k, const double *B, double *X,
@@ -232,14 +315,38 @@ amg_status amg_pcg_solve_batch(amg_hierarchy *h, int32_t k, const double *B, dou
     return AMG_ERR_ARG;
   if (k == 0) return AMG_OK;
   if (!B || !X) return AMG_ERR_ARG;
-  if (hipSetDevice(h->device) != hipSuccess) return AMG_ERR_HIP;
+  join_async(h);
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return AMG_ERR_HIP;
+  const size_t bytes = sizeof(double) * (size_t)h->lv[0].n * (size_t)k;
+  if (!device_range(B, bytes, h->device) || !device_range(X, bytes, h->device))
+    return AMG_ERR_ARG;
   AMG_TRY(join_user_stream(h));
-  return pcg_batch(h, k, B, X, rtol, maxit, info);
+  return run_solve(h, [=]() { return pcg_batch(h, k, B, X, rtol, maxit, info); });
+}
+
+amg_status amg_wait(amg_hierarchy *h) {
+  if (!h) return AMG_ERR_ARG;
+  join_async(h);
+  const amg_status st = h->async_status;
+  h->async_status = AMG_OK;
+  return st;
+}
+
+amg_status amg_query(amg_hierarchy *h, int32_t *done) {
+  if (!h || !done) return AMG_ERR_ARG;
+  *done = !h->async_pending || h->async_finished.load() ? 1 : 0;
+  return AMG_OK;
 }
 
 amg_status amg_vcycle_apply(amg_hierarchy *h, const double *r, double *z) {
   if (!h || !r || !z) return AMG_ERR_ARG;
-  if (hipSetDevice(h->device) != hipSuccess) return AMG_ERR_HIP;
+  join_async(h);
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return AMG_ERR_HIP;
+  const size_t bytes = sizeof(double) * (size_t)h->lv[0].n;
+  if (!device_range(r, bytes, h->device) || !device_range(z, bytes, h->device))
+    return AMG_ERR_ARG;
   AMG_TRY(join_user_stream(h));
   AMG_TRY(vcycle(h, r, z, false, h->zero_flag));
   AMG_HIP(hipStreamSynchronize(h->stream));
@@ -248,11 +355,16 @@ amg_status amg_vcycle_apply(amg_hierarchy *h, const double *r, double *z) {
 
 amg_status amg_set_stream(amg_hierarchy *h, void *stream) {
   if (!h) return AMG_ERR_ARG;
+  join_async(h);
   h->user_stream = reinterpret_cast<hipStream_t>(stream);
   return AMG_OK;
 }
 
-void amg_free(amg_hierarchy *h) { destroy(h); }
+void amg_free(amg_hierarchy *h) {
+  if (!h) return;
+  DeviceGuard guard(h->device);
+  destroy(h);
+}
 
 amg_status amg_num_levels(const amg_hierarchy *h, int32_t *nlev) {
   if (!h || !nlev) return AMG_ERR_ARG;
@@ -269,7 +381,11 @@ amg_status amg_level_info(const amg_hierarchy *h, int32_t l, int64_t *n, int64_t
 
 namespace {
 // device-to-host copy ordered after all of the hierarchy's queued work
+// (a solve in flight included)
 amg_status d2h(const amg_hierarchy *h, void *dst, const void *src, size_t bytes) {
+  join_async(h);
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return AMG_ERR_HIP;
   AMG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
   AMG_HIP(hipStreamSynchronize(h->stream));
   return AMG_OK;
@@ -284,6 +400,11 @@ amg_status amg_get_level_csr(const amg_hierarchy *h, int32_t l, int32_t *rp, int
   if (ci) AMG_TRY(d2h(h, ci, L.ci, sizeof(int32_t) * L.nnz));
   if (val) AMG_TRY(d2h(h, val, L.val, sizeof(double) * L.nnz));
   return AMG_OK;
+}
+
+amg_status amg_get_aggregates(const amg_hierarchy *h, int32_t l, int32_t *agg) {
+  if (!h || !agg || l < 0 || l + 1 >= (int32_t)h->lv.size()) return AMG_ERR_ARG;
+  return d2h(h, agg, h->lv[l].agg, sizeof(int32_t) * h->lv[l].n);
 }
 
 amg_status amg_get_transfer(const amg_hierarchy *h, int32_t l, int32_t *agg, double *p) {
@@ -323,7 +444,9 @@ amg_status amg_get_w(const amg_hierarchy *h, int32_t l, double *w) {
 }
 
 size_t amg_footprint_bytes(const amg_hierarchy *h) {
-  return h ? h->bytes + h->batch_bytes : 0;
+  if (!h) return 0;
+  join_async(h);
+  return h->bytes + h->batch_bytes;
 }
 
 size_t amg_estimate_footprint(int64_t n, int64_t nnz, const amg_params *params) {
@@ -362,6 +485,7 @@ size_t amg_estimate_footprint(int64_t n, int64_t nnz, const amg_params *params) 
 
 amg_status amg_setup_times(const amg_hierarchy *h, double *ms) {
   if (!h || !ms) return AMG_ERR_ARG;
+  join_async(h);
   for (int k = 0; k < 8; ++k) ms[k] = h->setup_ms[k];
   return AMG_OK;
 }
@@ -374,14 +498,18 @@ amg_status amg_matching_rounds(const amg_hierarchy *h, int32_t l, int32_t *round
 
 amg_status amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
                            double *ms, double *bytes) {
-  if (!h || !ms || !bytes || kernel < 0 || kernel > 5) return AMG_ERR_ARG;
-  if (hipSetDevice(h->device) != hipSuccess) return AMG_ERR_HIP;
+  const int32_t base = kernel & ~AMG_TIME_IN_SOLVE;
+  if (!h || !ms || !bytes || kernel < 0 || base > 5) return AMG_ERR_ARG;
+  join_async(h);
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return AMG_ERR_HIP;
   AMG_TRY(join_user_stream(h));
   return time_kernel(h, kernel, level, reps, ms, bytes);
 }
 
 amg_status amg_batch_tile(const amg_hierarchy *h, int32_t *kt) {
   if (!h || !kt) return AMG_ERR_ARG;
+  join_async(h);
   return batch_kt(h, kt);
 }
 

@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdint>
+#include <new>
 #include <type_traits>
 
 #include "internal.h"
@@ -1323,16 +1324,10 @@ amg_status balloc(amg_hierarchy *h, void **p, size_t bytes) {
   return AMG_OK;
 }
 
-amg_status ensure_batch(amg_hierarchy *h, int32_t k) {
-  if (h->batch && h->batch->k == k) return AMG_OK;
-  if (h->batch) {
-    free_batch(h->batch, h->device, h->stream);
-    h->batch = nullptr;
-    h->batch_bytes = 0;
-  }
-  h->batch = new Batch();
+// Allocates every buffer of a batch of k columns into h->batch (whose k is
+// still 0: a batch is marked usable only once all of them exist).
+amg_status alloc_batch(amg_hierarchy *h, int32_t k) {
   Batch &B = *h->batch;
-  B.k = k;
   const bool fp32 = h->params.precision == AMG_FP32;
   const size_t V = fp32 ? 4 : 8;
   const int32_t nlev = (int32_t)h->lv.size();
@@ -1364,7 +1359,30 @@ amg_status ensure_batch(amg_hierarchy *h, int32_t k) {
   AMG_HIP(hipHostMalloc((void **)&B.iter_host, sizeof(int32_t) * (size_t)k));
   AMG_HIP(hipHostMalloc((void **)&B.done_host, sizeof(int32_t) * (size_t)k));
   AMG_HIP(hipMemsetAsync(B.all_done, 0, sizeof(int32_t) * 4, h->stream));
-  h->batch_bytes = B.bytes;
+  return AMG_OK;
+}
+
+// The batch state for k columns, reallocated when k changes. On any failure
+// the partial batch is released and h->batch left null, so a later call
+// allocates afresh instead of launching on missing buffers.
+amg_status ensure_batch(amg_hierarchy *h, int32_t k) {
+  if (h->batch && h->batch->k == k) return AMG_OK;
+  if (h->batch) {
+    free_batch(h->batch, h->device, h->stream);
+    h->batch = nullptr;
+    h->batch_bytes = 0;
+  }
+  h->batch = new (std::nothrow) Batch();
+  if (!h->batch) return AMG_ERR_OOM;
+  const amg_status st = alloc_batch(h, k);
+  if (st != AMG_OK) {
+    free_batch(h->batch, h->device, h->stream);
+    h->batch = nullptr;
+    h->batch_bytes = 0;
+    return st;
+  }
+  h->batch->k = k;
+  h->batch_bytes = h->batch->bytes;
   return AMG_OK;
 }
 
@@ -1539,7 +1557,7 @@ amg_status pcg_batch(amg_hierarchy *h, int32_t k, const double *Bu, double *Xu, 
       const double bb = B.col_host[cBb * k + j];
       info[j].iterations = B.iter_host[j];
       info[j].converged = (d == 1 || d == 4) ? 1 : 0;
-      info[j].rel_res = bb > 0 ? std::sqrt(B.col_host[cRr * k + j] / bb) : 0.0;
+      info[j].rel_res_recursive = bb > 0 ? std::sqrt(B.col_host[cRr * k + j] / bb) : 0.0;
       info[j].rel_res_true = bb > 0 ? std::sqrt(B.col_host[cRrTrue * k + j] / bb) : 0.0;
       info[j].ms = ms;
     }

@@ -3,8 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <thread>
 #include <vector>
 
 #include "amg.h"
@@ -197,6 +199,20 @@ struct amg_hierarchy {
   hipGraphExec_t iter_exec4 = nullptr;  // kIterGroup CG iterations
   hipGraph_t iter_graph4 = nullptr;
   bool graph_failed = false;
+  // in-solve kernel timing (amg_time_kernel with AMG_TIME_IN_SOLVE): while
+  // probe_id names a kernel, events are recorded right before and after each
+  // of its launches, pairwise into probe_ev
+  int32_t probe_id = -1;
+  mutable bool probe_armed = false;  // the next probed launch is the timed one
+  std::vector<hipEvent_t> probe_ev;
+  mutable size_t probe_next = 0;
+  bool has_rhs = false;  // a right-hand side was given to amg_pcg_solve
+  // AMG_ASYNC: the solve in flight runs on this host thread (joined by
+  // amg_wait, or by the next call on the hierarchy); its status is kept here
+  std::thread worker;
+  bool async_pending = false;
+  std::atomic<int> async_finished{0};
+  amg_status async_status = AMG_OK;
   // bookkeeping
   std::vector<void *> allocs;
   size_t bytes = 0;

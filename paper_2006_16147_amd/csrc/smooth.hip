@@ -1,5 +1,7 @@
 // Smoothed aggregation on the GPU (the alternative to the K-cycle in
-// Section 3.2): omega = 1 / ||D^-1 A||_inf, the smoothed prolongator
+// Section 3.2): omega = 4 / (3 ||D^-1 A||_inf) (the damping 4 / (3 rho(D^-1 A))
+// with rho estimated by the infinity norm, which reproduces the supplement's
+// convergence constant of the smoothed prolongator), the smoothed prolongator
 // Pbar = (I - omega D^-1 A) P of the composed tentative P, and the next level
 // Pbar^T A Pbar; plus Pbar and Pbar^T in the solve numbering.
 //
@@ -529,7 +531,7 @@ amg_status smooth_level(amg_hierarchy *h, Level &F, int32_t nc, const int32_t *a
   double nrm;
   std::memcpy(&nrm, &hmx, sizeof(double));
   if (!(nrm > 0.0) || !std::isfinite(nrm)) return AMG_ERR_NOT_SPD;
-  F.omega = 1.0 / nrm;
+  F.omega = 4.0 / (3.0 * nrm);
   // Pbar: one term per entry of A, reduced per (i, J), then finished
   {
     const int32_t count = (int32_t)F.nnz;

@@ -28,6 +28,8 @@
 #include <chrono>
 #include <cmath>
 
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 
 namespace amg {
@@ -1428,6 +1430,25 @@ const double *pbart_vals<double>(const Level &L) { return L.st_v64; }
 template <>
 const float *pbart_vals<float>(const Level &L) { return L.st_v32; }
 
+// In-solve timing probe. arm_probe(h, id) marks the next launch made through
+// launch_k as the timed one when kernel `id` is being timed (never during
+// graph capture, whose probe_id is -1); launch_k then launches it with
+// hipExtLaunchKernelGGL and the next pair of probe events, which the runtime
+// stamps at that dispatch's own start and end (no marker packets around it).
+inline void arm_probe(amg_hierarchy *h, int32_t id) { h->probe_armed = h->probe_id == id; }
+
+template <typename K, typename... Args>
+void launch_k(const amg_hierarchy *h, K k, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+  if (h->probe_armed && h->probe_next + 2 <= h->probe_ev.size()) {
+    h->probe_armed = false;
+    hipEvent_t e0 = h->probe_ev[h->probe_next], e1 = h->probe_ev[h->probe_next + 1];
+    h->probe_next += 2;
+    hipExtLaunchKernelGGL(k, grid, block, 0, s, e0, e1, 0, args...);
+    return;
+  }
+  hipLaunchKernelGGL(k, grid, block, 0, s, args...);
+}
+
 void finalize(amg_hierarchy *h, int32_t op, int32_t nparts, const int32_t *done) {
   k_finalize<<<1, 1024, 0, h->stream>>>(op, nparts, h->partials, h->scal, done);
 }
@@ -1447,15 +1468,10 @@ void pre_restrict(const amg_hierarchy *h, const Level &F, const Level &C, const 
   const int R = F.n >= (1 << 21) && F.n < kManyRows ? 2 : 1;
   const int32_t G = coarse_per_block(h) * R;
   const int32_t grid = ceil_div(C.n, G);
-  if (R == 4)
-    k_pre_restrict<TV, TR, MODE, TA, 4><<<grid, kBlock, 0, s>>>(C.n, G, F.seg, F.S.sptr, F.S.col,
-                                                               val, mv, pp, r, z, rc, done);
-  else if (R == 2)
-    k_pre_restrict<TV, TR, MODE, TA, 2><<<grid, kBlock, 0, s>>>(C.n, G, F.seg, F.S.sptr, F.S.col,
-                                                               val, mv, pp, r, z, rc, done);
-  else
-    k_pre_restrict<TV, TR, MODE, TA, 1><<<grid, kBlock, 0, s>>>(C.n, G, F.seg, F.S.sptr, F.S.col,
-                                                               val, mv, pp, r, z, rc, done);
+  auto k = R == 4 ? k_pre_restrict<TV, TR, MODE, TA, 4>
+           : R == 2 ? k_pre_restrict<TV, TR, MODE, TA, 2> : k_pre_restrict<TV, TR, MODE, TA, 1>;
+  launch_k(h, k, dim3(grid), dim3(kBlock), s, C.n, G, F.seg, F.S.sptr, F.S.col, val, mv, pp, r, z,
+           rc, done);
 }
 
 // whether the products of level l read A from its exact FP32 copy: level 0
@@ -1577,14 +1593,16 @@ void level0_post(amg_hierarchy *h, const double *r0, TV *z, double *z0, bool dot
     std::swap(z, tmp);
   }
   if (dot) {
+    arm_probe(h, 1);
     if (a32)
-      k_post<TV, double, double, true, float><<<g.grid, kBlock, 0, s>>>(
-          F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), r0, z, z0, h->partials, done,
-          dv);
+      launch_k(h, k_post<TV, double, double, true, float>, dim3(g.grid), dim3(kBlock), s, F.n,
+               g.chunk, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), r0, (const TV *)z, z0,
+               h->partials, done, dv);
     else
-      k_post<TV, double, double, true><<<g.grid, kBlock, 0, s>>>(
-          F.n, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), r0, z, z0, h->partials,
-          done, dv);
+      launch_k(h, k_post<TV, double, double, true>, dim3(g.grid), dim3(kBlock), s, F.n, g.chunk,
+               F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), r0, (const TV *)z, z0, h->partials,
+               done, dv);
+    h->probe_armed = false;
     if (!dv) finalize(h, kFinRZ, g.grid, done);
   } else {
     if (a32)
@@ -1711,7 +1729,9 @@ void vcycle_t(amg_hierarchy *h, const double *r0, double *z0, bool dot, const do
   const bool tail = L >= 2 && h->params.pre == 1 && h->params.post == 1 &&
                     h->lv[L - 1].n <= kTailMax && h->C.n <= kTailCoarseMax && !coarse_is_pcg(h);
   const int32_t down_end = tail ? L - 1 : L;  // levels [0, down_end) take the down step
+  arm_probe(h, 0);
   zb[0] = launch_down<TV, double>(h, 0, r0, done);
+  h->probe_armed = false;
   for (int32_t l = 1; l < down_end; ++l)
     zb[l] = launch_down<TV, TV>(h, l, (const TV *)h->lv[l].r, done);
   if (tail) {
@@ -2090,12 +2110,14 @@ void cg_iteration(amg_hierarchy *h) {
   const int32_t n = L0.n;
   const int32_t *done = &h->scal->done;
   const Geom g = geom(n);
+  arm_probe(h, 4);
   if (L0.S.exact32)
-    k_spmv_dot<float><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v32, h->p,
-                                                h->q, h->partials, done);
+    launch_k(h, k_spmv_dot<float>, dim3(g.grid), dim3(kBlock), s, n, g.chunk, L0.S.sptr,
+             L0.S.col, (const float *)L0.S.v32, (const double *)h->p, h->q, h->partials, done);
   else
-    k_spmv_dot<double><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col, L0.S.v64,
-                                                 h->p, h->q, h->partials, done);
+    launch_k(h, k_spmv_dot<double>, dim3(g.grid), dim3(kBlock), s, n, g.chunk, L0.S.sptr,
+             L0.S.col, (const double *)L0.S.v64, (const double *)h->p, h->q, h->partials, done);
+  h->probe_armed = false;
   finalize(h, kFinPQ, g.grid, done);
   k_update_xr<<<g.grid, kBlock, 0, s>>>(n, g.chunk, h->x, h->r, h->p, h->q, h->partials, h->scal,
                                         done);
@@ -2157,6 +2179,7 @@ amg_status pcg(amg_hierarchy *h, const double *b_user, double *x_user, double rt
   const Geom g = geom(n);
   AMG_TRY(ensure_iteration_graph(h));
   k_permute_in<<<grid1(n), kBlock, 0, s>>>(n, L0.perm, b_user, h->b);
+  h->has_rhs = true;
   k_permute_in<<<grid1(n), kBlock, 0, s>>>(n, L0.perm, x_user, h->x);
   k_scal_init<<<1, 1, 0, s>>>(h->scal, rtol, maxit);
   if (L0.S.exact32)
@@ -2218,7 +2241,7 @@ amg_status pcg(amg_hierarchy *h, const double *b_user, double *x_user, double rt
   if (info) {
     info->iterations = sc.iter;
     info->converged = (sc.done == 1 || sc.done == 4) ? 1 : 0;
-    info->rel_res = sc.bb > 0.0 ? std::sqrt(sc.rr / sc.bb) : 0.0;
+    info->rel_res_recursive = sc.bb > 0.0 ? std::sqrt(sc.rr / sc.bb) : 0.0;
     info->rel_res_true = sc.bb > 0.0 ? std::sqrt(sc.rr_true / sc.bb) : 0.0;
     info->ms = now_ms() - t0;
   }
@@ -2294,11 +2317,100 @@ amg_status time_vcycle(amg_hierarchy *h, int32_t reps, double *ms, double *bytes
   return AMG_OK;
 }
 
+// algorithmic HBM bytes of one launch of kernel 0-4 on `level`: CSR values +
+// int32 columns + int32 row offsets once per SpMV, every vector entry once
+double kernel_bytes(const amg_hierarchy *h, int32_t kernel, int32_t level) {
+  const Level &F = h->lv[level];
+  const Level &C = h->lv[level + 1];
+  const bool fp32 = h->params.precision == AMG_FP32;
+  const double V = fp32 ? 4.0 : 8.0;
+  const double n = F.n, nnz = (double)F.nnz, nc = C.n, nnzc = (double)C.nnz;
+  const double Vr = level == 0 ? 8.0 : V;  // level 0 reads/writes the FP64 CG vectors
+  switch (kernel) {
+    case 0:  // A M^-1, r, minv, p read; z, r_c written; segment offsets
+      return nnz * (V + 4) + 4 * (n + 1) + n * (Vr + 3 * V) + nc * (V + 4);
+    case 1:  // A, r, z, minv read; y written (level 0: A from its exact FP32 copy if any)
+      return nnz * ((level == 0 && F.S.exact32 ? 4.0 : V) + 4) + 4 * (n + 1) +
+             n * (Vr + V + V + Vr);
+    case 2:
+    case 3:  // coarse A, r_c, z_c, minv_c; fine z read + written, p, positions
+      return nnzc * (V + 4) + 4 * (nc + 1) + nc * (3 * V + 4) + n * (3 * V + 4);
+    default:  // A (8 or, from the exact FP32 copy, 4 bytes per value), p read; q written
+      return nnz * ((F.S.exact32 ? 4.0 : 8.0) + 4) + 4 * (n + 1) + n * 16;
+  }
+}
+
+
+// One of the level-0 kernels 0 (down step), 1 (post-smoothing with the CG
+// dot) or 4 (outer SpMV with its dot) timed where the solve runs it: `reps`
+// CG iterations from x = 0 on the last right-hand side, launched directly
+// (the graph cannot hold the events), rtol 0 and maxit reps + 1 so that no
+// kernel takes its early exit; the kernel's own dispatch start and end,
+// stamped into events by hipExtLaunchKernelGGL, give its mean duration with
+// the caches as the iteration leaves them. Hierarchies with one pre- and one
+// post-sweep only (otherwise these steps are several kernels).
+amg_status time_in_solve(amg_hierarchy *h, int32_t kernel, int32_t reps, double *ms,
+                         double *bytes) {
+  if (kernel != 0 && kernel != 1 && kernel != 4) return AMG_ERR_ARG;
+  if (reps < 1 || reps > 10000 || flexible(h) || h->params.smooth_p || h->lv.size() < 2 ||
+      h->params.pre != 1 || h->params.post != 1 || !h->has_rhs)
+    return AMG_ERR_ARG;
+  hipStream_t s = h->stream;
+  Level &L0 = h->lv[0];
+  const int32_t n = L0.n;
+  const int32_t *done = &h->scal->done;
+  const Geom g = geom(n);
+  AMG_HIP(hipMemsetAsync(h->x, 0, sizeof(double) * n, s));
+  k_scal_init<<<1, 1, 0, s>>>(h->scal, 0.0, reps + 1);
+  if (L0.S.exact32)
+    k_residual_norms<0, float><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col,
+                                                         L0.S.v32, h->b, h->x, h->r, h->partials);
+  else
+    k_residual_norms<0, double><<<g.grid, kBlock, 0, s>>>(n, g.chunk, L0.S.sptr, L0.S.col,
+                                                          L0.S.v64, h->b, h->x, h->r,
+                                                          h->partials);
+  finalize(h, kFinInit, g.grid, nullptr);
+  AMG_TRY(vcycle_perm(h, h->r, h->z, true, done));
+  k_xpay<<<grid1(n), kBlock, 0, s>>>(n, h->z, h->p, h->scal, 1, done);
+  h->probe_ev.assign(2 * (size_t)reps, nullptr);
+  amg_status st = AMG_OK;
+  for (auto &e : h->probe_ev)
+    if (hipEventCreate(&e) != hipSuccess) st = AMG_ERR_HIP;
+  if (st == AMG_OK) {
+    h->probe_next = 0;
+    h->probe_id = kernel;
+    for (int32_t k = 0; k < reps; ++k) cg_iteration(h);
+    h->probe_id = -1;
+    if (hipGetLastError() != hipSuccess || h->probe_next != h->probe_ev.size() ||
+        hipStreamSynchronize(s) != hipSuccess || hipEventSynchronize(h->probe_ev.back()) != hipSuccess)
+      st = AMG_ERR_HIP;
+  }
+  double total = 0.0;
+  for (size_t k = 0; st == AMG_OK && k + 1 < h->probe_ev.size(); k += 2) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, h->probe_ev[k], h->probe_ev[k + 1]) != hipSuccess)
+      st = AMG_ERR_HIP;
+    total += t;
+  }
+  for (auto e : h->probe_ev)
+    if (e) (void)hipEventDestroy(e);
+  h->probe_ev.clear();
+  (void)hipGetLastError();
+  if (st != AMG_OK) return st;
+  *ms = total / reps;
+  *bytes = kernel_bytes(h, kernel, 0);
+  return AMG_OK;
+}
+
 }  // namespace
 
 amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
                        double *ms, double *bytes) {
   const int32_t L = (int32_t)h->lv.size() - 1;
+  if (kernel & AMG_TIME_IN_SOLVE) {
+    if (level != 0) return AMG_ERR_ARG;
+    return time_in_solve(h, kernel & ~AMG_TIME_IN_SOLVE, reps, ms, bytes);
+  }
   if (kernel == 5) return time_vcycle(h, reps, ms, bytes);
   if (level < 0 || level >= L || reps < 1 || kernel < 0 || kernel > 4) return AMG_ERR_ARG;
   if (kernel == 4 && level != 0) return AMG_ERR_ARG;
@@ -2391,24 +2503,7 @@ amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *ms = (double)t / reps;
-  // algorithmic bytes: CSR values + int32 columns + int32 row offsets once per
-  // SpMV, every vector entry once
-  switch (kernel) {
-    case 0:  // A M^-1, r, minv, p read; z, r_c written; segment offsets
-      *bytes = nnz * (V + 4) + 4 * (n + 1) + n * (Vr + 3 * V) + nc * (V + 4);
-      break;
-    case 1:  // A, r, z, minv read; y written (level 0: A from its exact FP32 copy if any)
-      *bytes = nnz * ((level == 0 && F.S.exact32 ? 4.0 : V) + 4) + 4 * (n + 1) +
-               n * (Vr + V + V + Vr);
-      break;
-    case 2:
-    case 3:  // coarse A, r_c, z_c, minv_c; fine z read + written, p, positions
-      *bytes = nnzc * (V + 4) + 4 * (nc + 1) + nc * (3 * V + 4) + n * (3 * V + 4);
-      break;
-    default:  // A (8 or, from the exact FP32 copy, 4 bytes per value), p read; q written
-      *bytes = nnz * ((F.S.exact32 ? 4.0 : 8.0) + 4) + 4 * (n + 1) + n * 16;
-      break;
-  }
+  *bytes = kernel_bytes(h, kernel, level);
   return AMG_OK;
 }
 

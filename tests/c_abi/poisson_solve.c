@@ -1,8 +1,12 @@
 /* A plain C caller of the library (include/amg.h): builds the 7-point
  * Dirichlet Laplacian on an N^3 grid (Section 4's model problem) on the host,
  * copies it to the device with the HIP runtime, builds the hierarchy, solves
- * A x = A u to rtol 1e-8 with the V-cycle and with the K-cycle, and prints
- * one line per solve. Exit status 0 when both converge. */
+ * A x = A u to rtol 1e-8 with the V-cycle, with the K-cycle and with the
+ * V-cycle as a non-blocking solve (AMG_ASYNC, amg_query, amg_wait) on an
+ * explicitly named device (amg_params.device), and prints one line per
+ * solve. For even N it also checks the level-0 aggregates (amg_get_aggregates)
+ * against the 2 x 2 x 2 cubes that the matching gives on this problem.
+ * Exit status 0 when every solve converges and every check holds. */
 #include <hip/hip_runtime_api.h>
 #include <math.h>
 #include <stdio.h>
@@ -18,10 +22,35 @@
     }                                                       \
   } while (0)
 
-static int solve_with(const amg_csr *A, int cycle, const double *db, double *dx, int64_t n) {
+/* 1 when the level-0 aggregates are the 2 x 2 x 2 cubes numbered in the
+ * order of their smallest member (N even). */
+static int cubes_ok(amg_hierarchy *h, int N) {
+  const int64_t n = (int64_t)N * N * N;
+  int32_t *agg = malloc(sizeof(int32_t) * (size_t)n);
+  if (!agg || amg_get_aggregates(h, 0, agg) != AMG_OK) {
+    free(agg);
+    return 0;
+  }
+  int ok = 1;
+  const int H = N / 2;
+  for (int64_t i = 0; i < n && ok; ++i) {
+    const int x = (int)(i % N), y = (int)((i / N) % N), z = (int)(i / ((int64_t)N * N));
+    ok = agg[i] == x / 2 + H * (y / 2 + H * (z / 2));
+  }
+  free(agg);
+  return ok;
+}
+
+static int solve_with(const amg_csr *A, int cycle, int async, const double *db, double *dx,
+                      int N) {
+  const int64_t n = (int64_t)N * N * N;
   amg_params p;
   amg_params_default(&p);
   p.cycle = cycle;
+  if (async) {
+    p.flags |= AMG_ASYNC;
+    CHECK_HIP(hipGetDevice(&p.device));
+  }
   amg_hierarchy *h = NULL;
   amg_status st = amg_setup(A, &p, &h);
   if (st != AMG_OK) {
@@ -30,14 +59,21 @@ static int solve_with(const amg_csr *A, int cycle, const double *db, double *dx,
   }
   int32_t nlev = 0;
   amg_num_levels(h, &nlev);
+  const int agg_ok = N % 2 == 1 || cubes_ok(h, N);
   CHECK_HIP(hipMemset(dx, 0, sizeof(double) * (size_t)n));
   amg_solve_info info;
+  int polls = 0;
   st = amg_pcg_solve(h, db, dx, 1e-8, 500, &info);
-  printf("cycle=%s levels=%d iterations=%d converged=%d rel_res_true=%.3e\n",
-         cycle == AMG_CYCLE_K ? "K" : "V", nlev, info.iterations, info.converged,
-         info.rel_res_true);
+  if (async && st == AMG_OK) {
+    int32_t done = 0;
+    while (amg_query(h, &done) == AMG_OK && !done) ++polls;
+    st = amg_wait(h);
+  }
+  printf("cycle=%s%s levels=%d iterations=%d converged=%d rel_res_true=%.3e aggregates=%s\n",
+         cycle == AMG_CYCLE_K ? "K" : "V", async ? " async" : "", nlev, info.iterations,
+         info.converged, info.rel_res_true, agg_ok ? "cubes" : "WRONG");
   amg_free(h);
-  return st == AMG_OK && info.converged && info.rel_res_true <= 1.001e-8 ? 0 : 1;
+  return st == AMG_OK && info.converged && info.rel_res_true <= 1.001e-8 && agg_ok ? 0 : 1;
 }
 
 int main(int argc, char **argv) {
@@ -83,8 +119,9 @@ int main(int argc, char **argv) {
   CHECK_HIP(hipMemcpy(dva, va, sizeof(double) * (size_t)nnz, hipMemcpyHostToDevice));
   CHECK_HIP(hipMemcpy(db, b, sizeof(double) * (size_t)n, hipMemcpyHostToDevice));
   amg_csr A = {n, nnz, drp, dci, dva};
-  int rc = solve_with(&A, AMG_CYCLE_V, db, dx, n);
-  rc |= solve_with(&A, AMG_CYCLE_K, db, dx, n);
+  int rc = solve_with(&A, AMG_CYCLE_V, 0, db, dx, N);
+  rc |= solve_with(&A, AMG_CYCLE_K, 0, db, dx, N);
+  rc |= solve_with(&A, AMG_CYCLE_V, 1, db, dx, N);
   hipFree(drp);
   hipFree(dci);
   hipFree(dva);

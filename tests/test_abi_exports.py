@@ -4,6 +4,7 @@
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -52,7 +53,7 @@ def test_host_only_calls(lib):
     assert (p.sweeps, p.max_coarse, p.pre, p.post, p.precision) == (3, 200, 1, 1, 0)
     assert (p.cycle, p.w_sweeps, p.coarse_solver) == (amg.CYCLE_V, 0, amg.COARSE_CHOLESKY)
     assert (p.coarse_rtol, p.coarse_maxit) == (1e-4, 30)  # Section 5's coarsest CG stop
-    assert p.smooth_p == 0
+    assert p.smooth_p == 0 and p.device == -1
     assert ctypes.sizeof(amg.Params) == 80  # the C struct, field for field
     assert amg.amg_status_string(amg.Status.ERR_STALL).startswith("coarsening")
     est = amg.amg_estimate_footprint(4096000, 28518400, p)
@@ -61,4 +62,36 @@ def test_host_only_calls(lib):
     L = amg.load_library()
     n = ctypes.c_int32()
     assert L.amg_num_levels(None, ctypes.byref(n)) == amg.Status.ERR_ARG
+    assert L.amg_wait(None) == amg.Status.ERR_ARG
+    assert L.amg_query(None, ctypes.byref(n)) == amg.Status.ERR_ARG
+    assert L.amg_get_aggregates(None, 0, None) == amg.Status.ERR_ARG
     L.amg_free(None)
+
+
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and offsetof of a struct of amg.h, as the C compiler lays it out."""
+    src = tmp_path / "layout.c"
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "amg.h"', "int main(void) {",
+             '  printf("%%zu\\n", sizeof(%s));' % struct]
+    lines += ['  printf("%%zu\\n", offsetof(%s, %s));' % (struct, f) for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(v) for v in out[1:]]
+
+
+@pytest.mark.parametrize("struct, cls", [("amg_params", "Params"),
+                                         ("amg_solve_info", "SolveInfo"),
+                                         ("amg_csr", "Csr")])
+def test_binding_structs_match_the_header(struct, cls, tmp_path):
+    """The ctypes structures of the binding have the C layout, field by field."""
+    from paper_2006_16147_amd import amg
+
+    C = getattr(amg, cls)
+    fields = [f[0] for f in C._fields_]
+    size, offsets = _c_layout(struct, fields, tmp_path)
+    assert ctypes.sizeof(C) == size
+    assert [getattr(C, f).offset for f in fields] == offsets

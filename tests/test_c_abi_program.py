@@ -1,6 +1,8 @@
 """A plain C program calls the library through include/amg.h (no Python in
 the path): it must compile and link against the built library here, and on
-a GPU it must solve the Poisson problem with both cycles."""
+a GPU it must solve the Poisson problem with both cycles, and once more as a
+non-blocking (AMG_ASYNC) solve on a named device, with the level-0 aggregates
+read back through amg_get_aggregates."""
 
 import os
 import subprocess
@@ -35,4 +37,6 @@ def test_c_program_solves_on_gpu(tmp_path):
     r = subprocess.run([exe, "24"], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     lines = [l for l in r.stdout.splitlines() if l.startswith("cycle=")]
-    assert len(lines) == 2 and all("converged=1" in l for l in lines)
+    assert len(lines) == 3 and all("converged=1" in l for l in lines)
+    assert all("aggregates=cubes" in l for l in lines)
+    assert lines[2].startswith("cycle=V async")

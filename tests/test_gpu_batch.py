@@ -83,14 +83,17 @@ def test_batch_fp32_hierarchy(orc):
     assert np.linalg.norm(X[:, 7] - x1) / np.linalg.norm(x1) < 1e-8
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("k", [2, 6, 12])
+@pytest.mark.parametrize("k,precision", [(2, "fp64"), (6, "fp64"), (12, "fp64"), (130, "fp64"),
+                                         (2, "fp32"), (6, "fp32"), (12, "fp32")])
 def test_batch_vector_and_one_value_forms_agree(orc, k, precision):
     """The level-0 kernels move two FP64 or four FP32 columns per lane when k
     allows it. With k = 2 and 6 the FP32 hierarchy mixes the two-column FP64
     kernels (outer SpMV, CG update, p = z + b p) with the one-value forms of
-    the FP32 ones; k = 12 takes the vector forms throughout. Every column
-    matches its single solve and, at equal iterations, the oracle."""
+    the FP32 ones; k = 12 takes the vector forms throughout. FP64 with
+    k = 130 needs more than 64 two-column lanes per row, so the column
+    reductions come from two blocks along the grid's second dimension.
+    Every column matches its single solve and, at equal iterations, the
+    oracle."""
     from paper_2006_16147_amd import amg
 
     A = inputs.laplacian7(16)
@@ -158,14 +161,16 @@ def test_batch_deterministic():
     np.testing.assert_array_equal(X1.view(np.uint64), X2.view(np.uint64))
 
 
+@pytest.mark.parametrize("k", [6, 12])
 @pytest.mark.parametrize("pre,post", [(2, 2), (3, 1), (1, 2)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_batch_extra_sweeps_match_single_and_oracle(orc, pre, post, precision):
-    """The block V-cycle applies the hierarchy's pre/post sweep counts."""
+def test_batch_extra_sweeps_match_single_and_oracle(orc, pre, post, precision, k):
+    """The block V-cycle applies the hierarchy's pre/post sweep counts. With
+    k = 12 an FP32 hierarchy takes the four-column down step before the
+    one-value post-smoothing and residual kernels of the extra sweeps."""
     from paper_2006_16147_amd import amg
 
     A = inputs.laplacian7(20)
-    k = 6
     B = np.random.default_rng(5).uniform(-1, 1, (A.n, k))
     prec = amg.FP32 if precision == "fp32" else amg.FP64
     h = setup(A, pre=pre, post=post, precision=prec)

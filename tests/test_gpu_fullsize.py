@@ -1,11 +1,22 @@
-"""Parity at the benchmark's full size and launch configuration.
+"""Parity at the benchmark's full sizes and launch configurations.
 
-160^3 Poisson (n = 4 096 000) with b = A u: the whole GPU hierarchy is
-compared bit for bit with the oracle's (its serial setup takes seconds at
-this size), the closed-form cube aggregates are checked, and the solve is
-compared with the oracle at an equal iteration count. The 256^3 anisotropic
-case checks properties that hold at any size.
+160^3 Poisson (n = 4 096 000) with b = A u and the 256^3 anisotropic-block
+problem (n = 16 777 216): the whole GPU hierarchy is compared bit for bit
+with the oracle's (its serial setup takes seconds at these sizes), the
+closed-form cube aggregates are checked on the Poisson problem, the FP64
+solve is compared with the oracle at an equal iteration count, and the
+FP32-hierarchy solve is compared with the oracle's FP64 solution of the same
+system to the same tolerance. The 128^3 x 32 block solve is compared column
+by column with the single solves and, on sampled columns, with the oracle.
 """
+
+# FP32 hierarchy (V-cycle in FP32, CG in FP64) against the FP64 oracle's
+# solution to the same rtol. Each preconditioned residual is perturbed by
+# FP32 rounding (~1e-7 relative), and the outer CG damps that perturbation
+# of each correction; both solves take the same iterations, and the measured
+# differences are 1.2e-12 (160^3), 6.0e-14 (256^3 anisotropic) and below
+# 1e-13 (128^3 x 32 columns). The bound keeps two orders of margin.
+FP32_VS_ORACLE = 1e-10
 
 import numpy as np
 import pytest
@@ -58,12 +69,18 @@ def test_headline_solve(orc, headline, precision):
     assert info["rel_res_true"] <= 1.001e-8
     # error bound ||x - u|| <= kappa(A) ||r|| / ||b|| ||u|| with kappa < 2e4
     assert np.linalg.norm(x - u) / np.linalg.norm(u) < 1e-8 * 1.2e4
+    ho = orc.Hierarchy(A)
+    xo_conv, io_conv = ho.pcg(b, rtol=1e-8, maxit=200)
+    assert abs(io_conv["iterations"] - info["iterations"]) <= 1
     if precision == "fp64":
-        ho = orc.Hierarchy(A)
-        xo, io = ho.pcg(b, rtol=0.0, maxit=info["iterations"])
+        xo = xo_conv
+        if io_conv["iterations"] != info["iterations"]:
+            xo, _ = ho.pcg(b, rtol=0.0, maxit=info["iterations"])
         assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8
-        _, io_conv = ho.pcg(b, rtol=1e-8, maxit=200)
-        assert abs(io_conv["iterations"] - info["iterations"]) <= 1
+    else:
+        err = np.linalg.norm(x - xo_conv) / np.linalg.norm(xo_conv)
+        print("160^3 FP32 hierarchy vs FP64 oracle: rel diff %.3e" % err)
+        assert err < FP32_VS_ORACLE
 
 
 def test_headline_vcycle_sampled_against_oracle(orc, headline):
@@ -84,31 +101,58 @@ def test_headline_vcycle_sampled_against_oracle(orc, headline):
     np.testing.assert_allclose(zg[sel], zo[sel], rtol=0, atol=1e-12 * np.abs(zo).max())
 
 
-def test_aniso_256_fp32_vs_fp64():
-    """256^3 anisotropic blocks: both hierarchies reach the FP64 residual and
-    agree within the conditioning bound."""
+@pytest.fixture(scope="module")
+def aniso256(orc):
+    """256^3 anisotropic blocks (16^3-node blocks, eps log-uniform, seed 2):
+    the numpy case both sides use, and the oracle's hierarchy of it."""
+    c = inputs.aniso_blocks_case(256, 16, seed=2)
+    ho = orc.Hierarchy(c["A"])
+    assert ho.ok
+    return c, ho
+
+
+def test_aniso_256_hierarchy_bit_exact(aniso256):
+    c, ho = aniso256
+    h = setup(c["A"])
+    assert_same_hierarchy(h, ho)
+    print("256^3 aniso levels", h.sizes())
+    h.close()
+
+
+def test_aniso_256_solves_against_oracle(aniso256):
+    """FP64 hierarchy: equal to the oracle's iterate at an equal iteration
+    count, iterations within one. FP32 hierarchy: within FP32_VS_ORACLE of
+    the oracle's FP64 solution to the same rtol. Both reach the true
+    residual."""
     from paper_2006_16147_amd import amg
 
-    import torch
-
-    ex, ey, b = inputs.aniso_blocks_coefficients(256, 16, seed=2)
-    rp, ci, va = inputs.diffusion7_torch(256, torch.from_numpy(ex), torch.from_numpy(ey), 1.0,
-                                         "cuda")
-    h64 = amg.amg_setup(rp, ci, va)
+    c, ho = aniso256
+    A, b = c["A"], c["b"]
+    h64 = setup(A)
     st, i64, x64 = solve(h64, b, rtol=1e-8, maxit=500)
     h64.close()
-    h32 = amg.amg_setup(rp, ci, va, precision=amg.FP32)
+    h32 = setup(A, precision=amg.FP32)
     st32, i32, x32 = solve(h32, b, rtol=1e-8, maxit=500)
     h32.close()
     assert st == 0 and st32 == 0
     assert i64["rel_res_true"] <= 1.001e-8 and i32["rel_res_true"] <= 1.01e-8
-    assert np.linalg.norm(x32 - x64) / np.linalg.norm(x64) < 1e-4
+    xo, io = ho.pcg(b, rtol=1e-8, maxit=500)
+    assert abs(io["iterations"] - i64["iterations"]) <= 1
+    err32 = np.linalg.norm(x32 - xo) / np.linalg.norm(xo)
+    print("256^3 aniso: %d / %d / %d iterations (GPU FP64 / GPU FP32 / oracle), FP32 vs oracle "
+          "%.3e" % (i64["iterations"], i32["iterations"], io["iterations"], err32))
+    assert err32 < FP32_VS_ORACLE
+    if io["iterations"] != i64["iterations"]:
+        xo, _ = ho.pcg(b, rtol=0.0, maxit=i64["iterations"])
+    assert np.linalg.norm(x64 - xo) / np.linalg.norm(xo) < 1e-8
 
 
-def test_batch_128_k32_sampled_against_oracle(orc):
+def test_batch_128_k32_against_single_solves_and_oracle(orc):
     """Multi-RHS at its full size and launch configuration (128^3, k = 32,
     FP32 hierarchy, autotuned tile): every column reaches the FP64 true
-    residual, and two sampled columns match the oracle's FP64 solve."""
+    residual and equals the single FP32 solve of its right-hand side closely;
+    four sampled columns are within FP32_VS_ORACLE of the oracle's FP64
+    solution."""
     import torch
 
     from paper_2006_16147_amd import amg
@@ -122,12 +166,23 @@ def test_batch_128_k32_sampled_against_oracle(orc):
     assert st == 0
     assert all(i["converged"] and i["rel_res_true"] <= 1.01e-8 for i in infos)
     Xh = X.cpu().numpy()
+    worst = 0.0
+    for j in range(32):
+        b = torch.from_numpy(np.ascontiguousarray(B[:, j])).cuda()
+        x = torch.zeros_like(b)
+        st1, i1 = amg.amg_pcg_solve(h, b, x, rtol=1e-8, maxit=200)
+        assert st1 == 0 and abs(i1["iterations"] - infos[j]["iterations"]) <= 1
+        x1 = x.cpu().numpy()
+        worst = max(worst, np.linalg.norm(Xh[:, j] - x1) / np.linalg.norm(x1))
+    print("128^3 x 32: batch column vs single FP32 solve, worst rel diff %.3e" % worst)
+    assert worst < 1e-10  # measured 3.1e-13
     ho = orc.Hierarchy(A)
-    for j in (0, 31):
+    for j in (0, 11, 22, 31):
         xo, io = ho.pcg(B[:, j], rtol=1e-8, maxit=200)
-        assert abs(io["iterations"] - infos[j]["iterations"]) <= 2
-        # both solutions within the conditioning bound of the exact one
-        assert np.linalg.norm(Xh[:, j] - xo) / np.linalg.norm(xo) < 1e-8 * 1.2e4
+        assert abs(io["iterations"] - infos[j]["iterations"]) <= 1
+        err = np.linalg.norm(Xh[:, j] - xo) / np.linalg.norm(xo)
+        print("128^3 x 32: column %d vs FP64 oracle %.3e" % (j, err))
+        assert err < FP32_VS_ORACLE
     h.close()
 
 
@@ -135,7 +190,8 @@ def test_smoothed_hierarchy_and_paper_gpu_preconditioner_at_160(orc, headline):
     """Smoothed aggregation at the benchmark size: the GPU hierarchy (levels,
     every coarse matrix, every Pbar) bit-exact with the oracle's, and Section
     5's GPU preconditioner (Pbar, 4 l1-Jacobi pre/post sweeps, CG coarsest)
-    reaching 1e-6 in 7 flexible-CG iterations, equal to the oracle's iterate."""
+    reaching 1e-6 in as many flexible-CG iterations as the oracle (6; Section
+    5 reports 7 on one GPU at 6M unknowns), equal to the oracle's iterate."""
     from paper_2006_16147_amd import amg
 
     A, b = headline["A"], headline["b"]
@@ -150,7 +206,9 @@ def test_smoothed_hierarchy_and_paper_gpu_preconditioner_at_160(orc, headline):
         assert om == ho.omega(l)
         np.testing.assert_array_equal(pv.view(np.uint64), ho.pbar(l)[2].view(np.uint64))
     st, info, x = solve(h, b, rtol=1e-6, maxit=100)
-    assert st == 0 and info["iterations"] == 7 and info["rel_res_true"] <= 1.001e-6
-    xo, _ = ho.fcg(b, rtol=0.0, maxit=7, pre=4, post=4, cycle="V")
+    _, io = ho.fcg(b, rtol=1e-6, maxit=100, pre=4, post=4, cycle="V")
+    assert st == 0 and info["iterations"] == io["iterations"] == 6
+    assert info["rel_res_true"] <= 1.001e-6
+    xo, _ = ho.fcg(b, rtol=0.0, maxit=info["iterations"], pre=4, post=4, cycle="V")
     assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8
     h.close()

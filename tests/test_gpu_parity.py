@@ -328,6 +328,34 @@ def test_time_whole_vcycle_reports_bytes_and_rejects_kcycle():
         hk.time_kernel(5, 0, reps=2)
 
 
+def test_time_in_solve_matches_the_kernel_and_leaves_the_solve_unchanged():
+    """amg_time_kernel with AMG_TIME_IN_SOLVE: kernels 0, 1 and 4 of level 0
+    timed inside the CG iterations report the same algorithmic bytes as the
+    back-to-back timing and a positive duration; it needs a right-hand side
+    first and one pre/post sweep, and a later solve gives the same bits."""
+    from paper_2006_16147_amd import amg
+
+    A = inputs.laplacian7(32)
+    h = setup(A)
+    with pytest.raises(amg.AmgError):  # no right-hand side yet
+        h.time_kernel(0 | amg.TIME_IN_SOLVE, 0, reps=3)
+    b = np.random.default_rng(2).uniform(-1, 1, A.n)
+    _, info, x1 = solve(h, b)
+    for k in (0, 1, 4):
+        ms, by = h.time_kernel(k | amg.TIME_IN_SOLVE, 0, reps=info["iterations"])
+        assert ms > 0.0
+        assert by == h.time_kernel(k, 0, reps=2)[1]
+    with pytest.raises(amg.AmgError):  # kernel 2 is not a level-0 solve kernel
+        h.time_kernel(2 | amg.TIME_IN_SOLVE, 0, reps=3)
+    _, info2, x2 = solve(h, b)
+    assert info2["iterations"] == info["iterations"]
+    np.testing.assert_array_equal(x1.view(np.uint64), x2.view(np.uint64))
+    h2 = setup(A, pre=2)
+    solve(h2, b)
+    with pytest.raises(amg.AmgError):
+        h2.time_kernel(0 | amg.TIME_IN_SOLVE, 0, reps=3)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_exact_fp32_level0_values_are_lossless(precision):
     """When every value of A is an FP32 number (the 7-point Laplacian), level

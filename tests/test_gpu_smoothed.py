@@ -133,14 +133,14 @@ def test_smoothed_rejections_and_byte_count():
 
 def test_smoothed_hierarchy_at_80_matches_oracle(orc):
     """80^3 Poisson (512k unknowns, the paper's per-core size): the smoothed
-    hierarchy is bit-exact with the oracle's; opc 2.018 by the stated formula
-    (the paper prints 1.835)."""
+    hierarchy is bit-exact with the oracle's; opc 2.025 with omega =
+    4 / (3 ||D^-1 A||_inf) (the paper prints 1.835)."""
     A = inputs.laplacian7(80)
     h = setup(A, smooth_p=1)
     ho = orc.Hierarchy(A, smooth=True)
-    assert h.sizes() == ho.sizes() == [512000, 64000, 8030, 1013, 128]
+    assert h.sizes() == ho.sizes() == [512000, 64000, 8056, 1019, 129]
     assert h.nnzs() == ho.nnzs()
     for l in range(1, ho.num_levels):
         _, _, val = h.level_csr(l)
         np.testing.assert_array_equal(val.view(np.uint64), ho.level_csr(l).val.view(np.uint64))
-    assert abs(h.opc() - 2.0177) < 1e-3
+    assert abs(h.opc() - 2.0255) < 1e-3
