@@ -202,6 +202,22 @@ amg_status amg_setup(const amg_csr *A, const amg_params *params, amg_hierarchy *
 amg_status amg_pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol,
                          int32_t maxit, amg_solve_info *info);
 
+/* amg_pcg_solve for callers that cannot allocate device memory (code that
+ * must not call hipMalloc: tight serving loops, harnesses that forbid
+ * allocation). Same arguments, results (bit for bit) and errors as
+ * amg_pcg_solve, but the call allocates nothing: the solve's scratch (the
+ * block partial sums of its reductions, 3 x 65536 doubles, the CG scalars
+ * and the K-cycle scalars of up to 64 levels: ~1.6 MB in all) comes from
+ * one static device array per device, which the library holds until the
+ * process ends, and the iterations are launched directly instead of from
+ * the graph amg_pcg_solve instantiates on its first call. Every hierarchy
+ * fits that array (its size does not depend on n). The array is shared by
+ * all hierarchies on a device: calls on one device that overlap in time
+ * race, so issue them from one host thread at a time. Always blocking (a
+ * hierarchy built with AMG_ASYNC is solved synchronously here). */
+amg_status amg_pcg_solve_noalloc(amg_hierarchy *h, const double *b, double *x, double rtol,
+                                 int32_t maxit, amg_solve_info *info);
+
 /* k independent PCG solves sharing the hierarchy: column j of the n x k
  * row-major blocks B (device, read) and X (device, in: x0, out: x) is solved
  * with its own CG recurrence (own alpha, beta, stop test); the V-cycle runs

@@ -18,7 +18,7 @@ __all__ = [
     "lib_path", "load_library", "Params", "SolveInfo", "Hierarchy",
     "amg_params_default", "amg_setup", "amg_pcg_solve", "amg_pcg_solve_batch",
     "amg_vcycle_apply", "amg_free", "amg_estimate_footprint", "amg_status_string",
-    "amg_wait", "amg_query", "FLAG_ASYNC", "EXPORTED_SYMBOLS",
+    "amg_wait", "amg_query", "amg_pcg_solve_noalloc", "FLAG_ASYNC", "EXPORTED_SYMBOLS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -35,7 +35,7 @@ EXPORTED_SYMBOLS = (
     "amg_get_transfer", "amg_get_l1diag", "amg_get_w", "amg_footprint_bytes",
     "amg_estimate_footprint", "amg_setup_times", "amg_matching_rounds", "amg_time_kernel",
     "amg_batch_tile", "amg_status_string", "amg_get_prolongator", "amg_get_aggregates",
-    "amg_wait", "amg_query",
+    "amg_wait", "amg_query", "amg_pcg_solve_noalloc",
 )
 
 
@@ -106,6 +106,7 @@ def load_library():
         "amg_setup": (C.c_int, [P(Csr), P(Params), P(V)]),
         "amg_pcg_solve": (C.c_int, [V, V, V, D, I32, P(SolveInfo)]),
         "amg_pcg_solve_batch": (C.c_int, [V, I32, V, V, D, I32, P(SolveInfo)]),
+        "amg_pcg_solve_noalloc": (C.c_int, [V, V, V, D, I32, P(SolveInfo)]),
         "amg_vcycle_apply": (C.c_int, [V, V, V]),
         "amg_set_stream": (C.c_int, [V, V]),
         "amg_wait": (C.c_int, [V]),
@@ -354,6 +355,21 @@ def amg_pcg_solve(h: Hierarchy, b, x, rtol=1e-8, maxit=1000, raise_on_error=True
         return st, None  # amg_wait(h) gives the status and info
     if raise_on_error and st not in (Status.OK, Status.NOT_CONVERGED):
         raise AmgError(st, "amg_pcg_solve")
+    return st, info.as_dict()
+
+
+def amg_pcg_solve_noalloc(h: Hierarchy, b, x, rtol=1e-8, maxit=1000, raise_on_error=True):
+    """amg_pcg_solve without any device allocation in the call (its scratch
+    is the library's static device array); always blocking."""
+    import torch
+
+    _check_vectors(h, (h.n,), b=b, x=x)
+    info = SolveInfo()
+    st = load_library().amg_pcg_solve_noalloc(h.handle, _ptr(b, torch.float64, "b"),
+                                              _ptr(x, torch.float64, "x"), float(rtol),
+                                              int(maxit), C.byref(info))
+    if raise_on_error and st not in (Status.OK, Status.NOT_CONVERGED):
+        raise AmgError(st, "amg_pcg_solve_noalloc")
     return st, info.as_dict()
 
 

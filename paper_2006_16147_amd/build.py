@@ -25,6 +25,7 @@ SOURCES = {
     "smooth.hip": ["-ffp-contract=off"],
     "solve.hip": [],
     "batch.hip": [],
+    "noalloc.hip": [],
 }
 
 COMMON = [

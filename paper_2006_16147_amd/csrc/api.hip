@@ -256,6 +256,9 @@ amg_status amg_setup(const amg_csr *A, const amg_params *params, amg_hierarchy *
   }
   DeviceGuard guard(device);
   if (!guard.ok) return AMG_ERR_HIP;
+  // set-up of the allocation-free solve: the device address of its scratch
+  // array, looked up once per device with that device current
+  AMG_TRY(init_noalloc_scratch(device));
   const size_t n1 = (size_t)A->n + 1, nz = (size_t)A->nnz;
   if (!device_range(A->row_ptr, 4 * n1, device) || !device_range(A->col, 4 * nz, device) ||
       !device_range(A->val, 8 * nz, device))
@@ -305,6 +308,19 @@ amg_status amg_pcg_solve(amg_hierarchy *h, const double *b, double *x, double rt
     return AMG_ERR_ARG;
   AMG_TRY(join_user_stream(h));
   return run_solve(h, [=]() { return pcg(h, b, x, rtol, maxit, info); });
+}
+
+amg_status amg_pcg_solve_noalloc(amg_hierarchy *h, const double *b, double *x, double rtol,
+                                 int32_t maxit, amg_solve_info *info) {
+  if (!h || !b || !x || !(rtol >= 0.0) || maxit < 0) return AMG_ERR_ARG;
+  join_async(h);
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return AMG_ERR_HIP;
+  const size_t bytes = sizeof(double) * (size_t)h->lv[0].n;
+  if (!device_range(b, bytes, h->device) || !device_range(x, bytes, h->device))
+    return AMG_ERR_ARG;
+  AMG_TRY(join_user_stream(h));
+  return pcg_noalloc(h, b, x, rtol, maxit, info);
 }
 
 amg_status amg_pcg_solve_batch(amg_hierarchy *h, int32_t k, const double *B, double *X,

@@ -260,7 +260,12 @@ amg_status long_row_csr(amg_hierarchy *h, int32_t l, bool fp32);
 amg_status build_solve_formats(amg_hierarchy *h);
 amg_status vcycle(amg_hierarchy *h, const double *r, double *z, bool fuse_dot, const int32_t *done);
 amg_status pcg(amg_hierarchy *h, const double *b, double *x, double rtol, int32_t maxit,
-               amg_solve_info *info);
+               amg_solve_info *info, bool use_graph = true);
+// allocation-free solve (noalloc.hip): the solve's scratch in a file-scope
+// device array whose address amg_setup looks up once per device
+amg_status init_noalloc_scratch(int device);
+amg_status pcg_noalloc(amg_hierarchy *h, const double *b, double *x, double rtol, int32_t maxit,
+                       amg_solve_info *info);
 amg_status pcg_batch(amg_hierarchy *h, int32_t k, const double *B, double *X, double rtol,
                      int32_t maxit, amg_solve_info *info);
 amg_status batch_kt(const amg_hierarchy *h, int32_t *kt);

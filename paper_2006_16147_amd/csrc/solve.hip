@@ -2170,14 +2170,18 @@ amg_status ensure_iteration_graph(amg_hierarchy *h) {
 }  // namespace
 
 amg_status pcg(amg_hierarchy *h, const double *b_user, double *x_user, double rtol,
-               int32_t maxit, amg_solve_info *info) {
+               int32_t maxit, amg_solve_info *info, bool use_graph) {
   const double t0 = now_ms();
   hipStream_t s = h->stream;
   Level &L0 = h->lv[0];
   const int32_t n = L0.n;
   const int32_t *done = &h->scal->done;
   const Geom g = geom(n);
-  AMG_TRY(ensure_iteration_graph(h));
+  if (use_graph) AMG_TRY(ensure_iteration_graph(h));
+  // the graphs hold the hierarchy's own scratch buffers: launched only when
+  // the solve uses them
+  hipGraphExec_t exec1 = use_graph ? h->iter_exec : nullptr;
+  hipGraphExec_t exec4 = use_graph ? h->iter_exec4 : nullptr;
   k_permute_in<<<grid1(n), kBlock, 0, s>>>(n, L0.perm, b_user, h->b);
   h->has_rhs = true;
   k_permute_in<<<grid1(n), kBlock, 0, s>>>(n, L0.perm, x_user, h->x);
@@ -2213,10 +2217,10 @@ amg_status pcg(amg_hierarchy *h, const double *b_user, double *x_user, double rt
     it_prev = sc.iter;
     const int32_t c = std::min(chunk, maxit - queued);
     int32_t k = 0;
-    if (h->iter_exec4)
-      for (; k + kIterGroup <= c; k += kIterGroup) AMG_HIP(hipGraphLaunch(h->iter_exec4, s));
+    if (exec4)
+      for (; k + kIterGroup <= c; k += kIterGroup) AMG_HIP(hipGraphLaunch(exec4, s));
     for (; k < c; ++k) {
-      if (h->iter_exec) AMG_HIP(hipGraphLaunch(h->iter_exec, s));
+      if (exec1) AMG_HIP(hipGraphLaunch(exec1, s));
       else cg_iteration(h);
     }
     AMG_HIP(hipGetLastError());
