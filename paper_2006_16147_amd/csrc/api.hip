@@ -482,6 +482,7 @@ size_t amg_estimate_footprint(int64_t n, int64_t nnz, const amg_params *params) 
   b += sn * (4 * 4 + 8) + sn * 2 * X;           // perm, iperm, seg, aggp, pp (+ FP32 pp, 1/m)
   b += pad * (4 + 2 * 8 + 2 * X);               // SELL: columns, A, A M^-1 (+ FP32 copies)
   b += 4.0 * 1.02 * nnz;                        // exact FP32 copy of A_0 (when it applies)
+  b += 2 * (2.0 * 1.02 * nnz + 4.0 * 2.5 * n);  // level 0's two sets of LDS tile lists
   b += 4 * V * sn;                              // V-cycle vectors
   b += 6 * 8.0 * n;                             // CG vectors (x, r, z, p, q, b)
   b += (double)kPartPlanes * kMaxParts * 8.0;   // block partials

@@ -437,6 +437,127 @@ __global__ void __launch_bounds__(kBlock) k_post(
   if (DOT) block_partial<1>(d, partials);
 }
 
+// ---- LDS-staged gathers (level 0): the same products as above, with the
+// gathered vector's entries of the block's tile loaded into LDS first ----
+
+// xs[i] = x(hidx[h0 + i]) for the block's list of u entries, eight loads in
+// flight per thread, then a barrier
+template <typename TV, typename X>
+__device__ __forceinline__ void stage_tile(TV *xs, const int32_t *__restrict__ hidx, int32_t h0,
+                                           int32_t u, X x) {
+  for (int32_t i0 = threadIdx.x; i0 < u; i0 += 8 * kBlock) {
+    int32_t c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int32_t i = i0 + q * kBlock;
+      c[q] = i < u ? hidx[h0 + i] : 0;
+    }
+    TV v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = i0 + q * kBlock < u ? x(c[q]) : TV(0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (i0 + q * kBlock < u) xs[i0 + q * kBlock] = v[q];
+  }
+  __syncthreads();
+}
+
+// sum_k val[k] * xs[lcol[k]] over one SELL row: the products and sums of
+// sell_dot_t, in the same order and with the same unconditional batched
+// loads, with the operands read from LDS
+template <typename TV, typename TA>
+__device__ __forceinline__ TV sell_dot_lds(const uint16_t *__restrict__ lcol,
+                                           const TA *__restrict__ val, int32_t base, int32_t w,
+                                           const TV *xs) {
+  TV acc = 0;
+  for (int32_t k0 = 0; k0 < w; k0 += kRowBatch) {
+    int32_t c[kRowBatch];
+    TA va[kRowBatch];
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      const int32_t idx = base + (k0 + u < w ? k0 + u : w - 1) * kSlice;
+      c[u] = ld_stream(&lcol[idx]);
+      va[u] = ld_stream(&val[idx]);
+    }
+    TV g[kRowBatch];
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) g[u] = xs[c[u]];
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u)
+      if (k0 + u < w) acc += (TV)va[u] * g[u];
+  }
+  return acc;
+}
+
+// k_pre_restrict with the tile of block b = its segment rows (tiles hseg)
+template <typename TV, typename TR, int MODE, typename TA = TV, int R = 1>
+__global__ void __launch_bounds__(kBlock) k_pre_restrict_lds(
+    int32_t nc, int32_t G, const int32_t *__restrict__ seg, const int32_t *__restrict__ sptr,
+    const uint16_t *__restrict__ lcol, const int32_t *__restrict__ hptr,
+    const int32_t *__restrict__ hidx, const TA *__restrict__ val, const TV *__restrict__ minv,
+    const TV *__restrict__ pp, const TR *__restrict__ r, TV *__restrict__ z,
+    TV *__restrict__ rc, const int32_t *__restrict__ done) {
+  extern __shared__ double lds_d[];
+  TV *xs = reinterpret_cast<TV *>(lds_d);
+  __shared__ TV sh[kBlock * R];
+  if (*done) return;
+  const int32_t J0 = blockIdx.x * G;
+  const int32_t J1 = min(nc, J0 + G);
+  const int32_t f0 = seg[J0], f1 = seg[J1];
+  const int32_t h0 = hptr[blockIdx.x];
+  if (MODE == kPreFromZ)
+    stage_tile(xs, hidx, h0, hptr[blockIdx.x + 1] - h0, [&](int32_t c) { return z[c]; });
+  else
+    stage_tile(xs, hidx, h0, hptr[blockIdx.x + 1] - h0, [&](int32_t c) { return (TV)r[c]; });
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int32_t row = f0 + (int32_t)threadIdx.x + u * kBlock;
+    if (row < f1) {
+      int32_t base, w;
+      sell_row(sptr, row, &base, &w);
+      const TV acc = sell_dot_lds<TV, TA>(lcol, val, base, w, xs);
+      const TV ri = (TV)r[row];
+      if (MODE == kPreScaled) z[row] = ri * minv[row];
+      sh[threadIdx.x + u * kBlock] = pp[row] * (ri - acc);
+    }
+  }
+  __syncthreads();
+  for (int32_t J = J0 + (int32_t)threadIdx.x; J < J1; J += kBlock) {
+    const int32_t b = seg[J] - f0, e = seg[J + 1] - f0;
+    TV s = 0;
+    for (int32_t m = b; m < e; ++m) s += sh[m];
+    rc[J] = s;
+  }
+}
+
+// k_post with the tile of block b = its row chunk (tiles hrow)
+template <typename TV, typename TR, typename TO, bool DOT, typename TA = TV>
+__global__ void __launch_bounds__(kBlock) k_post_lds(
+    int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const uint16_t *__restrict__ lcol,
+    const int32_t *__restrict__ hptr, const int32_t *__restrict__ hidx,
+    const TA *__restrict__ val, const TV *__restrict__ minv, const TR *__restrict__ r,
+    const TV *__restrict__ z, TO *__restrict__ y, double *__restrict__ partials,
+    const int32_t *__restrict__ done, const double *__restrict__ dv = nullptr) {
+  extern __shared__ double lds_d[];
+  TV *xs = reinterpret_cast<TV *>(lds_d);
+  if (*done) return;
+  int32_t rb, re;
+  rows_of_block(n, chunk, &rb, &re);
+  const int32_t h0 = hptr[blockIdx.x];
+  stage_tile(xs, hidx, h0, hptr[blockIdx.x + 1] - h0, [&](int32_t c) { return z[c]; });
+  double d[1] = {0.0};
+  for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
+    int32_t base, w;
+    sell_row(sptr, row, &base, &w);
+    const TV acc = sell_dot_lds<TV, TA>(lcol, val, base, w, xs);
+    const TR rr = r[row];
+    const TO yo = (TO)(z[row] + ((TV)rr - acc) * minv[row]);
+    y[row] = yo;
+    if (DOT) d[0] += (dv ? dv[row] : (double)rr) * (double)yo;
+  }
+  if (DOT) block_partial<1>(d, partials);
+}
+
 // ---- smoothed aggregation: unfused down and up steps (Pbar is not a
 // segment map, so restriction and prolongation are CSR products) ----
 
@@ -857,6 +978,30 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot(
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
     const double acc = sell_dot_t<double, TA>(col, val, base, w, [&](int32_t c) { return p[c]; });
+    q[row] = acc;
+    d[0] += p[row] * acc;
+  }
+  block_partial<1>(d, partials);
+}
+
+// k_spmv_dot with the tile of block b = its row chunk (tiles hrow)
+template <typename TA>
+__global__ void __launch_bounds__(kBlock) k_spmv_dot_lds(
+    int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const uint16_t *__restrict__ lcol,
+    const int32_t *__restrict__ hptr, const int32_t *__restrict__ hidx,
+    const TA *__restrict__ val, const double *__restrict__ p, double *__restrict__ q,
+    double *__restrict__ partials, const int32_t *__restrict__ done) {
+  extern __shared__ double lds_d[];
+  if (*done) return;
+  int32_t rb, re;
+  rows_of_block(n, chunk, &rb, &re);
+  const int32_t h0 = hptr[blockIdx.x];
+  stage_tile(lds_d, hidx, h0, hptr[blockIdx.x + 1] - h0, [&](int32_t c) { return p[c]; });
+  double d[1] = {0.0};
+  for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
+    int32_t base, w;
+    sell_row(sptr, row, &base, &w);
+    const double acc = sell_dot_lds<double, TA>(lcol, val, base, w, lds_d);
     q[row] = acc;
     d[0] += p[row] * acc;
   }
@@ -1438,16 +1583,22 @@ const float *pbart_vals<float>(const Level &L) { return L.st_v32; }
 inline void arm_probe(amg_hierarchy *h, int32_t id) { h->probe_armed = h->probe_id == id; }
 
 template <typename K, typename... Args>
-void launch_k(const amg_hierarchy *h, K k, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+void launch_k(const amg_hierarchy *h, K k, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s,
+              Args... args) {
   if (h->probe_armed && h->probe_next + 2 <= h->probe_ev.size()) {
     h->probe_armed = false;
     hipEvent_t e0 = h->probe_ev[h->probe_next], e1 = h->probe_ev[h->probe_next + 1];
     h->probe_next += 2;
-    hipExtLaunchKernelGGL(k, grid, block, 0, s, e0, e1, 0, args...);
+    hipExtLaunchKernelGGL(k, grid, block, shmem, s, e0, e1, 0, args...);
     return;
   }
-  hipLaunchKernelGGL(k, grid, block, 0, s, args...);
+  hipLaunchKernelGGL(k, grid, block, shmem, s, args...);
 }
+
+// rows per thread of the down step on a level of n rows: 2 on levels of 2^21
+// to kManyRows rows (160^3 level 0: 79.4 -> 78.1 us; 4 rows: 83 us; on
+// 16.7 M rows 2 rows were slower)
+inline int down_rows(int64_t n) { return n >= (1 << 21) && n < kManyRows ? 2 : 1; }
 
 void finalize(amg_hierarchy *h, int32_t op, int32_t nparts, const int32_t *done) {
   k_finalize<<<1, 1024, 0, h->stream>>>(op, nparts, h->partials, h->scal, done);
@@ -1458,20 +1609,73 @@ int32_t coarse_per_block(const amg_hierarchy *h) {
   return g < 1 ? 1 : g;
 }
 
-// Down step of level F into C with R fine rows per thread: 2 on levels of
-// 2^21 to kManyRows rows (160^3 level 0: 79.4 -> 78.1 us; 4 rows: 83 us;
-// on 16.7 M rows 2 rows were slower).
+// Down step of level F into C with down_rows(n) fine rows per thread; with
+// LDS-staged gathers where the level has tiles of this geometry.
 template <typename TV, typename TR, int MODE, typename TA>
 void pre_restrict(const amg_hierarchy *h, const Level &F, const Level &C, const TA *val,
                   const TV *mv, const TV *pp, const TR *r, TV *z, TV *rc, const int32_t *done) {
   hipStream_t s = h->stream;
-  const int R = F.n >= (1 << 21) && F.n < kManyRows ? 2 : 1;
+  const int R = down_rows(F.n);
   const int32_t G = coarse_per_block(h) * R;
   const int32_t grid = ceil_div(C.n, G);
-  auto k = R == 4 ? k_pre_restrict<TV, TR, MODE, TA, 4>
-           : R == 2 ? k_pre_restrict<TV, TR, MODE, TA, 2> : k_pre_restrict<TV, TR, MODE, TA, 1>;
-  launch_k(h, k, dim3(grid), dim3(kBlock), s, C.n, G, F.seg, F.S.sptr, F.S.col, val, mv, pp, r, z,
-           rc, done);
+  if (F.hseg.ok() && F.hseg.param == G && F.hseg.ntiles == grid) {
+    const Halo &H = F.hseg;
+    auto k = R == 2 ? k_pre_restrict_lds<TV, TR, MODE, TA, 2> : k_pre_restrict_lds<TV, TR, MODE, TA, 1>;
+    launch_k(h, k, dim3(grid), dim3(kBlock), (uint32_t)(sizeof(TV) * H.umax), s, C.n, G, F.seg,
+             F.S.sptr, (const uint16_t *)H.lcol, (const int32_t *)H.hptr, (const int32_t *)H.hidx,
+             val, mv, pp, r, z, rc, done);
+    return;
+  }
+  auto k = R == 2 ? k_pre_restrict<TV, TR, MODE, TA, 2> : k_pre_restrict<TV, TR, MODE, TA, 1>;
+  launch_k(h, k, dim3(grid), dim3(kBlock), 0u, s, C.n, G, F.seg, F.S.sptr, F.S.col, val, mv, pp,
+           r, z, rc, done);
+}
+
+// y = z + M^-1 (r - A z) on a level (DOT: with the block partials of the CG
+// dot), with LDS-staged gathers where the level has row tiles
+template <typename TV, typename TR, typename TO, bool DOT, typename TA>
+void post_sweep(const amg_hierarchy *h, const Level &F, const TA *val, const TV *minv,
+                const TR *r, const TV *z, TO *y, double *partials, const int32_t *done,
+                const double *dv = nullptr) {
+  hipStream_t s = h->stream;
+  const Geom g = geom(F.n);
+  if (F.hrow.ok() && F.hrow.param == g.chunk && F.hrow.ntiles == g.grid) {
+    const Halo &H = F.hrow;
+    launch_k(h, k_post_lds<TV, TR, TO, DOT, TA>, dim3(g.grid), dim3(kBlock),
+             (uint32_t)(sizeof(TV) * H.umax), s, F.n, g.chunk, F.S.sptr,
+             (const uint16_t *)H.lcol, (const int32_t *)H.hptr, (const int32_t *)H.hidx, val,
+             minv, r, z, y, partials, done, dv);
+    return;
+  }
+  launch_k(h, k_post<TV, TR, TO, DOT, TA>, dim3(g.grid), dim3(kBlock), 0u, s, F.n, g.chunk,
+           F.S.sptr, F.S.col, val, minv, r, z, y, partials, done, dv);
+}
+
+// q = A p with the block partials of (p, q) on level 0 (A from its exact FP32
+// copy when there is one), with LDS-staged gathers where there are row tiles
+inline void spmv_dot0(const amg_hierarchy *h, const double *p, double *q, const int32_t *done) {
+  hipStream_t s = h->stream;
+  const Level &F = h->lv[0];
+  const Geom g = geom(F.n);
+  if (F.hrow.ok() && F.hrow.param == g.chunk && F.hrow.ntiles == g.grid) {
+    const Halo &H = F.hrow;
+    const uint32_t shmem = (uint32_t)(sizeof(double) * H.umax);
+    if (F.S.exact32)
+      launch_k(h, k_spmv_dot_lds<float>, dim3(g.grid), dim3(kBlock), shmem, s, F.n, g.chunk,
+               F.S.sptr, (const uint16_t *)H.lcol, (const int32_t *)H.hptr,
+               (const int32_t *)H.hidx, (const float *)F.S.v32, p, q, h->partials, done);
+    else
+      launch_k(h, k_spmv_dot_lds<double>, dim3(g.grid), dim3(kBlock), shmem, s, F.n, g.chunk,
+               F.S.sptr, (const uint16_t *)H.lcol, (const int32_t *)H.hptr,
+               (const int32_t *)H.hidx, (const double *)F.S.v64, p, q, h->partials, done);
+    return;
+  }
+  if (F.S.exact32)
+    launch_k(h, k_spmv_dot<float>, dim3(g.grid), dim3(kBlock), 0u, s, F.n, g.chunk, F.S.sptr,
+             F.S.col, (const float *)F.S.v32, p, q, h->partials, done);
+  else
+    launch_k(h, k_spmv_dot<double>, dim3(g.grid), dim3(kBlock), 0u, s, F.n, g.chunk, F.S.sptr,
+             F.S.col, (const double *)F.S.v64, p, q, h->partials, done);
 }
 
 // whether the products of level l read A from its exact FP32 copy: level 0
@@ -1585,32 +1789,30 @@ void level0_post(amg_hierarchy *h, const double *r0, TV *z, double *z0, bool dot
   const bool a32 = reads32<TV>(F, 0);
   for (int32_t k = 1; k < h->params.post; ++k) {
     if (a32)
-      k_post<TV, double, TV, false, float><<<g.grid, kBlock, 0, s>>>(
-          F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), r0, z, tmp, nullptr, done);
+      post_sweep<TV, double, TV, false, float>(h, F, F.S.v32, minv<TV>(F), r0, z, tmp, nullptr,
+                                               done);
     else
-      k_post<TV, double, TV, false><<<g.grid, kBlock, 0, s>>>(
-          F.n, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), r0, z, tmp, nullptr, done);
+      post_sweep<TV, double, TV, false, TV>(h, F, vals<TV>(F), minv<TV>(F), r0, z, tmp, nullptr,
+                                            done);
     std::swap(z, tmp);
   }
   if (dot) {
     arm_probe(h, 1);
     if (a32)
-      launch_k(h, k_post<TV, double, double, true, float>, dim3(g.grid), dim3(kBlock), s, F.n,
-               g.chunk, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), r0, (const TV *)z, z0,
-               h->partials, done, dv);
+      post_sweep<TV, double, double, true, float>(h, F, F.S.v32, minv<TV>(F), r0, z, z0,
+                                                  h->partials, done, dv);
     else
-      launch_k(h, k_post<TV, double, double, true>, dim3(g.grid), dim3(kBlock), s, F.n, g.chunk,
-               F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), r0, (const TV *)z, z0, h->partials,
-               done, dv);
+      post_sweep<TV, double, double, true, TV>(h, F, vals<TV>(F), minv<TV>(F), r0, z, z0,
+                                               h->partials, done, dv);
     h->probe_armed = false;
     if (!dv) finalize(h, kFinRZ, g.grid, done);
   } else {
     if (a32)
-      k_post<TV, double, double, false, float><<<g.grid, kBlock, 0, s>>>(
-          F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, minv<TV>(F), r0, z, z0, nullptr, done);
+      post_sweep<TV, double, double, false, float>(h, F, F.S.v32, minv<TV>(F), r0, z, z0,
+                                                   nullptr, done);
     else
-      k_post<TV, double, double, false><<<g.grid, kBlock, 0, s>>>(
-          F.n, g.chunk, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), r0, z, z0, nullptr, done);
+      post_sweep<TV, double, double, false, TV>(h, F, vals<TV>(F), minv<TV>(F), r0, z, z0,
+                                                nullptr, done);
   }
 }
 
@@ -1874,6 +2076,192 @@ amg_status alloc_level_vectors(amg_hierarchy *h, Level &L, size_t vbytes) {
 
 }  // namespace
 
+// ---- LDS-staged gathers: tile lists (setup) ----
+
+constexpr int kHaloCap = 8192;        // padded entries of one tile sorted in LDS
+constexpr int kHaloThreads = 1024;
+constexpr int32_t kHaloMaxList = 4096;  // longest list a level may have (LDS of a block)
+
+__global__ void k_tile_starts(int32_t ntiles, int32_t step, int32_t nmax,
+                              const int32_t *__restrict__ seg, int32_t *__restrict__ tb) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > ntiles) return;
+  const int64_t v = (int64_t)t * step;
+  const int32_t c = (int32_t)(v < nmax ? v : nmax);
+  tb[t] = seg ? seg[c] : c;  // row chunks, or the first row of coarse row c
+}
+
+// Tile t = rows [tb[t], tb[t + 1]). Its SELL positions' columns (W per row,
+// W the widest slice among its rows; shorter rows padded with INT32_MAX) are
+// sorted in LDS and made distinct. Pass 0 writes the number of distinct
+// columns to count[t] (-1 when the padded entries exceed kHaloCap); pass 1
+// writes the list at hidx + hptr[t] and, at every position, the index of its
+// column in the list.
+__global__ void __launch_bounds__(kHaloThreads) k_halo(
+    int32_t pass, const int32_t *__restrict__ tb, const int32_t *__restrict__ sptr,
+    const int32_t *__restrict__ col, int32_t *__restrict__ count,
+    const int32_t *__restrict__ hptr, int32_t *__restrict__ hidx, uint16_t *__restrict__ lcol) {
+  __shared__ int32_t keys[kHaloCap];
+  __shared__ int32_t part[kHaloThreads];
+  __shared__ int32_t wmax;
+  const int32_t t = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int32_t r0 = tb[t], r1 = tb[t + 1], rows = r1 - r0;
+  if (tid == 0) wmax = 0;
+  __syncthreads();
+  if (rows > 0) {
+    int32_t wl = 0;
+    for (int32_t q = r0 / kSlice + tid; q <= (r1 - 1) / kSlice; q += nt)
+      wl = max(wl, (sptr[q + 1] - sptr[q]) / kSlice);
+    atomicMax(&wmax, wl);
+  }
+  __syncthreads();
+  const int32_t W = wmax;
+  const int64_t E = (int64_t)rows * W;
+  if (E > kHaloCap) {
+    if (pass == 0 && tid == 0) count[t] = -1;
+    return;
+  }
+  int32_t P = 1;
+  while (P < E) P <<= 1;
+  for (int32_t i = tid; i < P; i += nt) {
+    int32_t key = INT32_MAX;
+    if (i < E) {
+      int32_t base, w;
+      sell_row(sptr, r0 + i / W, &base, &w);
+      if (i % W < w) key = col[base + (i % W) * kSlice];
+    }
+    keys[i] = key;
+  }
+  __syncthreads();
+  for (int32_t size = 2; size <= P; size <<= 1)  // bitonic sort, ascending
+    for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int32_t i = tid; i < P; i += nt) {
+        const int32_t j = i ^ stride;
+        if (j > i) {
+          const int32_t a = keys[i], b = keys[j];
+          if ((a > b) == ((i & size) == 0)) {
+            keys[i] = b;
+            keys[j] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  // distinct keys: thread tid takes positions [tid * per, tid * per + per)
+  const int32_t per = (P + nt - 1) / nt;  // at most kHaloCap / kHaloThreads = 8
+  int32_t kv[kHaloCap / kHaloThreads];
+  uint32_t first = 0;
+  int32_t mine = 0;
+  for (int32_t q = 0; q < per; ++q) {
+    const int32_t i = tid * per + q;
+    kv[q] = i < P ? keys[i] : INT32_MAX;
+    if (i < P && kv[q] != INT32_MAX && (i == 0 || keys[i - 1] != kv[q])) {
+      first |= 1u << q;
+      ++mine;
+    }
+  }
+  part[tid] = mine;
+  __syncthreads();
+  for (int32_t off = 1; off < nt; off <<= 1) {  // inclusive scan of the counts
+    const int32_t add = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += add;
+    __syncthreads();
+  }
+  const int32_t u = part[nt - 1];
+  int32_t pos = part[tid] - mine;
+  for (int32_t q = 0; q < per; ++q)  // every key was read before the scan
+    if (first & (1u << q)) keys[pos++] = kv[q];
+  __syncthreads();
+  if (pass == 0) {
+    if (tid == 0) count[t] = u;
+    return;
+  }
+  const int32_t h0 = hptr[t];
+  for (int32_t j = tid; j < u; j += nt) hidx[h0 + j] = keys[j];
+  for (int64_t i = tid; i < E; i += nt) {
+    int32_t base, w;
+    sell_row(sptr, r0 + (int32_t)(i / W), &base, &w);
+    const int32_t k = (int32_t)(i % W);
+    if (k >= w) continue;
+    const int32_t idx = base + k * kSlice;
+    const int32_t c = col[idx];
+    int32_t lo = 0, hi = u - 1;  // c is in the list
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (keys[mid] < c) lo = mid + 1;
+      else hi = mid;
+    }
+    lcol[idx] = (uint16_t)lo;
+  }
+}
+
+// Tile lists of level L for `ntiles` tiles starting at tb (device, ntiles + 1
+// entries). Leaves H empty (the kernels then gather from memory) when a tile
+// has too many entries to sort in LDS or too long a list for a block's LDS.
+amg_status build_halo(amg_hierarchy *h, const Level &L, const int32_t *tb, int32_t ntiles,
+                      int32_t param, Halo *H) {
+  hipStream_t s = h->stream;
+  int32_t *count;
+  AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&count), sizeof(int32_t) * (ntiles + 1), s));
+  k_halo<<<ntiles, kHaloThreads, 0, s>>>(0, tb, L.S.sptr, L.S.col, count, nullptr, nullptr,
+                                        nullptr);
+  std::vector<int32_t> hc(ntiles);
+  AMG_HIP(hipMemcpyAsync(hc.data(), count, sizeof(int32_t) * ntiles, hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  int64_t total = 0;
+  int32_t umax = 0;
+  bool fits = true;
+  for (int32_t c : hc) {
+    fits = fits && c >= 0;
+    umax = std::max(umax, c);
+    total += c > 0 ? c : 0;
+  }
+  if (!fits || umax > kHaloMaxList || total > INT32_MAX) {
+    (void)hipFreeAsync(count, s);
+    return AMG_OK;
+  }
+  Halo G;
+  G.ntiles = ntiles;
+  G.param = param;
+  G.umax = umax;
+  amg_status st = dalloc(h, &G.hptr, (size_t)ntiles + 1);
+  if (st == AMG_OK) st = scan_exclusive_i32(count, G.hptr, ntiles, s);
+  if (st == AMG_OK) st = dalloc(h, &G.hidx, (size_t)(total > 0 ? total : 1));
+  if (st == AMG_OK) st = dalloc(h, &G.lcol, (size_t)L.S.nnz_padded);
+  if (st == AMG_OK)
+    k_halo<<<ntiles, kHaloThreads, 0, s>>>(1, tb, L.S.sptr, L.S.col, nullptr, G.hptr, G.hidx,
+                                          G.lcol);
+  (void)hipFreeAsync(count, s);
+  AMG_TRY(st);
+  AMG_HIP(hipGetLastError());
+  *H = G;
+  return AMG_OK;
+}
+
+// Level 0's tiles: the row chunks of the streaming kernels and the blocks of
+// the down step (coarse rows by coarse_per_block, fine rows by segment).
+amg_status build_level0_halos(amg_hierarchy *h) {
+  hipStream_t s = h->stream;
+  Level &F = h->lv[0];
+  const Level &C = h->lv[1];
+  int32_t *tb;
+  const Geom g = geom(F.n);
+  const int32_t G = coarse_per_block(h) * down_rows(F.n);
+  const int32_t nseg = ceil_div(C.n, G);
+  const int32_t most = std::max(g.grid, nseg);
+  AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&tb), sizeof(int32_t) * (most + 1), s));
+  k_tile_starts<<<ceil_div(g.grid + 1, kBlock), kBlock, 0, s>>>(g.grid, g.chunk, F.n, nullptr,
+                                                                tb);
+  amg_status st = build_halo(h, F, tb, g.grid, g.chunk, &F.hrow);
+  if (st == AMG_OK) {
+    k_tile_starts<<<ceil_div(nseg + 1, kBlock), kBlock, 0, s>>>(nseg, G, C.n, F.seg, tb);
+    st = build_halo(h, F, tb, nseg, G, &F.hseg);
+  }
+  (void)hipFreeAsync(tb, s);
+  return st;
+}
+
 // average row length from which a level of a smoothed hierarchy is smoothed
 // with several lanes per row
 constexpr double kLongRow = 48.0;
@@ -1994,6 +2382,8 @@ amg_status build_solve_formats(amg_hierarchy *h) {
       AMG_TRY(dev_alloc(h, &L.v2, vbytes * L.n + 16));
     }
   }
+  // LDS-staged gathers of level 0's products (where every tile's list fits)
+  if (nlev > 1) AMG_TRY(build_level0_halos(h));
   if (h->params.cycle == AMG_CYCLE_K) AMG_TRY(dalloc(h, &h->kscal, (size_t)kKScal * nlev));
   if (h->params.smooth_p)
     for (int32_t l = 0; l + 1 < nlev; ++l) {
@@ -2111,12 +2501,7 @@ void cg_iteration(amg_hierarchy *h) {
   const int32_t *done = &h->scal->done;
   const Geom g = geom(n);
   arm_probe(h, 4);
-  if (L0.S.exact32)
-    launch_k(h, k_spmv_dot<float>, dim3(g.grid), dim3(kBlock), s, n, g.chunk, L0.S.sptr,
-             L0.S.col, (const float *)L0.S.v32, (const double *)h->p, h->q, h->partials, done);
-  else
-    launch_k(h, k_spmv_dot<double>, dim3(g.grid), dim3(kBlock), s, n, g.chunk, L0.S.sptr,
-             L0.S.col, (const double *)L0.S.v64, (const double *)h->p, h->q, h->partials, done);
+  spmv_dot0(h, h->p, h->q, done);
   h->probe_armed = false;
   finalize(h, kFinPQ, g.grid, done);
   k_update_xr<<<g.grid, kBlock, 0, s>>>(n, g.chunk, h->x, h->r, h->p, h->q, h->partials, h->scal,
@@ -2451,26 +2836,26 @@ amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t 
       case 1:  // post-smoothing on `level` (level 0: with the CG dot product)
         if (fp32) {
           if (level == 0)
-            k_post<float, double, double, true><<<g.grid, kBlock, 0, s>>>(
-                F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, F.sminv32, h->r, (const float *)F.z,
-                h->z, h->partials, done);
+            post_sweep<float, double, double, true, float>(h, F, F.S.v32, F.sminv32, h->r,
+                                                           (const float *)F.z, h->z,
+                                                           h->partials, done);
           else
-            k_post<float, float, float, false><<<g.grid, kBlock, 0, s>>>(
-                F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, F.sminv32, (const float *)F.r,
-                (const float *)F.z, (float *)F.y, nullptr, done);
+            post_sweep<float, float, float, false, float>(h, F, F.S.v32, F.sminv32,
+                                                          (const float *)F.r, (const float *)F.z,
+                                                          (float *)F.y, nullptr, done);
         } else {
           if (level == 0 && F.S.exact32)
-            k_post<double, double, double, true, float><<<g.grid, kBlock, 0, s>>>(
-                F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32, F.sminv64, h->r, (const double *)F.z,
-                h->z, h->partials, done);
+            post_sweep<double, double, double, true, float>(h, F, F.S.v32, F.sminv64, h->r,
+                                                            (const double *)F.z, h->z,
+                                                            h->partials, done);
           else if (level == 0)
-            k_post<double, double, double, true><<<g.grid, kBlock, 0, s>>>(
-                F.n, g.chunk, F.S.sptr, F.S.col, F.S.v64, F.sminv64, h->r, (const double *)F.z,
-                h->z, h->partials, done);
+            post_sweep<double, double, double, true, double>(h, F, F.S.v64, F.sminv64, h->r,
+                                                             (const double *)F.z, h->z,
+                                                             h->partials, done);
           else
-            k_post<double, double, double, false><<<g.grid, kBlock, 0, s>>>(
-                F.n, g.chunk, F.S.sptr, F.S.col, F.S.v64, F.sminv64, (const double *)F.r,
-                (const double *)F.z, (double *)F.y, nullptr, done);
+            post_sweep<double, double, double, false, double>(
+                h, F, F.S.v64, F.sminv64, (const double *)F.r, (const double *)F.z,
+                (double *)F.y, nullptr, done);
         }
         break;
       case 2:  // post-smoothing on level + 1 fused with prolongation into level
@@ -2485,12 +2870,7 @@ amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t 
               (const double *)C.z, F.seg, F.aggp, F.pp64, (double *)F.t, done);
         break;
       default:
-        if (F.S.exact32)
-          k_spmv_dot<float><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col, F.S.v32,
-                                                      h->p, h->q, h->partials, done);
-        else
-          k_spmv_dot<double><<<g.grid, kBlock, 0, s>>>(F.n, g.chunk, F.S.sptr, F.S.col,
-                                                       F.S.v64, h->p, h->q, h->partials, done);
+        spmv_dot0(h, h->p, h->q, done);
         break;
     }
   };
