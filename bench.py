@@ -46,7 +46,7 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def vcycle_bytes(sizes, nnzs, V, nL, a0=None):
+def vcycle_bytes(sizes, nnzs, V, nL, a0=None, s0=None):
     """Algorithmic HBM bytes of one V-cycle with this library's kernel set.
 
     n_l rows, z_l entries per level; V value bytes; Vr = 8 on level 0, whose
@@ -61,10 +61,13 @@ def vcycle_bytes(sizes, nnzs, V, nL, a0=None):
       coarsest solve (dense A_L^-1):      8 n_L^2 + V n_L
       level-0 post-smoothing:             z_0 (A0 + 4) + 4 (n_0 + 1) + n_0 (16 + 2 V)
     A0 = a0 is the byte width of level 0's stored values there (4 when the
-    FP64 hierarchy reads the exact FP32 copy of A; V otherwise; the down
-    step reads the scaled A M^-1 in the hierarchy precision).
+    FP64 hierarchy reads the exact FP32 copy of A; V otherwise). s0 is the
+    byte width of the values level 0's down step reads: the scaled A M^-1 in
+    the hierarchy precision (V), or 4 where an FP64 hierarchy forms M^-1 r
+    in LDS and reads the exact FP32 copy of A.
     """
     a0 = V if a0 is None else a0
+    s0 = V if s0 is None else s0
     L = len(sizes) - 1
     if L == 0:
         return 8.0 * nL * nL + 16.0 * nL
@@ -72,7 +75,8 @@ def vcycle_bytes(sizes, nnzs, V, nL, a0=None):
     for l in range(L):
         n, z, nc = sizes[l], nnzs[l], sizes[l + 1]
         Vr = 8.0 if l == 0 else V
-        total += z * (V + 4) + 4 * (n + 1) + n * (Vr + 3 * V) + nc * (V + 4)
+        Vs = s0 if l == 0 else V
+        total += z * (Vs + 4) + 4 * (n + 1) + n * (Vr + 3 * V) + nc * (V + 4)
         total += n * (3 * V + 4)
     for c in range(1, L):
         total += nnzs[c] * (V + 4) + 4 * (sizes[c] + 1) + 3 * V * sizes[c]

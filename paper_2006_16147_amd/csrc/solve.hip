@@ -372,11 +372,14 @@ __global__ void k_permute_out(int32_t n, const int32_t *__restrict__ perm,
 // Down step on level l for the coarse positions [J0, J0 + G) of this block:
 // z = M^-1 r with the residual through the stored A M^-1 (kPreScaled) or,
 // after extra pre-smoothing sweeps, the given z (kPreFromZ, plain A stored
-// as TA); then
+// as TA), or z = M^-1 r formed while staging r in LDS and the residual
+// through the plain A (kPreStagedZ, LDS kernel only: where A is stored in
+// fewer bytes than A M^-1, i.e. level 0's exact FP32 copy in an FP64
+// hierarchy); then
 // r_{l+1}(J) = sum over the segment of J, in order, of p_k (r - A z)_k.
 // The block's fine rows are the union of its segments (at most R kBlock
 // rows; thread t takes rows t, t + kBlock, ...).
-enum PreMode : int { kPreScaled = 0, kPreFromZ = 1 };
+enum PreMode : int { kPreScaled = 0, kPreFromZ = 1, kPreStagedZ = 2 };
 
 template <typename TV, typename TR, int MODE, typename TA = TV, int R = 1>
 __global__ void __launch_bounds__(kBlock) k_pre_restrict(
@@ -507,6 +510,9 @@ __global__ void __launch_bounds__(kBlock) k_pre_restrict_lds(
   const int32_t h0 = hptr[blockIdx.x];
   if (MODE == kPreFromZ)
     stage_tile(xs, hidx, h0, hptr[blockIdx.x + 1] - h0, [&](int32_t c) { return z[c]; });
+  else if (MODE == kPreStagedZ)
+    stage_tile(xs, hidx, h0, hptr[blockIdx.x + 1] - h0,
+               [&](int32_t c) { return (TV)r[c] * minv[c]; });
   else
     stage_tile(xs, hidx, h0, hptr[blockIdx.x + 1] - h0, [&](int32_t c) { return (TV)r[c]; });
 #pragma unroll
@@ -517,7 +523,7 @@ __global__ void __launch_bounds__(kBlock) k_pre_restrict_lds(
       sell_row(sptr, row, &base, &w);
       const TV acc = sell_dot_lds<TV, TA>(lcol, val, base, w, xs);
       const TV ri = (TV)r[row];
-      if (MODE == kPreScaled) z[row] = ri * minv[row];
+      if (MODE != kPreFromZ) z[row] = ri * minv[row];
       sh[threadIdx.x + u * kBlock] = pp[row] * (ri - acc);
     }
   }
@@ -1685,6 +1691,33 @@ bool reads32(const Level &F, int32_t l) {
   return l == 0 && sizeof(TV) == 8 && F.S.exact32;
 }
 
+// whether level F's one-sweep down step forms z = M^-1 r in LDS and reads
+// the plain A: an FP64 level with down-step tiles. With level 0's exact
+// FP32 copy of A that is 4 value bytes per entry instead of the 8 of
+// A M^-1; without it the same bytes, and the same arithmetic either way, so
+// that the FP32 copy changes no result bit.
+template <typename TV>
+bool staged_down(const amg_hierarchy *h, const Level &F, const Level &C) {
+  const int32_t G = coarse_per_block(h) * down_rows(F.n);
+  return sizeof(TV) == 8 && F.hseg.ok() && F.hseg.param == G &&
+         F.hseg.ntiles == ceil_div(C.n, G);
+}
+
+// the one-sweep down step of level F (z = M^-1 r, residual, restriction)
+template <typename TV, typename TR>
+void down_one_sweep(const amg_hierarchy *h, const Level &F, const Level &C, const TR *r, TV *z,
+                    const int32_t *done) {
+  if (staged_down<TV>(h, F, C) && F.S.exact32)
+    pre_restrict<TV, TR, kPreStagedZ, float>(h, F, C, F.S.v32, minv<TV>(F), ppv<TV>(F), r, z,
+                                             (TV *)C.r, done);
+  else if (staged_down<TV>(h, F, C))
+    pre_restrict<TV, TR, kPreStagedZ, TV>(h, F, C, vals<TV>(F), minv<TV>(F), ppv<TV>(F), r, z,
+                                          (TV *)C.r, done);
+  else
+    pre_restrict<TV, TR, kPreScaled, TV>(h, F, C, svals<TV>(F), minv<TV>(F), ppv<TV>(F), r, z,
+                                         (TV *)C.r, done);
+}
+
 // down step on level l: smoothing from zero, residual, restriction into
 // level l + 1's right-hand side; returns the buffer holding z_l
 template <typename TV, typename TR>
@@ -1694,8 +1727,7 @@ TV *launch_down(amg_hierarchy *h, int32_t l, const TR *r, const int32_t *done) {
   Level &C = h->lv[l + 1];
   TV *z = (TV *)F.z, *tmp = (TV *)F.y;
   if (h->params.pre == 1) {
-    pre_restrict<TV, TR, kPreScaled, TV>(h, F, C, svals<TV>(F), minv<TV>(F), ppv<TV>(F), r, z,
-                                         (TV *)C.r, done);
+    down_one_sweep<TV, TR>(h, F, C, r, z, done);
     return z;
   }
   const Geom g = geom(F.n);
@@ -2694,7 +2726,11 @@ amg_status time_vcycle(amg_hierarchy *h, int32_t reps, double *ms, double *bytes
   for (int32_t l = 0; l < L; ++l) {
     const double n = h->lv[l].n, z = (double)h->lv[l].nnz, nc = h->lv[l + 1].n;
     const double Vr = l == 0 ? 8.0 : V;
-    b += z * (V + 4) + 4 * (n + 1) + n * (Vr + 3 * V) + nc * (V + 4) + n * (3 * V + 4);
+    // the down step reads A M^-1, or A's exact FP32 copy where it stages M^-1 r
+    const double Vs =
+        l == 0 && V == 8.0 && h->lv[0].S.exact32 && staged_down<double>(h, h->lv[0], h->lv[1])
+            ? 4.0 : V;
+    b += z * (Vs + 4) + 4 * (n + 1) + n * (Vr + 3 * V) + nc * (V + 4) + n * (3 * V + 4);
     if (l > 0) b += z * (V + 4) + 4 * (n + 1) + 3 * V * n;
   }
   if (L > 0) {
@@ -2716,8 +2752,11 @@ double kernel_bytes(const amg_hierarchy *h, int32_t kernel, int32_t level) {
   const double n = F.n, nnz = (double)F.nnz, nc = C.n, nnzc = (double)C.nnz;
   const double Vr = level == 0 ? 8.0 : V;  // level 0 reads/writes the FP64 CG vectors
   switch (kernel) {
-    case 0:  // A M^-1, r, minv, p read; z, r_c written; segment offsets
-      return nnz * (V + 4) + 4 * (n + 1) + n * (Vr + 3 * V) + nc * (V + 4);
+    case 0:  // A M^-1 (or A from its exact FP32 copy), r, minv, p read; z, r_c
+             // written; segment offsets
+      return nnz * ((level == 0 && V == 8.0 && staged_down<double>(h, F, C) && F.S.exact32
+                         ? 4.0 : V) + 4) +
+             4 * (n + 1) + n * (Vr + 3 * V) + nc * (V + 4);
     case 1:  // A, r, z, minv read; y written (level 0: A from its exact FP32 copy if any)
       return nnz * ((level == 0 && F.S.exact32 ? 4.0 : V) + 4) + 4 * (n + 1) +
              n * (Vr + V + V + Vr);
@@ -2828,9 +2867,8 @@ amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t 
                                                           (const float *)F.r, (float *)F.z,
                                                           (float *)C.r, done);
         } else {
-          pre_restrict<double, double, kPreScaled, double>(
-              h, F, C, F.S.s64, F.sminv64, F.pp64, level == 0 ? h->r : (const double *)F.r,
-              (double *)F.z, (double *)C.r, done);
+          down_one_sweep<double, double>(h, F, C, level == 0 ? h->r : (const double *)F.r,
+                                         (double *)F.z, done);
         }
         break;
       case 1:  // post-smoothing on `level` (level 0: with the CG dot product)

@@ -322,7 +322,9 @@ def test_time_whole_vcycle_reports_bytes_and_rejects_kcycle():
         ms, by = h.time_kernel(5, 0, reps=5)
         assert ms > 0.0
         # the 7-point Laplacian's values are FP32 numbers: level 0 reads 4-byte values
-        assert abs(by - bench.vcycle_bytes(h.sizes(), h.nnzs(), V, h.sizes()[-1], a0=4.0)) < 1.0
+        # (in the FP64 hierarchy's down step too, which forms M^-1 r in LDS)
+        assert abs(by - bench.vcycle_bytes(h.sizes(), h.nnzs(), V, h.sizes()[-1], a0=4.0,
+                                           s0=4.0)) < 1.0
     hk = setup(A, cycle=amg.CYCLE_K)
     with pytest.raises(amg.AmgError):
         hk.time_kernel(5, 0, reps=2)
