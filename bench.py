@@ -503,7 +503,8 @@ def bench_batch(args):
     torch.cuda.synchronize()
     single = (time.perf_counter() - t0) * 1e3
     out = {"mode": "batch", "workload": "poisson7_%d^3_k%d_seed3_rtol1e-8_fp32prec" % (N, k),
-           "n": A.n, "k": k, "status": st, "tile": h.batch_tile(),
+           "n": A.n, "k": k, "status": st, "tile": h.batch_tiles()[0],
+           "vector_tile_shift": h.batch_tiles()[1],
            "batch_p50_ms": round(percentile(times, 50), 3),
            "batch_p99_ms": round(percentile(times, 99), 3),
            "ms_per_rhs": round(percentile(times, 50) / k, 3),

@@ -222,6 +222,9 @@ amg_status amg_pcg_solve_noalloc(amg_hierarchy *h, const double *b, double *x, d
  * row-major blocks B (device, read) and X (device, in: x0, out: x) is solved
  * with its own CG recurrence (own alpha, beta, stop test); the V-cycle runs
  * once per iteration on the whole block. info: host array of k, may be NULL.
+ * The first call with a given k allocates the block's buffers and autotunes
+ * the kernels' tiles (amg_batch_tile); later calls with that k repeat the
+ * same arithmetic bit for bit.
  * Returns AMG_OK if every column converged, else AMG_NOT_CONVERGED, or an
  * error; AMG_ERR_ARG for a hierarchy built with AMG_CYCLE_K or
  * AMG_COARSE_PCG (the block solve runs the V-cycle with the Cholesky
@@ -320,10 +323,14 @@ amg_status amg_matching_rounds(const amg_hierarchy *h, int32_t l, int32_t *round
 amg_status amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
                            double *ms, double *bytes);
 
-/* Column tile the batch solve's autotuner chose for the last k used with
- * this hierarchy (the V-cycle covers 64 / tile rows x tile columns per
- * wavefront); 0 before any batch solve. */
-amg_status amg_batch_tile(const amg_hierarchy *h, int32_t *tile);
+/* Tiles the batch solve's autotuner chose for the last k used with this
+ * hierarchy, by timing the block CG iteration as the solve runs it for each
+ * candidate: *tile, the column tile of the one-value kernels (64 / tile rows
+ * x tile columns per wavefront), and *vshift (may be NULL), the scale
+ * 2^vshift (vshift in -1..1) applied to the vector kernels' default tile
+ * (the power of two covering their kv = k / 2 or k / 4 column vectors per
+ * row, within 4..64). 0, 0 before any batch solve. */
+amg_status amg_batch_tile(const amg_hierarchy *h, int32_t *tile, int32_t *vshift);
 
 const char *amg_status_string(amg_status s);
 

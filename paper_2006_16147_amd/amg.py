@@ -125,7 +125,7 @@ def load_library():
         "amg_setup_times": (C.c_int, [V, V]),
         "amg_matching_rounds": (C.c_int, [V, I32, P(I32)]),
         "amg_time_kernel": (C.c_int, [V, I32, I32, I32, P(D), P(D)]),
-        "amg_batch_tile": (C.c_int, [V, P(I32)]),
+        "amg_batch_tile": (C.c_int, [V, P(I32), P(I32)]),
         "amg_status_string": (C.c_char_p, [C.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -300,9 +300,14 @@ class Hierarchy:
         return int(v.value)
 
     def batch_tile(self) -> int:
-        v = C.c_int32()
-        self._check(load_library().amg_batch_tile(self._h, C.byref(v)), "amg_batch_tile")
-        return int(v.value)
+        return self.batch_tiles()[0]
+
+    def batch_tiles(self):
+        """(one-value column tile, vector tile shift) chosen by the autotuner."""
+        v, sh = C.c_int32(), C.c_int32()
+        self._check(load_library().amg_batch_tile(self._h, C.byref(v), C.byref(sh)),
+                    "amg_batch_tile")
+        return int(v.value), int(sh.value)
 
     def time_kernel(self, kernel, level=0, reps=20):
         ms, by = C.c_double(), C.c_double()

@@ -524,10 +524,10 @@ amg_status amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int3
   return time_kernel(h, kernel, level, reps, ms, bytes);
 }
 
-amg_status amg_batch_tile(const amg_hierarchy *h, int32_t *kt) {
+amg_status amg_batch_tile(const amg_hierarchy *h, int32_t *kt, int32_t *vshift) {
   if (!h || !kt) return AMG_ERR_ARG;
   join_async(h);
-  return batch_kt(h, kt);
+  return batch_kt(h, kt, vshift);
 }
 
 const char *amg_status_string(amg_status s) {

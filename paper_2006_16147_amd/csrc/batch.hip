@@ -619,10 +619,10 @@ __global__ void __launch_bounds__(kBlock) kb_spmv(
 // kb_spmv with two consecutive columns per lane, each gathered block row
 // entry loaded as one 16-byte vector (k even, blocks 16-byte aligned, kv =
 // k / 2): half the gather instructions; the same sums in the same order
-template <int KT>
+template <int KT, typename TA>
 __global__ void __launch_bounds__(kBlock) kb_spmv_v(
     int32_t n, int32_t kv, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
-    const double *__restrict__ val, const double *__restrict__ Xin,
+    const TA *__restrict__ val, const double *__restrict__ Xin,
     const double *__restrict__ B, double *__restrict__ Out, float *__restrict__ OutF,
     double *__restrict__ partials, int32_t mode, const int32_t *__restrict__ stop) {
   if (stop && *stop) return;
@@ -640,18 +640,21 @@ __global__ void __launch_bounds__(kBlock) kb_spmv_v(
       double a0 = 0.0, a1 = 0.0;
       for (int32_t k0 = 0; k0 < w; k0 += kRowBatch) {
         int32_t c[kRowBatch];
-        double v[kRowBatch];
+        TA va[kRowBatch];  // as stored: converted at the product, not inside the guard
         double2 g[kRowBatch];
 #pragma unroll
         for (int u = 0; u < kRowBatch; ++u) {
           c[u] = 0;
-          v[u] = 0.0;
+          va[u] = 0;
           if (k0 + u < w) {
             const int32_t idx = base + (k0 + u) * kSlice;
             c[u] = ld_stream(&col[idx]);
-            v[u] = ld_stream(&val[idx]);
+            va[u] = ld_stream(&val[idx]);
           }
         }
+        double v[kRowBatch];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) v[u] = (double)va[u];
 #pragma unroll
         for (int u = 0; u < kRowBatch; ++u)
           g[u] = k0 + u < w ? X2[(int64_t)c[u] * kv + jv] : make_double2(0.0, 0.0);
@@ -933,6 +936,15 @@ __global__ void kb_all_done(int32_t k, const int32_t *done, int32_t *stop) {
   *stop = all;
 }
 
+// the vector kernels' tile for kv vectors per row: row_tile(kv) scaled by
+// the autotuned 2^vshift, kept within 4..64
+template <typename F>
+void with_vec_tile(const Batch &B, int32_t kv, F &&f) {
+  int32_t t = row_tile(kv);
+  t = B.vshift > 0 ? t << B.vshift : t >> -B.vshift;
+  with_row_tile(t < 4 ? 4 : (t > 64 ? 64 : t), f);
+}
+
 // ---------------------------------------------------------------------------
 // host
 // ---------------------------------------------------------------------------
@@ -1035,7 +1047,7 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
                                        : nullptr));
     constexpr int VW = Vec16<TV>::width;
     if (Rl && k % VW == 0 && aligned16(Rl) && aligned16(z) && aligned16(t))
-      with_row_tile(k / VW, [&](auto kt) {
+      with_vec_tile(B, k / VW, [&](auto kt) {
         constexpr int KV = decltype(kt)::value;
         const BGeom gv = bgeom(F.n, k / VW, KV);
         kb_pre_residual_v<TV, KV><<<gv.grid, kBlock, 0, s>>>(
@@ -1095,7 +1107,7 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
     Level &F = h->lv[l];
     constexpr int VW = Vec16<TV>::width;
     if (k % VW == 0 && aligned16(yout[l + 1]) && aligned16(zc[l]))
-      with_row_tile(k / VW, [&](auto kt) {
+      with_vec_tile(B, k / VW, [&](auto kt) {
         constexpr int KE = decltype(kt)::value;
         kb_prolong_v<TV, KE><<<egrid(F.n, k / VW, KE), kBlock, 0, s>>>(
             F.n, k / VW, F.aggp, ppv<TV>(F), yout[l + 1], zc[l], stop);
@@ -1138,7 +1150,7 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
         constexpr int VW = Vec16<TV>::width;
         if (k % VW == 0 && aligned16(R0) && aligned16(z) && aligned16(Z0)) {
           int32_t np = 0;
-          with_row_tile(k / VW, [&](auto kt) {
+          with_vec_tile(B, k / VW, [&](auto kt) {
             constexpr int KV = decltype(kt)::value;
             const BGeom gv = bgeom(F.n, k / VW, KV);
             kb_post_v<TV, double, double, KV, true><<<gv.grid, kBlock, 0, s>>>(
@@ -1173,12 +1185,18 @@ int32_t spmv_vec(amg_hierarchy *h, const double *Xin, const double *Bv, double *
       (OutF && reinterpret_cast<uintptr_t>(OutF) % 8 != 0))
     return 0;
   int32_t nparts = 0;
-  with_row_tile(k / 2, [&](auto kt) {
+  with_vec_tile(B, k / 2, [&](auto kt) {
     constexpr int KV = decltype(kt)::value;
     const BGeom g = bgeom(n, k / 2, KV);
-    kb_spmv_v<KV><<<g.grid, kBlock, 0, h->stream>>>(n, k / 2, L0.S.sptr, L0.S.col, L0.S.v64,
-                                                    Xin, Bv, Out, OutF, B.partials, mode,
-                                                    stop);
+    // level 0's exact FP32 copy of A when there is one: same numbers, half the bytes
+    if (L0.S.exact32)
+      kb_spmv_v<KV, float><<<g.grid, kBlock, 0, h->stream>>>(n, k / 2, L0.S.sptr, L0.S.col,
+                                                             L0.S.v32, Xin, Bv, Out, OutF,
+                                                             B.partials, mode, stop);
+    else
+      kb_spmv_v<KV, double><<<g.grid, kBlock, 0, h->stream>>>(n, k / 2, L0.S.sptr, L0.S.col,
+                                                              L0.S.v64, Xin, Bv, Out, OutF,
+                                                              B.partials, mode, stop);
     nparts = (int32_t)g.grid.x;
   });
   return nparts;
@@ -1200,7 +1218,7 @@ int32_t cg_update(amg_hierarchy *h, const int32_t *stop) {
   int32_t nparts = 0;
   if (k % 2 == 0 && aligned16(B.X) && aligned16(B.R) && aligned16(B.P) && aligned16(B.Q) &&
       (!B.Rf || reinterpret_cast<uintptr_t>(B.Rf) % 8 == 0)) {
-    with_row_tile(k / 2, [&](auto kt) {
+    with_vec_tile(B, k / 2, [&](auto kt) {
       constexpr int KU = decltype(kt)::value;
       const BGeom g = bgeom(n, k / 2, KU);
       kb_update_v<KU><<<g.grid, kBlock, 0, h->stream>>>(n, k / 2, B.X, B.R, B.Rf, B.P, B.Q,
@@ -1233,7 +1251,7 @@ void iteration_b(amg_hierarchy *h, int32_t maxit) {
   kb_all_done<<<1, 64, 0, s>>>(k, B.done, B.all_done);
   vcycle_b<TV, KT>(h, B.R, B.Z, bRz, maxit, stop);
   if (k % 2 == 0 && aligned16(B.Z) && aligned16(B.P))
-    with_row_tile(k / 2, [&](auto kt) {
+    with_vec_tile(B, k / 2, [&](auto kt) {
       constexpr int KE = decltype(kt)::value;
       kb_xpay_v<KE><<<egrid(n, k / 2, KE), kBlock, 0, s>>>(n, k / 2, B.Z, B.P, B.col, B.done,
                                                             stop);
@@ -1386,59 +1404,81 @@ amg_status ensure_batch(amg_hierarchy *h, int32_t k) {
   return AMG_OK;
 }
 
-// Autotuner: time the level-0 post-smoothing kernel for each column tile.
-template <typename TV, int KT>
-float time_post(amg_hierarchy *h) {
-  Batch &B = *h->batch;
-  Level &L0 = h->lv[0];
-  if (h->lv.size() < 2) return 0.f;
-  const BGeom g = bgeom(L0.n, B.k, KT);
-  hipEvent_t e0, e1;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
-  auto go = [&]() {
-    kb_post<TV, double, double, KT, true><<<tgrid(g, B.k, KT), kBlock, 0, h->stream>>>(
-        L0.n, B.k, L0.S.sptr, L0.S.col, vals<TV>(L0), minv<TV>(L0), B.R,
-        (const TV *)B.z[0], B.Z, B.partials, h->zero_flag);
-  };
-  go();
-  (void)hipEventRecord(e0, h->stream);
-  for (int r = 0; r < 5; ++r) go();
-  (void)hipEventRecord(e1, h->stream);
-  (void)hipEventSynchronize(e1);
-  float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  return ms;
+__global__ void kb_fill_f64(double *p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
+// Autotuner: the block CG iteration as the solve runs it (direct launches),
+// timed for every candidate pair of the one-value kernels' column tile kt
+// and the vector kernels' tile shift, so that the choice is made on the
+// kernels that run. The state is synthetic but valid (X = 0, right-hand
+// sides of ones, then the solve's own prologue, rtol 0), so every kernel
+// does its full work; the solve's prologue overwrites it afterwards. The
+// tiles set how rows are dealt to blocks and hence the order in which each
+// column's dot products are summed: the choice is kept for the hierarchy
+// and k, so later solves repeat the same sums.
 template <typename TV>
 amg_status autotune(amg_hierarchy *h) {
   Batch &B = *h->batch;
-  // contents of the blocks do not matter for timing; start from zeros
-  const size_t e0 = (size_t)h->lv[0].n * B.k * sizeof(double);
-  AMG_HIP(hipMemsetAsync(B.R, 0, e0, h->stream));
-  AMG_HIP(hipMemsetAsync(B.z[0], 0, (size_t)h->lv[0].n * B.k * sizeof(TV), h->stream));
+  hipStream_t s = h->stream;
+  const int32_t n = h->lv[0].n, k = B.k;
+  const int64_t nk = (int64_t)n * k;
+  kb_fill_f64<<<ceil_div(nk, kBlock), kBlock, 0, s>>>(B.X, nk, 0.0);
+  kb_fill_f64<<<ceil_div(nk, kBlock), kBlock, 0, s>>>(B.Bp, nk, 1.0);
+  B.kt = 16;
+  B.vshift = 0;
+  kb_init_cols<<<ceil_div(k, 64), 64, 0, s>>>(k, 0.0, INT32_MAX, B.col, B.iter, B.done,
+                                              B.all_done);
+  int32_t np = 0;
+  spmv_mode(h, B.X, B.Bp, B.R, 1, &np);
+  bfinalize(h, bInit, np, INT32_MAX, nullptr);
+  kb_all_done<<<1, 64, 0, s>>>(k, B.done, B.all_done);
+  dispatch_vcycle<TV>(h, B.R, B.Z, bRz0, INT32_MAX, B.all_done);
+  small_kernel(h, 1);  // P = Z
+  AMG_HIP(hipGetLastError());
+  hipEvent_t e0, e1;
+  AMG_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return AMG_ERR_HIP;
+  }
   const int cands[5] = {4, 8, 16, 32, 64};
+  const int shifts[3] = {0, -1, 1};
+  const int nshift = k % 2 == 0 ? 3 : 1;  // vector kernels run only for even k
   float best = 0.f;
-  int best_kt = 0;
+  int best_kt = 16, best_vs = 0;
+  bool first = true;
+  amg_status st = AMG_OK;
   for (int c : cands) {
-    if (c > 4 && c / 2 >= B.k) break;  // wider tiles would only add idle lanes
-    float t = 0.f;
-    switch (c) {
-      case 4: t = time_post<TV, 4>(h); break;
-      case 8: t = time_post<TV, 8>(h); break;
-      case 16: t = time_post<TV, 16>(h); break;
-      case 32: t = time_post<TV, 32>(h); break;
-      default: t = time_post<TV, 64>(h); break;
-    }
-    if (best_kt == 0 || t < best) {
-      best = t;
-      best_kt = c;
+    if (c > 4 && c / 2 >= k) break;  // wider tiles would only add idle lanes
+    for (int q = 0; q < nshift && st == AMG_OK; ++q) {
+      B.kt = c;
+      B.vshift = shifts[q];
+      dispatch_iteration<TV>(h, INT32_MAX);  // warm
+      float t = 0.f;
+      if (hipEventRecord(e0, s) != hipSuccess) st = AMG_ERR_HIP;
+      for (int r = 0; r < 2 && st == AMG_OK; ++r) dispatch_iteration<TV>(h, INT32_MAX);
+      if (st == AMG_OK &&
+          (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+           hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        st = AMG_ERR_HIP;
+      if (st == AMG_OK && (first || t < best)) {
+        best = t;
+        best_kt = c;
+        best_vs = shifts[q];
+        first = false;
+      }
     }
   }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   B.kt = best_kt;
+  B.vshift = best_vs;
+  if (st != AMG_OK) {
+    (void)hipGetLastError();
+    return st;
+  }
   AMG_HIP(hipGetLastError());
   return AMG_OK;
 }
@@ -1456,8 +1496,9 @@ void free_batch(Batch *b, int device, hipStream_t s) {
   delete b;
 }
 
-amg_status batch_kt(const amg_hierarchy *h, int32_t *kt) {
+amg_status batch_kt(const amg_hierarchy *h, int32_t *kt, int32_t *vshift) {
   *kt = h->batch ? h->batch->kt : 0;
+  if (vshift) *vshift = h->batch ? h->batch->vshift : 0;
   return AMG_OK;
 }
 
@@ -1472,7 +1513,6 @@ amg_status pcg_batch(amg_hierarchy *h, int32_t k, const double *Bu, double *Xu, 
   if (B.kt == 0) {
     if (fp32) AMG_TRY(autotune<float>(h));
     else AMG_TRY(autotune<double>(h));
-    if (B.kt == 0) B.kt = 32;
   }
   // capture one iteration (all kernels read their scalars from device memory)
   if (!B.exec && !(h->params.flags & AMG_FLAG_NO_GRAPH)) {

@@ -175,7 +175,10 @@ struct Coarse {
 // FP64 CG blocks on level 0 and per-column CG scalars.
 struct Batch {
   int32_t k = 0;
-  int32_t kt = 0;  // autotuned column tile (rows per wavefront = 64 / kt)
+  int32_t kt = 0;  // autotuned column tile of the one-value kernels (rows per
+                   // wavefront = 64 / kt)
+  int32_t vshift = 0;  // autotuned: the vector kernels (2 FP64 or 4 FP32 columns per
+                       // lane, kv vectors per row) use tiles of row_tile(kv) x 2^vshift
   std::vector<void *> r, z, t, y;  // per level, hierarchy precision
   // level-0 CG blocks, rows in the aggregate-major order of level 0
   double *X = nullptr, *Bp = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr;
@@ -292,7 +295,7 @@ amg_status pcg_noalloc(amg_hierarchy *h, const double *b, double *x, double rtol
                        amg_solve_info *info);
 amg_status pcg_batch(amg_hierarchy *h, int32_t k, const double *B, double *X, double rtol,
                      int32_t maxit, amg_solve_info *info);
-amg_status batch_kt(const amg_hierarchy *h, int32_t *kt);
+amg_status batch_kt(const amg_hierarchy *h, int32_t *kt, int32_t *vshift);
 amg_status time_kernel(amg_hierarchy *h, int32_t kernel, int32_t level, int32_t reps,
                        double *ms, double *bytes);
 

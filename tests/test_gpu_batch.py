@@ -52,7 +52,8 @@ def test_batch_columns_equal_single_solves_fp64(orc, k):
     h = setup(A)
     st, infos, X = _batch(h, B)
     assert st == 0 and all(i["converged"] for i in infos)
-    assert h.batch_tile() in (4, 8, 16, 32, 64)
+    kt, vshift = h.batch_tiles()
+    assert kt in (4, 8, 16, 32, 64) and vshift in (-1, 0, 1)
     ho = orc.Hierarchy(A)
     for j in range(k):
         st1, i1, x1 = _single(h, B[:, j])
