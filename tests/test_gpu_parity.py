@@ -67,6 +67,21 @@ def test_setup_random_spd_with_w(orc, seed):
     assert_same_hierarchy(h, ho)
 
 
+@pytest.mark.parametrize("seed,hub", [(11, 0), (12, 400)])
+def test_setup_large_random_graph_worklist_matching(orc, seed, hub):
+    """Graphs of at least 2^18 vertices are matched by rounds over the lists
+    of vertices that can change: on irregular random SPD graphs with signed
+    w (and one with a hub of degree 400) the hierarchy must still be the
+    oracle's, bit for bit."""
+    A = inputs.random_spd_graph(300000, 6.0, seed=seed, hub_degree=hub)
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.5, 2.0, A.n) * rng.choice([-1.0, 1.0], A.n)
+    st, h = setup_status(A, w=w, max_coarse=100)
+    assert st == 0
+    ho = orc.Hierarchy(A, w=w, max_coarse=100)
+    assert_same_hierarchy(h, ho)
+
+
 def test_setup_long_rows_take_block_path(orc):
     """A hub vertex of degree 300 makes coarse rows exceed the per-thread
     buffer; the block-per-row Galerkin path must give the same bits."""
