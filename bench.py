@@ -21,6 +21,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -226,19 +227,53 @@ def kernel_summary(trace_csv):
             _short(name), len(ds), sum(ds) / len(ds), min(ds), max(ds), sum(ds) / 1e3, 100 * sum(ds) / tot))
     out += ["", "Level-0 solve kernels, full launches only (largest grid, early exits left out):",
             "", "| kernel | full launches | avg us | min us | max us |", "|---|---|---|---|---|"]
-    for frag in ("k_pre_restrict<double, double, 0", "k_post<double, double, double, true,",
-                 "k_spmv_dot<float>", "k_pre_restrict<float, double, 0",
-                 "k_post<float, double, double, true,"):
-        for name, v in per.items():
-            if frag not in name:
-                continue
-            top = max(g for _, g in v)
-            ds = sorted(d for d, g in v if g == top)
-            med = ds[len(ds) // 2]
-            full = [d for d in ds if d >= 0.5 * med]
-            out.append("| `%s` | %d | %.2f | %.1f | %.1f |" % (
-                _short(name), len(full), sum(full) / len(full), min(full), max(full)))
+    level0 = re.compile(r"^(k_pre_restrict|k_post|k_spmv_dot)(_lds)?<")
+    for name, v in sorted(per.items(), key=lambda kv: -sum(d for d, _ in kv[1])):
+        if not level0.match(_short(name)):
+            continue
+        top = max(g for _, g in v)
+        ds = sorted(d for d, g in v if g == top)
+        med = ds[len(ds) // 2]
+        full = [d for d in ds if d >= 0.5 * med]
+        if sum(full) / len(full) < 20.0:  # a coarse level's launches, not level 0's
+            continue
+        out.append("| `%s` | %d | %.2f | %.1f | %.1f |" % (
+            _short(name), len(full), sum(full) / len(full), min(full), max(full)))
     print("\n".join(out))
+
+
+def overlap_summary(trace_csv):
+    """GPU busy fraction and cross-stream overlap of a rocprofv3 kernel trace:
+    the time covered by at least one kernel, and by kernels of at least two
+    different queues at once, over the span from the first kernel's start to
+    the last one's end (a serving run: each slot has its own stream)."""
+    rows = _counter_rows(trace_csv)
+    ev = []
+    for r in rows:
+        q = r.get("Queue_Id") or r.get("Stream_Id") or "0"
+        s0, s1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        if s1 > s0:
+            ev.append((s0, 1, q))
+            ev.append((s1, -1, q))
+    ev.sort()
+    active = {}
+    busy = multi = 0
+    t_prev = ev[0][0]
+    for t, d, q in ev:
+        if t > t_prev:
+            live = sum(1 for c in active.values() if c > 0)
+            if live >= 1:
+                busy += t - t_prev
+            if live >= 2:
+                multi += t - t_prev
+            t_prev = t
+        active[q] = active.get(q, 0) + d
+    span = ev[-1][0] - ev[0][0]
+    out = {"kernels": len(rows), "queues": len({e[2] for e in ev}), "span_ms": span / 1e6,
+           "busy_ms": busy / 1e6, "busy_fraction": busy / span,
+           "overlap_ms": multi / 1e6, "overlap_fraction_of_busy": multi / busy if busy else 0.0}
+    print(json.dumps(out))
+    return out
 
 
 def bench_kcycle(args):
@@ -520,7 +555,8 @@ def bench_serve(args):
     from paper_2006_16147_amd import serve
 
     serve.main(["--rates", args.rates, "--count", str(args.count), "--warmup",
-                str(max(0, args.count // 10)), "--slots", str(args.slots)])
+                str(max(0, args.count // 20)), "--slots", str(args.slots)]
+               + ([] if args.budget_gb is None else ["--budget-gb", str(args.budget_gb)]))
 
 
 def physical_cores():
@@ -616,7 +652,11 @@ def main():
                              "smoothed"],
                     help="headline (default): the 160^3 benchmark line; the others print "
                          "their own JSON lines")
-    ap.add_argument("--rates", default="10,50,200,500", help="serve mode: arrival rates /s")
+    ap.add_argument("--rates", default="10,20,50,100,200,500",
+                    help="serve mode: arrival rates /s")
+    ap.add_argument("--budget-gb", type=float, default=None,
+                    help="serve mode: GiB the server may reserve (default: the device's "
+                         "memory less 32 GiB)")
     ap.add_argument("--count", type=int, default=200, help="serve mode: requests per rate")
     ap.add_argument("--slots", type=int, default=4, help="serve mode: concurrent slots")
     ap.add_argument("--profile-pass", action="store_true",
@@ -625,9 +665,14 @@ def main():
                     help="write profiles/traffic.json from two counter runs")
     ap.add_argument("--kernel-summary", metavar="KERNEL_TRACE_CSV",
                     help="print a markdown summary of a rocprofv3 kernel trace")
+    ap.add_argument("--overlap-summary", metavar="KERNEL_TRACE_CSV",
+                    help="print the GPU busy fraction and cross-queue overlap of a trace")
     args = ap.parse_args()
     if args.kernel_summary:
         kernel_summary(args.kernel_summary)
+        return
+    if args.overlap_summary:
+        overlap_summary(args.overlap_summary)
         return
     if args.ingest_pmc:
         ingest_pmc(*args.ingest_pmc)

@@ -16,6 +16,13 @@
  *                      coarsest-size stop rule
  * The coarsest level is solved by a dense Cholesky factorisation.
  *
+ * Every function is pinned by tests against values the paper prints, closed
+ * forms, dense or library computations or brute force. One printed figure is
+ * not reproduced: the operator complexity of the smoothed-prolongator
+ * hierarchy in Section 5 (80^3); for that figure parity is unpinned, while
+ * the smoothed hierarchy itself is pinned (dense products and the
+ * supplement's convergence constant for the smoothed prolongator).
+ *
  * Arithmetic: IEEE binary64, round to nearest, compiled with
  * -ffp-contract=off; every sum runs left to right starting from its first
  * term, in the order each function states.

@@ -2802,8 +2802,10 @@ amg_status time_in_solve(amg_hierarchy *h, int32_t kernel, int32_t reps, double 
   k_xpay<<<grid1(n), kBlock, 0, s>>>(n, h->z, h->p, h->scal, 1, done);
   h->probe_ev.assign(2 * (size_t)reps, nullptr);
   amg_status st = AMG_OK;
+  // timing-only events: no system-scope release at the timed dispatch's end
+  // (that writeback of L2 is not part of the kernel inside the solve)
   for (auto &e : h->probe_ev)
-    if (hipEventCreate(&e) != hipSuccess) st = AMG_ERR_HIP;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) st = AMG_ERR_HIP;
   if (st == AMG_OK) {
     h->probe_next = 0;
     h->probe_id = kernel;

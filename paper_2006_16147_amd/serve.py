@@ -11,7 +11,8 @@ are started on other slots and their GPU work overlaps:
   operator id; a repeated operator skips the setup (the reuse the paper
   motivates for time-dependent and nonlinear sequences). Idle entries are
   evicted least-recently-used when memory is needed.
-* Admission by footprint: a cache miss reserves the library's footprint
+* Admission by footprint (by default the device's memory less a headroom of
+  32 GiB, ~236 GiB on one MI355X): a cache miss reserves the library's footprint
   estimate for the operator (amg_estimate_footprint) plus the solve's
   vectors; a hit reserves the vectors only. A request that cannot fit even
   into an empty device is rejected; one that does not fit now waits. Later
@@ -315,6 +316,17 @@ class GpuBackend:
         self.keep_x = keep_x
         amg.load_library()
 
+    # Device memory the admission budget leaves alone: the library pool's
+    # reserve of freed blocks (up to 8 GiB), the torch allocator's cached
+    # request arrays, the runtime's per-dispatch scratch (private segments)
+    # and pool fragmentation. With 12 GiB left, a 2000-request stream filled
+    # the device and a dispatch failed to get its scratch.
+    HEADROOM = 32 << 30
+
+    def default_budget(self) -> int:
+        _, total = self.torch.cuda.mem_get_info(self.dev)
+        return max(0, int(total) - self.HEADROOM)
+
     def make_slot(self, i):
         torch = self.torch
         torch.cuda.set_device(self.dev)
@@ -380,14 +392,17 @@ def main(argv=None):
     ap.add_argument("--count", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--budget-gb", type=float, default=None,
+                    help="GiB the server may reserve (default: device memory less 32 GiB)")
     ap.add_argument("--seed", type=int, default=4)
     args = ap.parse_args(argv)
     backend = GpuBackend()
     rows = []
     for rate in [float(r) for r in args.rates.split(",")]:
         reqs = requests_from_stream(inputs.serving_requests(args.count, rate, seed=args.seed))
-        srv = Server(backend, slots=args.slots, budget_bytes=int(args.budget_gb * (1 << 30)))
+        budget = (int(args.budget_gb * (1 << 30)) if args.budget_gb is not None
+                  else backend.default_budget())
+        srv = Server(backend, slots=args.slots, budget_bytes=budget)
         t0 = time.perf_counter()
         res = srv.run(reqs)
         wall = time.perf_counter() - t0
@@ -395,7 +410,8 @@ def main(argv=None):
         summ.update({"rate_per_s": rate, "wall_s": wall, "setups": srv.stats["setups"],
                      "evictions": srv.stats["evictions"],
                      "max_concurrency": srv.stats["max_concurrency"],
-                     "peak_reserved_gb": srv.peak_used / (1 << 30)})
+                     "budget_gib": budget / (1 << 30),
+                     "peak_reserved_gib": srv.peak_used / (1 << 30)})
         srv.close()
         rows.append(summ)
         print(json.dumps(summ), flush=True)
