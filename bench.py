@@ -110,10 +110,10 @@ def load_traffic(kernel_key):
 
 
 CALIB_BYTES = 512 << 20  # plain device copy used to scale the HBM counters
-TRAFFIC_KERNELS = {  # kernel-name fragment (its largest launches are level 0's) -> key
-    "fp64_level0_0": "k_pre_restrict<double, double, 0",
-    "fp64_level0_1": "k_post<double, double, double, true,",
-    "fp64_level0_4": "k_spmv_dot",
+TRAFFIC_KERNELS = {  # kernel-name pattern (its largest launches are level 0's) -> key
+    "fp64_level0_0": r"k_pre_restrict(_lds)?<double, double, [02],",
+    "fp64_level0_1": r"k_post(_lds)?<double, double, double, true,",
+    "fp64_level0_4": r"k_spmv_dot(_lds)?<",
 }
 
 
@@ -164,7 +164,7 @@ def ingest_pmc(fetch_csv, write_csv):
         scale = kib_copy * 1024.0 / CALIB_BYTES  # counter bytes per real byte moved
         out["%s_scale" % counter] = scale
         for key, frag in TRAFFIC_KERNELS.items():
-            match = [r for r in rows if frag in r["Kernel_Name"]]
+            match = [r for r in rows if re.search(frag, r["Kernel_Name"])]
             top = max((int(r.get("Grid_Size", 0)) for r in match), default=0)
             vals = [float(r["Counter_Value"]) * 1024.0 / scale for r in match
                     if int(r.get("Grid_Size", 0)) == top]

@@ -765,15 +765,15 @@ __global__ void kb_xpay(int32_t n, int32_t k, const double *__restrict__ Z,
   P[o] = copy ? Z[o] : Z[o] + colv[cBeta * k + j] * P[o];
 }
 
-// the CG update with two columns per thread (k even, blocks 16-byte
-// aligned); a converged column's half of each vector is stored back
-// unchanged, and its partial sum is zero as in the one-value form
+// r -= alpha q with two columns per thread (k even, blocks 16-byte aligned),
+// the FP32 copy of r and the (r, r) partials; a converged column's half of r
+// is stored back unchanged, and its partial sum is zero as in the one-value
+// form. x += alpha p is left to kb_xpay_v, which reads p anyway: one block
+// read fewer per iteration, the same arithmetic.
 template <int KT>
 __global__ void __launch_bounds__(kBlock) kb_update_v(int32_t n, int32_t kv,
-                                                      double *__restrict__ X,
                                                       double *__restrict__ R,
                                                       float *__restrict__ Rf,
-                                                      const double *__restrict__ P,
                                                       const double *__restrict__ Q,
                                                       const double *__restrict__ colv,
                                                       const int32_t *__restrict__ done,
@@ -788,27 +788,23 @@ __global__ void __launch_bounds__(kBlock) kb_update_v(int32_t n, int32_t kv,
   const double a1 = live1 ? colv[cAlpha * k + j + 1] : 0.0;
   double d0 = 0.0, d1 = 0.0;
   if (live0 || live1) {
-    double2 *X2 = reinterpret_cast<double2 *>(X), *R2 = reinterpret_cast<double2 *>(R);
-    const double2 *P2 = reinterpret_cast<const double2 *>(P);
+    double2 *R2 = reinterpret_cast<double2 *>(R);
     const double2 *Q2 = reinterpret_cast<const double2 *>(Q);
     float2 *Rf2 = reinterpret_cast<float2 *>(Rf);
     for (int64_t grp = first_group(); grp * (kBlock / KT) < n; grp += gridDim.x) {
       const int32_t row = (int32_t)(grp * (kBlock / KT)) + (int32_t)threadIdx.x / KT;
       if (row >= n) continue;
       const int64_t o = (int64_t)row * kv + jv;
-      double2 x = X2[o], r = R2[o];
-      const double2 p = P2[o], q = Q2[o];
+      double2 r = R2[o];
+      const double2 q = Q2[o];
       if (live0) {
-        x.x += a0 * p.x;
         r.x = r.x - a0 * q.x;
         d0 += r.x * r.x;
       }
       if (live1) {
-        x.y += a1 * p.y;
         r.y = r.y - a1 * q.y;
         d1 += r.y * r.y;
       }
-      X2[o] = x;
       R2[o] = r;
       if (Rf) Rf2[o] = make_float2((float)r.x, (float)r.y);
     }
@@ -818,22 +814,33 @@ __global__ void __launch_bounds__(kBlock) kb_update_v(int32_t n, int32_t kv,
   column_partial<KT>(d1, valid, j + 1, k, partials);
 }
 
-// p = z + beta p with two columns per thread (k even, blocks 16-byte
-// aligned); a converged column's half of the vector is stored back unchanged
+// The end of an iteration with two columns per thread (k even, blocks
+// 16-byte aligned): x += alpha p for the columns whose alpha this iteration
+// set (xpend; also those that converged or broke down since, which is why
+// the kernel runs when every column has stopped), then p = z + beta p for
+// the live ones; a stopped column's half of p is stored back unchanged.
 template <int KT>
 __global__ void kb_xpay_v(int32_t n, int32_t kv, const double *__restrict__ Z,
-                          double *__restrict__ P, const double *__restrict__ colv,
-                          const int32_t *__restrict__ done, const int32_t *__restrict__ stop) {
-  if (*stop) return;
+                          double *__restrict__ P, double *__restrict__ X,
+                          const double *__restrict__ colv, const int32_t *__restrict__ done,
+                          const int32_t *__restrict__ xpend) {
   const int32_t jv = blockIdx.y * KT + threadIdx.x % KT;
   const int64_t i = (int64_t)blockIdx.x * (kBlock / KT) + threadIdx.x / KT;
   if (jv >= kv || i >= n) return;
   const int32_t k = 2 * kv, j = 2 * jv;
   const bool live0 = done[j] == 0, live1 = done[j + 1] == 0;
-  if (!live0 && !live1) return;
+  const bool xp0 = xpend[j] != 0, xp1 = xpend[j + 1] != 0;
+  if (!live0 && !live1 && !xp0 && !xp1) return;
   const int64_t o = i * kv + jv;
-  const double2 z = reinterpret_cast<const double2 *>(Z)[o];
   double2 v = reinterpret_cast<double2 *>(P)[o];
+  if (xp0 || xp1) {
+    double2 x = reinterpret_cast<double2 *>(X)[o];
+    if (xp0) x.x += colv[cAlpha * k + j] * v.x;
+    if (xp1) x.y += colv[cAlpha * k + j + 1] * v.y;
+    reinterpret_cast<double2 *>(X)[o] = x;
+  }
+  if (!live0 && !live1) return;
+  const double2 z = reinterpret_cast<const double2 *>(Z)[o];
   if (live0) v.x = z.x + colv[cBeta * k + j] * v.x;
   if (live1) v.y = z.y + colv[cBeta * k + j + 1] * v.y;
   reinterpret_cast<double2 *>(P)[o] = v;
@@ -849,13 +856,14 @@ __global__ void kb_zero_cols(int32_t n, int32_t k, double *__restrict__ X,
 }
 
 __global__ void kb_init_cols(int32_t k, double rtol, int32_t maxit, double *colv, int32_t *iter,
-                             int32_t *done, int32_t *stop) {
+                             int32_t *done, int32_t *xpend, int32_t *stop) {
   const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j == 0) *stop = 0;
   if (j >= k) return;
   for (int f = 0; f < kColFields; ++f) colv[f * k + j] = 0.0;
   colv[cRtol * k + j] = rtol;
   iter[j] = 0;
+  xpend[j] = 0;
   done[j] = maxit < 0 ? 2 : 0;
 }
 
@@ -864,10 +872,14 @@ __global__ void __launch_bounds__(kBlock) kb_finalize(int32_t op, int32_t nparts
                                                       const double *__restrict__ partials,
                                                       double *__restrict__ colv,
                                                       int32_t *__restrict__ iter,
-                                                      int32_t *__restrict__ done, int32_t maxit,
+                                                      int32_t *__restrict__ done,
+                                                      int32_t *__restrict__ xpend, int32_t maxit,
                                                       const int32_t *__restrict__ stop) {
-  if (stop && *stop) return;
   const int32_t j = blockIdx.x;
+  // the previous iteration's x update has been applied by now (also in
+  // iterations queued after every column stopped)
+  if (op == bPq && threadIdx.x == 0) xpend[j] = 0;
+  if (stop && *stop) return;
   __shared__ double sh[2][kBlock / kWave];
   const int nv = op == bInit ? 2 : 1;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -905,8 +917,12 @@ __global__ void __launch_bounds__(kBlock) kb_finalize(int32_t op, int32_t nparts
   switch (op) {
     case bPq:
       c[cPq * k + j] = tot[0];
-      if (!(tot[0] > 0.0)) done[j] = 3;
-      else c[cAlpha * k + j] = c[cRho * k + j] / tot[0];
+      if (!(tot[0] > 0.0)) {
+        done[j] = 3;
+      } else {
+        c[cAlpha * k + j] = c[cRho * k + j] / tot[0];
+        xpend[j] = 1;
+      }
       break;
     case bRr:
       c[cRr * k + j] = tot[0];
@@ -1001,7 +1017,7 @@ const float *ppv<float>(const Level &L) { return L.pp32; }
 void bfinalize(amg_hierarchy *h, int32_t op, int32_t nparts, int32_t maxit, const int32_t *stop) {
   Batch &B = *h->batch;
   kb_finalize<<<B.k, kBlock, 0, h->stream>>>(op, nparts, B.k, B.partials, B.col, B.iter, B.done,
-                                            maxit, stop);
+                                            B.xpend, maxit, stop);
 }
 
 // one block V-cycle: Z = B_0 R on all k columns; with rz_op >= 0 also the
@@ -1212,17 +1228,24 @@ int32_t launch_update(amg_hierarchy *h, const int32_t *stop) {
   return (int32_t)g.grid.x;
 }
 
+// whether the CG update and p = z + beta p take their two-column forms
+// (x += alpha p then moves into the latter)
+bool vec_cg(const Batch &B) {
+  return B.k % 2 == 0 && aligned16(B.X) && aligned16(B.R) && aligned16(B.P) &&
+         aligned16(B.Q) && aligned16(B.Z) &&
+         (!B.Rf || reinterpret_cast<uintptr_t>(B.Rf) % 8 == 0);
+}
+
 int32_t cg_update(amg_hierarchy *h, const int32_t *stop) {
   Batch &B = *h->batch;
   const int32_t n = h->lv[0].n, k = B.k;
   int32_t nparts = 0;
-  if (k % 2 == 0 && aligned16(B.X) && aligned16(B.R) && aligned16(B.P) && aligned16(B.Q) &&
-      (!B.Rf || reinterpret_cast<uintptr_t>(B.Rf) % 8 == 0)) {
+  if (vec_cg(B)) {
     with_vec_tile(B, k / 2, [&](auto kt) {
       constexpr int KU = decltype(kt)::value;
       const BGeom g = bgeom(n, k / 2, KU);
-      kb_update_v<KU><<<g.grid, kBlock, 0, h->stream>>>(n, k / 2, B.X, B.R, B.Rf, B.P, B.Q,
-                                                        B.col, B.done, B.partials, stop);
+      kb_update_v<KU><<<g.grid, kBlock, 0, h->stream>>>(n, k / 2, B.R, B.Rf, B.Q, B.col,
+                                                        B.done, B.partials, stop);
       nparts = (int32_t)g.grid.x;
     });
   } else {
@@ -1250,11 +1273,11 @@ void iteration_b(amg_hierarchy *h, int32_t maxit) {
   bfinalize(h, bRr, cg_update(h, stop), maxit, stop);
   kb_all_done<<<1, 64, 0, s>>>(k, B.done, B.all_done);
   vcycle_b<TV, KT>(h, B.R, B.Z, bRz, maxit, stop);
-  if (k % 2 == 0 && aligned16(B.Z) && aligned16(B.P))
+  if (vec_cg(B))
     with_vec_tile(B, k / 2, [&](auto kt) {
       constexpr int KE = decltype(kt)::value;
-      kb_xpay_v<KE><<<egrid(n, k / 2, KE), kBlock, 0, s>>>(n, k / 2, B.Z, B.P, B.col, B.done,
-                                                            stop);
+      kb_xpay_v<KE><<<egrid(n, k / 2, KE), kBlock, 0, s>>>(n, k / 2, B.Z, B.P, B.X, B.col,
+                                                            B.done, B.xpend);
     });
   else
     with_row_tile(k, [&](auto kt) {
@@ -1372,6 +1395,7 @@ amg_status alloc_batch(amg_hierarchy *h, int32_t k) {
   AMG_TRY(balloc(h, (void **)&B.col, sizeof(double) * kColFields * (size_t)k));
   AMG_TRY(balloc(h, (void **)&B.iter, sizeof(int32_t) * (size_t)k));
   AMG_TRY(balloc(h, (void **)&B.done, sizeof(int32_t) * (size_t)k));
+  AMG_TRY(balloc(h, (void **)&B.xpend, sizeof(int32_t) * (size_t)k));
   AMG_TRY(balloc(h, (void **)&B.all_done, sizeof(int32_t) * 4));
   AMG_HIP(hipHostMalloc((void **)&B.col_host, sizeof(double) * kColFields * (size_t)k));
   AMG_HIP(hipHostMalloc((void **)&B.iter_host, sizeof(int32_t) * (size_t)k));
@@ -1429,7 +1453,7 @@ amg_status autotune(amg_hierarchy *h) {
   B.kt = 16;
   B.vshift = 0;
   kb_init_cols<<<ceil_div(k, 64), 64, 0, s>>>(k, 0.0, INT32_MAX, B.col, B.iter, B.done,
-                                              B.all_done);
+                                              B.xpend, B.all_done);
   int32_t np = 0;
   spmv_mode(h, B.X, B.Bp, B.R, 1, &np);
   bfinalize(h, bInit, np, INT32_MAX, nullptr);
@@ -1534,7 +1558,8 @@ amg_status pcg_batch(amg_hierarchy *h, int32_t k, const double *Bu, double *Xu, 
   const int32_t pgrid = ceil_div((int64_t)n * k, kBlock);
   kb_permute_rows<true><<<pgrid, kBlock, 0, s>>>(n, k, perm0, Xu, B.X);
   kb_permute_rows<true><<<pgrid, kBlock, 0, s>>>(n, k, perm0, Bu, B.Bp);
-  kb_init_cols<<<ceil_div(k, 64), 64, 0, s>>>(k, rtol, maxit, B.col, B.iter, B.done, B.all_done);
+  kb_init_cols<<<ceil_div(k, 64), 64, 0, s>>>(k, rtol, maxit, B.col, B.iter, B.done, B.xpend,
+                                              B.all_done);
   int32_t np = 0;
   spmv_mode(h, B.X, B.Bp, B.R, 1, &np);
   bfinalize(h, bInit, np, maxit, nullptr);

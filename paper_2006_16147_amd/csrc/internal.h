@@ -188,6 +188,9 @@ struct Batch {
   double *partials = nullptr;  // 2 x kBatchBlocks x k
   double *col = nullptr;       // per-column scalars, 8 x k (see batch.hip)
   int32_t *iter = nullptr, *done = nullptr, *all_done = nullptr;
+  // per column: 1 while the iteration's x += alpha p is still to be applied
+  // (by p = z + beta p in the two-column form, which reads p anyway)
+  int32_t *xpend = nullptr;
   double *col_host = nullptr;  // pinned mirrors
   int32_t *iter_host = nullptr, *done_host = nullptr;
   hipGraph_t graph = nullptr;

@@ -492,7 +492,11 @@ __device__ __forceinline__ TV sell_dot_lds(const uint16_t *__restrict__ lcol,
   return acc;
 }
 
-// k_pre_restrict with the tile of block b = its segment rows (tiles hseg)
+// k_pre_restrict with the tile of block b = its segment rows (tiles hseg).
+// The LDS kernels take their tiles in XCD-aware order (xcd_block): each XCD
+// works down one contiguous range of tiles, so a tile's staged neighbours
+// were mostly just loaded into the same L2 by the tiles before it (160^3
+// FP64 down step 73.6 -> 64.4 us). The partial sums stay indexed by blockIdx.
 template <typename TV, typename TR, int MODE, typename TA = TV, int R = 1>
 __global__ void __launch_bounds__(kBlock) k_pre_restrict_lds(
     int32_t nc, int32_t G, const int32_t *__restrict__ seg, const int32_t *__restrict__ sptr,
@@ -504,17 +508,18 @@ __global__ void __launch_bounds__(kBlock) k_pre_restrict_lds(
   TV *xs = reinterpret_cast<TV *>(lds_d);
   __shared__ TV sh[kBlock * R];
   if (*done) return;
-  const int32_t J0 = blockIdx.x * G;
+  const int32_t tb = xcd_block(blockIdx.x, gridDim.x);
+  const int32_t J0 = tb * G;
   const int32_t J1 = min(nc, J0 + G);
   const int32_t f0 = seg[J0], f1 = seg[J1];
-  const int32_t h0 = hptr[blockIdx.x];
+  const int32_t h0 = hptr[tb];
   if (MODE == kPreFromZ)
-    stage_tile(xs, hidx, h0, hptr[blockIdx.x + 1] - h0, [&](int32_t c) { return z[c]; });
+    stage_tile(xs, hidx, h0, hptr[tb + 1] - h0, [&](int32_t c) { return z[c]; });
   else if (MODE == kPreStagedZ)
-    stage_tile(xs, hidx, h0, hptr[blockIdx.x + 1] - h0,
+    stage_tile(xs, hidx, h0, hptr[tb + 1] - h0,
                [&](int32_t c) { return (TV)r[c] * minv[c]; });
   else
-    stage_tile(xs, hidx, h0, hptr[blockIdx.x + 1] - h0, [&](int32_t c) { return (TV)r[c]; });
+    stage_tile(xs, hidx, h0, hptr[tb + 1] - h0, [&](int32_t c) { return (TV)r[c]; });
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     const int32_t row = f0 + (int32_t)threadIdx.x + u * kBlock;
@@ -536,7 +541,7 @@ __global__ void __launch_bounds__(kBlock) k_pre_restrict_lds(
   }
 }
 
-// k_post with the tile of block b = its row chunk (tiles hrow)
+// k_post with the tile of block b = its row chunk (tiles hrow), XCD-aware order
 template <typename TV, typename TR, typename TO, bool DOT, typename TA = TV>
 __global__ void __launch_bounds__(kBlock) k_post_lds(
     int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const uint16_t *__restrict__ lcol,
@@ -548,9 +553,11 @@ __global__ void __launch_bounds__(kBlock) k_post_lds(
   TV *xs = reinterpret_cast<TV *>(lds_d);
   if (*done) return;
   int32_t rb, re;
-  rows_of_block(n, chunk, &rb, &re);
-  const int32_t h0 = hptr[blockIdx.x];
-  stage_tile(xs, hidx, h0, hptr[blockIdx.x + 1] - h0, [&](int32_t c) { return z[c]; });
+  const int32_t tb = xcd_block(blockIdx.x, gridDim.x);
+  rb = (int32_t)((int64_t)tb * chunk);
+  re = (int32_t)min((int64_t)n, (int64_t)rb + chunk);
+  const int32_t h0 = hptr[tb];
+  stage_tile(xs, hidx, h0, hptr[tb + 1] - h0, [&](int32_t c) { return z[c]; });
   double d[1] = {0.0};
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;
@@ -990,7 +997,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot(
   block_partial<1>(d, partials);
 }
 
-// k_spmv_dot with the tile of block b = its row chunk (tiles hrow)
+// k_spmv_dot with the tile of block b = its row chunk (tiles hrow), XCD-aware order
 template <typename TA>
 __global__ void __launch_bounds__(kBlock) k_spmv_dot_lds(
     int32_t n, int32_t chunk, const int32_t *__restrict__ sptr, const uint16_t *__restrict__ lcol,
@@ -1000,9 +1007,11 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot_lds(
   extern __shared__ double lds_d[];
   if (*done) return;
   int32_t rb, re;
-  rows_of_block(n, chunk, &rb, &re);
-  const int32_t h0 = hptr[blockIdx.x];
-  stage_tile(lds_d, hidx, h0, hptr[blockIdx.x + 1] - h0, [&](int32_t c) { return p[c]; });
+  const int32_t tb = xcd_block(blockIdx.x, gridDim.x);
+  rb = (int32_t)((int64_t)tb * chunk);
+  re = (int32_t)min((int64_t)n, (int64_t)rb + chunk);
+  const int32_t h0 = hptr[tb];
+  stage_tile(lds_d, hidx, h0, hptr[tb + 1] - h0, [&](int32_t c) { return p[c]; });
   double d[1] = {0.0};
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
     int32_t base, w;

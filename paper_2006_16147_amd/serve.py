@@ -30,6 +30,7 @@ from __future__ import annotations
 
 import dataclasses
 import queue
+import sys
 import threading
 import time
 from typing import Any, Dict, List, Optional
@@ -167,8 +168,10 @@ class Server:
 
     # -- main loop ---------------------------------------------------------------
 
-    def run(self, requests: List[Request], realtime: bool = True, time_scale: float = 1.0):
-        """Serves the stream; arrival times are replayed in real time (scaled)."""
+    def run(self, requests: List[Request], realtime: bool = True, time_scale: float = 1.0,
+            progress: int = 0):
+        """Serves the stream; arrival times are replayed in real time (scaled).
+        progress > 0 prints a line to stderr every `progress` completions."""
         reqs = sorted(requests, key=lambda r: r.t_arrival)
         results: Dict[int, Result] = {}
         pending: List[list] = []  # [req, bypassed]
@@ -232,6 +235,9 @@ class Server:
             res.t_done = clock()
             running -= 1
             finished += 1
+            if progress and finished % progress == 0:
+                print("[serve] %d of %d requests done at %.1f s" % (finished, total, clock()),
+                      file=sys.stderr, flush=True)
             free.append(slot)
             free.sort()
             self.used -= self.backend.solve_bytes(req)
@@ -404,7 +410,7 @@ def main(argv=None):
                   else backend.default_budget())
         srv = Server(backend, slots=args.slots, budget_bytes=budget)
         t0 = time.perf_counter()
-        res = srv.run(reqs)
+        res = srv.run(reqs, progress=250)
         wall = time.perf_counter() - t0
         summ = summarize(res, warmup=args.warmup)
         summ.update({"rate_per_s": rate, "wall_s": wall, "setups": srv.stats["setups"],

@@ -72,13 +72,21 @@ def test_async_batch_and_calls_that_wait_for_the_solve_in_flight():
     assert rp[-1] == len(ci) == len(val)
     st, infos_a = amg.amg_wait(ha)
     assert st == amg.Status.OK
-    assert [i["iterations"] for i in infos_a] == [i["iterations"] for i in infos_b]
-    assert torch.equal(Xa, Xb)
+    # each hierarchy autotunes its tiles on its first block solve; the tiles
+    # fix the order of the per-column dot-product sums, so the two results
+    # are bitwise equal when both chose the same tiles, else equal to rounding
+    if ha.batch_tiles() == hb.batch_tiles():
+        assert [i["iterations"] for i in infos_a] == [i["iterations"] for i in infos_b]
+        assert torch.equal(Xa, Xb)
+    else:
+        assert all(abs(a["iterations"] - b["iterations"]) <= 1 for a, b in zip(infos_a, infos_b))
+        assert torch.allclose(Xa, Xb, rtol=0, atol=1e-9 * Xb.abs().max().item())
+    Xa1 = Xa.clone()
     # a second solve on the same hierarchy after the first was waited for
     Xa.zero_()
     assert amg.amg_pcg_solve_batch(ha, Bd, Xa)[0] == amg.Status.OK
     ha.close()  # amg_free waits for the solve in flight
-    assert torch.equal(Xa, Xb)
+    assert torch.equal(Xa, Xa1)
 
 
 def test_async_not_converged_status_comes_from_wait():
