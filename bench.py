@@ -242,6 +242,40 @@ def kernel_summary(trace_csv):
     print("\n".join(out))
 
 
+def counter_summary(fetch_csv, write_csv):
+    """Markdown table of rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs: per
+    kernel, the mean over its largest-grid dispatches, in MB, each counter
+    scaled as profiles/traffic.json records for the calibration copy."""
+    scale = {"FETCH_SIZE": 1.0, "WRITE_SIZE": 1.0}
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            t = json.load(f)
+        for c in scale:
+            scale[c] = t.get("%s_scale" % c, 1.0)
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        for r in _counter_rows(path):
+            if r.get("Counter_Name") != counter:
+                continue
+            d = per.setdefault(_short(r["Kernel_Name"]), {}).setdefault(counter, [])
+            d.append((_grid(r), float(r["Counter_Value"]) * 1024.0 / scale[counter]))
+    out = ["| kernel | largest-grid dispatches | fetched MB | written MB |", "|---|---|---|---|"]
+    rows = []
+    for name, d in per.items():
+        vals = {}
+        for counter, v in d.items():
+            top = max(g for g, _ in v)
+            sel = [b for g, b in v if g == top]
+            vals[counter] = (len(sel), sum(sel) / len(sel))
+        f = vals.get("FETCH_SIZE", (0, 0.0))
+        w = vals.get("WRITE_SIZE", (0, 0.0))
+        rows.append((f[1] + w[1], name, max(f[0], w[0]), f[1], w[1]))
+    for _, name, nd, fb, wb in sorted(rows, reverse=True)[:30]:
+        out.append("| `%s` | %d | %.1f | %.1f |" % (name, nd, fb / 1e6, wb / 1e6))
+    print("\n".join(out))
+
+
 def overlap_summary(trace_csv):
     """GPU busy fraction and cross-stream overlap of a rocprofv3 kernel trace:
     the time covered by at least one kernel, and by kernels of at least two
@@ -665,11 +699,16 @@ def main():
                     help="write profiles/traffic.json from two counter runs")
     ap.add_argument("--kernel-summary", metavar="KERNEL_TRACE_CSV",
                     help="print a markdown summary of a rocprofv3 kernel trace")
+    ap.add_argument("--counter-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print per-kernel HBM MB from two rocprofv3 counter runs")
     ap.add_argument("--overlap-summary", metavar="KERNEL_TRACE_CSV",
                     help="print the GPU busy fraction and cross-queue overlap of a trace")
     args = ap.parse_args()
     if args.kernel_summary:
         kernel_summary(args.kernel_summary)
+        return
+    if args.counter_summary:
+        counter_summary(*args.counter_summary)
         return
     if args.overlap_summary:
         overlap_summary(args.overlap_summary)

@@ -68,6 +68,18 @@ void stream_free(int device, hipStream_t s, void *p) {
   else (void)hipFree(p);
 }
 
+namespace {
+// Gives the pool's unused memory beyond kPoolKeepBytes back to the device
+// (called once a hierarchy's frees have completed): the release threshold
+// alone is not relied on to shrink the pool, and a serving loop that builds
+// and evicts hierarchies of many sizes would otherwise leave the device's
+// memory held by freed blocks.
+void pool_trim(int device) {
+  hipMemPool_t pool = lib_pool(device);
+  if (pool && hipMemPoolTrimTo(pool, kPoolKeepBytes) != hipSuccess) (void)hipGetLastError();
+}
+}  // namespace
+
 amg_status dev_alloc(amg_hierarchy *h, void **p, size_t bytes) {
   *p = nullptr;
   void *q = nullptr;
@@ -165,6 +177,7 @@ void destroy(amg_hierarchy *h) {
   if (h->batch) free_batch(h->batch, h->device, h->stream);
   for (void *p : h->allocs) stream_free(h->device, h->stream, p);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  pool_trim(h->device);
   if (h->scal_host) (void)hipHostFree(h->scal_host);
   if (h->join_event) (void)hipEventDestroy(h->join_event);
   if (h->stream) (void)hipStreamDestroy(h->stream);

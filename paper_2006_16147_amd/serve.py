@@ -12,11 +12,18 @@ are started on other slots and their GPU work overlaps:
   motivates for time-dependent and nonlinear sequences). Idle entries are
   evicted least-recently-used when memory is needed.
 * Admission by footprint (by default the device's memory less a headroom of
-  32 GiB, ~236 GiB on one MI355X): a cache miss reserves the library's footprint
+  32 GiB, 256 GiB on one MI355X): a cache miss reserves the library's footprint
   estimate for the operator (amg_estimate_footprint) plus the solve's
   vectors; a hit reserves the vectors only. A request that cannot fit even
   into an empty device is rejected; one that does not fit now waits. Later
   requests may bypass a waiting one at most ``max_bypass`` times.
+* Device check: the reservations leave out what else the device holds
+  (allocator caches, freed blocks kept by the library's pool, runtime
+  scratch). A backend that reports its free device memory gets a second
+  test before each admission: free memory, less the reservations of the
+  requests in flight and a margin, must cover the request; if it does not,
+  the backend's caches are released and idle hierarchies evicted before the
+  request waits.
 * Two requests on the same operator never run at once (a hierarchy is used
   by one thread at a time); the second waits for the first.
 
@@ -65,6 +72,9 @@ class Result:
     converged: bool = False
     rel_res_true: float = 0.0
     rejected: bool = False
+    reserved: int = 0  # bytes reserved while in flight
+    error: str = ""  # why a request failed
+    retries: int = 0  # admissions repeated after the device ran out of memory
     x: Any = None
 
     @property
@@ -95,7 +105,7 @@ class Server:
     """
 
     def __init__(self, backend, slots: int = 4, budget_bytes: int = 64 << 30,
-                 max_bypass: int = 8):
+                 max_bypass: int = 8, margin_bytes: int = 4 << 30):
         if slots < 1:
             raise ValueError("slots must be positive")
         self.backend = backend
@@ -114,7 +124,12 @@ class Server:
         for t in self._threads:
             t.start()
         self.stats = {"setups": 0, "hits": 0, "evictions": 0, "rejected": 0,
-                      "max_concurrency": 0}
+                      "max_concurrency": 0, "memory_waits": 0, "oom_retries": 0}
+        self.max_oom_retries = 2
+        self.inflight = 0  # reservations of the requests in flight
+        self.margin = int(margin_bytes)
+        self.device_used_peak = 0
+        self._last_release = -1e9
 
     # -- workers -------------------------------------------------------------
 
@@ -155,6 +170,52 @@ class Server:
         self.peak_used = max(self.peak_used, self.used)
         assert self.used <= self.budget, "admission exceeded the memory budget"
 
+    def _evict_one(self) -> bool:
+        idle = [(e.last_used, op) for op, e in self.cache.items() if not e.busy]
+        if not idle:
+            return False
+        _, op = min(idle)
+        e = self.cache.pop(op)
+        self.backend.release(e.handle)
+        self.used -= e.bytes
+        self.stats["evictions"] += 1
+        return True
+
+    def _device_room(self) -> Optional[int]:
+        """Bytes the device can still give to admissions: its free memory less
+        the reservations of the requests in flight (whose allocations may not
+        have happened yet) and a margin; None for a backend that does not
+        report device memory."""
+        free_fn = getattr(self.backend, "device_free_bytes", None)
+        if free_fn is None:
+            return None
+        return int(free_fn()) - self.inflight - self.margin
+
+    def _make_room(self, need, running) -> bool:
+        """The reservation accounting leaves out what the device holds besides
+        the hierarchies (allocator caches, freed pool blocks, runtime scratch).
+        Checks the device's own free memory; if it is short, releases the
+        backend's caches, then evicts idle hierarchies (least recently used
+        first). False: wait for requests in flight to finish."""
+        room = self._device_room()
+        if room is None or need <= room:
+            return True
+        rel = getattr(self.backend, "release_cache", None)
+        now = time.perf_counter()
+        # at most twice a second while requests run (it may wait for the device)
+        if rel is not None and (running == 0 or now - self._last_release >= 0.5):
+            rel()
+            self._last_release = now
+        while True:
+            room = self._device_room()
+            if need <= room:
+                return True
+            if not self._evict_one():
+                break
+        self.stats["memory_waits"] += 1
+        # nothing left to evict and nothing running: go ahead
+        return running == 0
+
     def _evict_until(self, need) -> bool:
         idle = sorted((e.last_used, op) for op, e in self.cache.items() if not e.busy)
         for _, op in idle:
@@ -175,6 +236,7 @@ class Server:
         reqs = sorted(requests, key=lambda r: r.t_arrival)
         results: Dict[int, Result] = {}
         pending: List[list] = []  # [req, bypassed]
+        retries: Dict[int, int] = {}  # req_id -> admissions repeated after running out of memory
         free = list(range(self.nslots))
         running = 0
         i = 0
@@ -201,7 +263,8 @@ class Server:
                     results[req.req_id] = res
                     self.stats["rejected"] += 1
                     continue
-                if self.used + need > self.budget and not self._evict_until(need):
+                if ((self.used + need > self.budget and not self._evict_until(need))
+                        or not self._make_room(need, running)):
                     if k == 0 and bypassed >= self.max_bypass:
                         return  # the head has waited long enough: nobody passes it
                     k += 1
@@ -219,8 +282,11 @@ class Server:
                     entry.busy = True
                     self.stats["hits"] += 1
                 self._reserve(need)
+                self.inflight += need
                 res = Result(req.req_id, req.op_id, req.N, req.t_arrival, slot=slot,
                              cache_hit=not build)
+                res.reserved = need
+                res.retries = retries.get(req.req_id, 0)
                 res.t_admit = clock()
                 results[req.req_id] = res
                 running += 1
@@ -234,6 +300,25 @@ class Server:
             res = results[req.req_id]
             res.t_done = clock()
             running -= 1
+            oom = getattr(self.backend, "is_oom", None)
+            if (err is not None and built is None and entry.handle is None and oom is not None
+                    and oom(err) and res.retries < self.max_oom_retries):
+                # the setup ran out of device memory: drop the placeholder,
+                # free an idle hierarchy and queue the request again at the front
+                free.append(slot)
+                free.sort()
+                self.used -= self.backend.solve_bytes(req)
+                self.inflight -= res.reserved
+                self.cache.pop(req.op_id, None)
+                self.used -= entry.bytes
+                self.stats["setups"] -= 1
+                self.stats["oom_retries"] += 1
+                self._evict_one()
+                retries[req.req_id] = res.retries + 1
+                del results[req.req_id]
+                pending.insert(0, [req, 0])
+                self.events.append((res.t_done, "retry", req.req_id, slot))
+                return
             finished += 1
             if progress and finished % progress == 0:
                 print("[serve] %d of %d requests done at %.1f s" % (finished, total, clock()),
@@ -241,6 +326,10 @@ class Server:
             free.append(slot)
             free.sort()
             self.used -= self.backend.solve_bytes(req)
+            self.inflight -= res.reserved
+            used_fn = getattr(self.backend, "device_used_bytes", None)
+            if used_fn is not None:
+                self.device_used_peak = max(self.device_used_peak, int(used_fn()))
             if built is not None:
                 handle, nbytes = built
                 entry.handle = handle
@@ -251,6 +340,7 @@ class Server:
             entry.last_used = res.t_done
             if err is not None or out is None:
                 res.status = -1
+                res.error = repr(err)[:200] if err is not None else "no result"
                 if entry.handle is None:  # the build failed: drop the placeholder
                     self.cache.pop(req.op_id, None)
                     self.used -= entry.bytes
@@ -260,6 +350,8 @@ class Server:
                 res.converged = out["converged"]
                 res.rel_res_true = out["rel_res_true"]
                 res.x = out.get("x")
+                if res.status != 0:
+                    res.error = "status %d" % res.status
             self.events.append((res.t_done, "done", req.req_id, slot))
 
         while finished + self.stats["rejected"] < total:
@@ -302,7 +394,15 @@ def summarize(results: List[Result], wall_s: Optional[float] = None, warmup: int
         "solves_per_s": (len(done) / wall_s) if wall_s else 0.0,
         "cache_hit_rate": (sum(r.cache_hit for r in done) / len(done)) if done else 0.0,
         "all_converged": all(r.converged for r in done),
+        "errors": _count([r.error for r in results if r.error]),
     }
+
+
+def _count(items) -> dict:
+    out: Dict[str, int] = {}
+    for it in items:
+        out[it] = out.get(it, 0) + 1
+    return out
 
 
 class GpuBackend:
@@ -333,6 +433,23 @@ class GpuBackend:
         _, total = self.torch.cuda.mem_get_info(self.dev)
         return max(0, int(total) - self.HEADROOM)
 
+    def device_free_bytes(self) -> int:
+        return int(self.torch.cuda.mem_get_info(self.dev)[0])
+
+    def device_used_bytes(self) -> int:
+        free, total = self.torch.cuda.mem_get_info(self.dev)
+        return int(total - free)
+
+    def is_oom(self, err) -> bool:
+        amg = self.amg
+        return ((isinstance(err, amg.AmgError) and err.status == amg.Status.ERR_OOM)
+                or isinstance(err, self.torch.cuda.OutOfMemoryError))
+
+    def release_cache(self):
+        # blocks the torch allocator keeps from earlier requests' operator
+        # builds and vectors
+        self.torch.cuda.empty_cache()
+
     def make_slot(self, i):
         torch = self.torch
         torch.cuda.set_device(self.dev)
@@ -345,7 +462,8 @@ class GpuBackend:
         n = req.N ** 3
         nnz = 7 * n - 6 * req.N * req.N
         csr = 4 * (n + 1) + 12 * nnz  # the operator while the setup copies it
-        return self.amg.amg_estimate_footprint(n, nnz, self._params()) + csr
+        build = 400 * n  # torch temporaries of the operator build (stacked columns, masks)
+        return self.amg.amg_estimate_footprint(n, nnz, self._params()) + csr + build
 
     def solve_bytes(self, req) -> int:
         return 2 * 8 * req.N ** 3
@@ -416,8 +534,11 @@ def main(argv=None):
         summ.update({"rate_per_s": rate, "wall_s": wall, "setups": srv.stats["setups"],
                      "evictions": srv.stats["evictions"],
                      "max_concurrency": srv.stats["max_concurrency"],
+                     "memory_waits": srv.stats["memory_waits"],
+                     "oom_retries": srv.stats["oom_retries"],
                      "budget_gib": budget / (1 << 30),
-                     "peak_reserved_gib": srv.peak_used / (1 << 30)})
+                     "peak_reserved_gib": srv.peak_used / (1 << 30),
+                     "device_used_peak_gib": srv.device_used_peak / (1 << 30)})
         srv.close()
         rows.append(summ)
         print(json.dumps(summ), flush=True)

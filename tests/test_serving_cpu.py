@@ -121,6 +121,99 @@ def test_admission_by_footprint_and_lru_eviction():
     assert srv.stats["evictions"] >= 2 and len(be.released) >= 2
 
 
+class DeviceBackend(SleepBackend):
+    """SleepBackend on a simulated device of `total` bytes: hierarchies hold
+    their footprint, and every build leaves `cache_per_build` bytes in an
+    allocator cache that only release_cache() gives back (memory that the
+    reservations do not see)."""
+
+    def __init__(self, total, cache_per_build, **kw):
+        super().__init__(**kw)
+        self.total = total
+        self.cache_per_build = cache_per_build
+        self.cache = 0
+        self.live = {}
+        self.peak = 0
+        self.cache_releases = 0
+
+    def _used(self):
+        return sum(self.live.values()) + self.cache
+
+    def device_free_bytes(self):
+        with self.lock:
+            return self.total - self._used()
+
+    def device_used_bytes(self):
+        with self.lock:
+            return self._used()
+
+    def release_cache(self):
+        with self.lock:
+            self.cache = 0
+            self.cache_releases += 1
+
+    def build(self, req, slot):
+        h, nbytes = super().build(req, slot)
+        with self.lock:
+            self.live[h] = nbytes
+            self.cache += self.cache_per_build
+            self.peak = max(self.peak, self._used())
+        return h, nbytes
+
+    def release(self, handle):
+        super().release(handle)
+        with self.lock:
+            self.live.pop(handle, None)
+
+
+def test_device_check_covers_memory_the_reservations_do_not_see():
+    """The budget alone would admit everything; the device's own free memory
+    (hierarchies plus a growing allocator cache) forces cache releases and
+    LRU evictions, and the simulated device never overflows."""
+    one = 100 * 10 ** 3  # one N=10 hierarchy's estimate
+    be = DeviceBackend(total=4 * one, cache_per_build=one // 2, setup_s=0.002,
+                       solve_s=0.002, bytes_per_dof=100)
+    srv = Server(be, slots=2, budget_bytes=10 ** 12, margin_bytes=one // 4)
+    reqs = _burst(40, ops=list(range(12)), dt=0.0005)
+    res = srv.run(reqs)
+    srv.close()
+    assert all(r.status == 0 for r in res)
+    assert be.peak <= be.total
+    assert be.cache_releases > 0 and srv.stats["evictions"] > 0
+    assert srv.device_used_peak <= be.total
+
+
+class OomOnceBackend(SleepBackend):
+    """The first setup of operator 3 runs out of device memory."""
+
+    def __init__(self, **kw):
+        super().__init__(**kw)
+        self.failed_once = False
+
+    def is_oom(self, err):
+        return isinstance(err, MemoryError)
+
+    def build(self, req, slot):
+        if req.op_id == 3 and not self.failed_once:
+            self.failed_once = True
+            raise MemoryError("device full")
+        return super().build(req, slot)
+
+
+def test_setup_out_of_memory_is_retried_after_an_eviction():
+    be = OomOnceBackend(setup_s=0.002, solve_s=0.002)
+    srv = Server(be, slots=2, budget_bytes=10 ** 9)
+    reqs = _burst(8, ops=[0, 1, 2, 3], dt=0.001)
+    res = srv.run(reqs)
+    srv.close()
+    assert all(r.status == 0 for r in res)
+    assert srv.stats["oom_retries"] == 1 and srv.stats["evictions"] >= 1
+    assert [r.retries for r in res if r.req_id == 3] == [1]
+    assert summarize(res)["errors"] == {}
+    # the eviction made room by dropping an idle hierarchy, which is built again later
+    assert be.builds.count(3) == 1 and srv.stats["setups"] == len(be.builds)
+
+
 def test_rejection_of_requests_larger_than_the_device():
     be = SleepBackend(bytes_per_dof=100)
     srv = Server(be, slots=2, budget_bytes=50_000)
