@@ -752,8 +752,8 @@ __global__ void __launch_bounds__(kBlock) kb_update(int32_t n, int32_t k,
   column_partial<KT>(d, valid, j, k, partials);
 }
 
-template <int KT>
-__global__ void kb_xpay(int32_t n, int32_t k, const double *__restrict__ Z,
+template <int KT, typename TZ = double>
+__global__ void kb_xpay(int32_t n, int32_t k, const TZ *__restrict__ Z,
                         double *__restrict__ P, const double *__restrict__ colv,
                         const int32_t *__restrict__ done, int32_t copy,
                         const int32_t *__restrict__ stop) {
@@ -762,7 +762,8 @@ __global__ void kb_xpay(int32_t n, int32_t k, const double *__restrict__ Z,
   const int64_t i = (int64_t)blockIdx.x * (kBlock / KT) + threadIdx.x / KT;
   if (j >= k || i >= n || done[j]) return;
   const int64_t o = i * k + j;
-  P[o] = copy ? Z[o] : Z[o] + colv[cBeta * k + j] * P[o];
+  const double z = (double)Z[o];
+  P[o] = copy ? z : z + colv[cBeta * k + j] * P[o];
 }
 
 // r -= alpha q with two columns per thread (k even, blocks 16-byte aligned),
@@ -819,8 +820,8 @@ __global__ void __launch_bounds__(kBlock) kb_update_v(int32_t n, int32_t kv,
 // set (xpend; also those that converged or broke down since, which is why
 // the kernel runs when every column has stopped), then p = z + beta p for
 // the live ones; a stopped column's half of p is stored back unchanged.
-template <int KT>
-__global__ void kb_xpay_v(int32_t n, int32_t kv, const double *__restrict__ Z,
+template <int KT, typename TZ>
+__global__ void kb_xpay_v(int32_t n, int32_t kv, const TZ *__restrict__ Z,
                           double *__restrict__ P, double *__restrict__ X,
                           const double *__restrict__ colv, const int32_t *__restrict__ done,
                           const int32_t *__restrict__ xpend) {
@@ -840,7 +841,13 @@ __global__ void kb_xpay_v(int32_t n, int32_t kv, const double *__restrict__ Z,
     reinterpret_cast<double2 *>(X)[o] = x;
   }
   if (!live0 && !live1) return;
-  const double2 z = reinterpret_cast<const double2 *>(Z)[o];
+  double2 z;
+  if constexpr (std::is_same<TZ, float>::value) {
+    const float2 zf = reinterpret_cast<const float2 *>(Z)[o];
+    z = make_double2((double)zf.x, (double)zf.y);
+  } else {
+    z = reinterpret_cast<const double2 *>(Z)[o];
+  }
   if (live0) v.x = z.x + colv[cBeta * k + j] * v.x;
   if (live1) v.y = z.y + colv[cBeta * k + j + 1] * v.y;
   reinterpret_cast<double2 *>(P)[o] = v;
@@ -1020,6 +1027,17 @@ void bfinalize(amg_hierarchy *h, int32_t op, int32_t nparts, int32_t maxit, cons
                                             B.xpend, maxit, stop);
 }
 
+// whether the block solve keeps the V-cycle's output in Batch::Zf: an FP32
+// hierarchy of more than one level whose final post-smoothing and
+// p = z + beta p take their vector forms
+bool z32(const amg_hierarchy *h) {
+  const Batch &B = *h->batch;
+  return B.Zf && h->lv.size() > 1 && B.k % 4 == 0 && aligned16(B.Zf) && aligned16(B.R) &&
+         aligned16(B.z[0]) && aligned16(B.y[0]) && aligned16(B.t[0]) && B.k % 2 == 0 &&
+         aligned16(B.X) && aligned16(B.P) && aligned16(B.Q) &&
+         (!B.Rf || reinterpret_cast<uintptr_t>(B.Rf) % 8 == 0);
+}
+
 // one block V-cycle: Z = B_0 R on all k columns; with rz_op >= 0 also the
 // per-column (R, Z) and that finalize
 template <typename TV, int KT>
@@ -1164,7 +1182,19 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
         z = out;
       } else if (rz_op >= 0) {
         constexpr int VW = Vec16<TV>::width;
-        if (k % VW == 0 && aligned16(R0) && aligned16(z) && aligned16(Z0)) {
+        if (std::is_same<TV, float>::value && Z0 == B.Z && z32(h)) {
+          // the FP32 store of z (same numbers, see Batch::Zf)
+          int32_t np = 0;
+          with_vec_tile(B, k / VW, [&](auto kt) {
+            constexpr int KV = decltype(kt)::value;
+            const BGeom gv = bgeom(F.n, k / VW, KV);
+            kb_post_v<TV, double, float, KV, true><<<gv.grid, kBlock, 0, s>>>(
+                F.n, k / VW, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, B.Zf,
+                B.partials, stop);
+            np = (int32_t)gv.grid.x;
+          });
+          bfinalize(h, rz_op, np, maxit, stop);
+        } else if (k % VW == 0 && aligned16(R0) && aligned16(z) && aligned16(Z0)) {
           int32_t np = 0;
           with_vec_tile(B, k / VW, [&](auto kt) {
             constexpr int KV = decltype(kt)::value;
@@ -1273,11 +1303,17 @@ void iteration_b(amg_hierarchy *h, int32_t maxit) {
   bfinalize(h, bRr, cg_update(h, stop), maxit, stop);
   kb_all_done<<<1, 64, 0, s>>>(k, B.done, B.all_done);
   vcycle_b<TV, KT>(h, B.R, B.Z, bRz, maxit, stop);
-  if (vec_cg(B))
+  if (z32(h))
     with_vec_tile(B, k / 2, [&](auto kt) {
       constexpr int KE = decltype(kt)::value;
-      kb_xpay_v<KE><<<egrid(n, k / 2, KE), kBlock, 0, s>>>(n, k / 2, B.Z, B.P, B.X, B.col,
-                                                            B.done, B.xpend);
+      kb_xpay_v<KE, float><<<egrid(n, k / 2, KE), kBlock, 0, s>>>(n, k / 2, B.Zf, B.P, B.X,
+                                                                   B.col, B.done, B.xpend);
+    });
+  else if (vec_cg(B))
+    with_vec_tile(B, k / 2, [&](auto kt) {
+      constexpr int KE = decltype(kt)::value;
+      kb_xpay_v<KE, double><<<egrid(n, k / 2, KE), kBlock, 0, s>>>(n, k / 2, B.Z, B.P, B.X,
+                                                                    B.col, B.done, B.xpend);
     });
   else
     with_row_tile(k, [&](auto kt) {
@@ -1342,6 +1378,9 @@ void launch_small(amg_hierarchy *h, int32_t which) {
   const int32_t n = h->lv[0].n;
   if (which == 0)
     kb_zero_cols<KT><<<egrid(n, B.k, KT), kBlock, 0, h->stream>>>(n, B.k, B.X, B.done);
+  else if (z32(h))
+    kb_xpay<KT, float><<<egrid(n, B.k, KT), kBlock, 0, h->stream>>>(n, B.k, B.Zf, B.P, B.col,
+                                                                   B.done, 1, B.all_done);
   else
     kb_xpay<KT><<<egrid(n, B.k, KT), kBlock, 0, h->stream>>>(n, B.k, B.Z, B.P, B.col, B.done, 1,
                                                             B.all_done);
@@ -1391,6 +1430,8 @@ amg_status alloc_batch(amg_hierarchy *h, int32_t k) {
   AMG_TRY(balloc(h, (void **)&B.P, e0));
   AMG_TRY(balloc(h, (void **)&B.Q, e0));
   if (fp32) AMG_TRY(balloc(h, (void **)&B.Rf, (size_t)h->lv[0].n * k * sizeof(float)));
+  if (fp32 && k % 4 == 0 && h->lv.size() > 1)
+    AMG_TRY(balloc(h, (void **)&B.Zf, (size_t)h->lv[0].n * k * sizeof(float)));
   AMG_TRY(balloc(h, (void **)&B.partials, sizeof(double) * 2 * kBatchBlocks * (size_t)k));
   AMG_TRY(balloc(h, (void **)&B.col, sizeof(double) * kColFields * (size_t)k));
   AMG_TRY(balloc(h, (void **)&B.iter, sizeof(int32_t) * (size_t)k));

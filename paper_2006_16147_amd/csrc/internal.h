@@ -185,6 +185,11 @@ struct Batch {
   // FP32 hierarchy only: float(R), kept by whichever kernel writes R, so the
   // level-0 kernels that only use R rounded to FP32 gather 4-byte entries
   float *Rf = nullptr;
+  // FP32 hierarchy, k a multiple of 4: the V-cycle's output z. The level-0
+  // post-smoothing computes it in FP32, so the FP32 store holds the same
+  // numbers as the FP64 block Z in half the bytes (written once, read by
+  // p = z + beta p)
+  float *Zf = nullptr;
   double *partials = nullptr;  // 2 x kBatchBlocks x k
   double *col = nullptr;       // per-column scalars, 8 x k (see batch.hip)
   int32_t *iter = nullptr, *done = nullptr, *all_done = nullptr;

@@ -249,6 +249,52 @@ __device__ __forceinline__ bool better(double c1, int32_t lo1, int32_t hi1, doub
   return hi1 < hi2;
 }
 
+// The best neighbour of v (entries [b, e) of its row) under the strict key
+// among those not taken: mate[j] != kFree, or (with cur) a mutual proposal
+// in cur. The loads go in batches of eight entries (all indices and weights,
+// then all mate and cur entries, then the proposals' proposals), so that a
+// vertex's chain of dependent loads does not grow with its degree; the
+// comparisons run in entry order. -1: every neighbour is taken.
+__device__ __forceinline__ int32_t best_free(int32_t v, int32_t b, int32_t e,
+                                             const int32_t *__restrict__ ci,
+                                             const double *__restrict__ c,
+                                             const int32_t *mate, const int32_t *cur) {
+  int32_t best = -1, blo = 0, bhi = 0;
+  double bc = 0.0;
+  for (int32_t k0 = b; k0 < e; k0 += 8) {
+    int32_t j[8];
+    double cc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = k0 + u < e;
+      j[u] = in ? ci[k0 + u] : v;
+      cc[u] = in ? c[k0 + u] : 0.0;
+    }
+    int32_t m[8], cj[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      m[u] = mate[j[u]];
+      cj[u] = cur ? cur[j[u]] : -1;
+    }
+    int32_t back[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) back[u] = cj[u] >= 0 ? cur[cj[u]] : -1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (k0 + u >= e || j[u] == v) continue;
+      if (m[u] != kFree || (cj[u] >= 0 && back[u] == j[u])) continue;
+      const int32_t lo = min(v, j[u]), hi = max(v, j[u]);
+      if (best < 0 || better(cc[u], lo, hi, bc, blo, bhi)) {
+        best = j[u];
+        bc = cc[u];
+        blo = lo;
+        bhi = hi;
+      }
+    }
+  }
+  return best;
+}
+
 // For every free vertex: keep its proposal if the proposed vertex is still
 // free (the free set only shrinks, so it is still the best), else propose to
 // the best free neighbour under the strict key; a free vertex with no free
@@ -263,20 +309,7 @@ __global__ void k_match_propose(int32_t n, const int32_t *rp, const int32_t *ci,
     if (u >= 0 && mate[u] == kFree) {
       live = true;
     } else {
-      int32_t best = -1, blo = 0, bhi = 0;
-      double bc = 0.0;
-      for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
-        const int32_t j = ci[k];
-        if (j == v || mate[j] != kFree) continue;
-        const int32_t lo = min(v, j), hi = max(v, j);
-        const double cc = c[k];
-        if (best < 0 || better(cc, lo, hi, bc, blo, bhi)) {
-          best = j;
-          bc = cc;
-          blo = lo;
-          bhi = hi;
-        }
-      }
+      const int32_t best = best_free(v, rp[v], rp[v + 1], ci, c, mate, nullptr);
       cand[v] = best;
       if (best < 0) mate[v] = kDead; else live = true;
     }
@@ -294,48 +327,34 @@ __global__ void k_match_accept(int32_t n, int32_t *mate, const int32_t *cand) {
   if (u >= 0 && cand[u] == v) mate[v] = u;
 }
 
-// x is no longer free after this round: matched or a singleton before it
-// (mate), or matched in it (mutual proposals in `cur`, which nobody writes in
-// this round). A stale read of mate[x] can only show a vertex that becomes a
-// singleton in this round as free; a proposal to it is then repeated next
-// round, while no free vertex is ever taken for matched.
-__device__ __forceinline__ bool taken(int32_t x, const int32_t *mate, const int32_t *cur) {
-  if (mate[x] != kFree) return true;
-  const int32_t c = cur[x];
-  return c >= 0 && cur[c] == x;
-}
-
 // One round: accept the mutual proposals of `cur` and, for vertices that stay
 // free, write their next proposal into `nxt` (kept while its target stays
 // free, else the best free neighbour under the strict key; none: singleton).
+// x counts as taken in this round if it was matched or became a singleton
+// before it (mate), or is matched in it (mutual proposals in `cur`, which
+// nobody writes in this round). A stale read of mate[x] can only show a
+// vertex that becomes a singleton in this round as free; a proposal to it is
+// then repeated next round, while no free vertex is ever taken for matched.
 __global__ void k_match_round(int32_t n, const int32_t *rp, const int32_t *ci, const double *c,
                               int32_t *mate, const int32_t *cur, int32_t *nxt,
                               int32_t *active) {
   const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   bool live = false;
   if (v < n && mate[v] == kFree) {
-    const int32_t u = cur[v];
-    if (u >= 0 && cur[u] == v) {
+    // a free vertex's proposal and row bounds together, then the proposed
+    // vertex's state and proposal, then that proposal's target
+    const int32_t u = cur[v], b = rp[v], e = rp[v + 1];
+    const int32_t cu = u >= 0 ? cur[u] : -1;
+    const int32_t mu = u >= 0 ? mate[u] : kFree;
+    const int32_t ccu = cu >= 0 ? cur[cu] : -1;
+    if (u >= 0 && cu == v) {
       mate[v] = u;
       nxt[v] = u;
-    } else if (u >= 0 && !taken(u, mate, cur)) {
-      nxt[v] = u;
+    } else if (u >= 0 && mu == kFree && !(cu >= 0 && ccu == u)) {
+      nxt[v] = u;  // still free: still the best
       live = true;
     } else {
-      int32_t best = -1, blo = 0, bhi = 0;
-      double bc = 0.0;
-      for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
-        const int32_t j = ci[k];
-        if (j == v || taken(j, mate, cur)) continue;
-        const int32_t lo = min(v, j), hi = max(v, j);
-        const double cc = c[k];
-        if (best < 0 || better(cc, lo, hi, bc, blo, bhi)) {
-          best = j;
-          bc = cc;
-          blo = lo;
-          bhi = hi;
-        }
-      }
+      const int32_t best = best_free(v, b, e, ci, c, mate, cur);
       nxt[v] = best;
       if (best < 0) mate[v] = kDead; else live = true;
     }

@@ -2132,22 +2132,28 @@ __global__ void k_tile_starts(int32_t ntiles, int32_t step, int32_t nmax,
   tb[t] = seg ? seg[c] : c;  // row chunks, or the first row of coarse row c
 }
 
-// Tile t = rows [tb[t], tb[t + 1]). Its SELL positions' columns (W per row,
-// W the widest slice among its rows; shorter rows padded with INT32_MAX) are
-// sorted in LDS and made distinct. Pass 0 writes the number of distinct
-// columns to count[t] (-1 when the padded entries exceed kHaloCap); pass 1
-// writes the list at hidx + hptr[t] and, at every position, the index of its
-// column in the list.
+// Tile t = rows [tb[t], tb[t + 1]). Its list is the sorted distinct columns
+// of its SELL positions (W per row, W the widest slice among its rows; at
+// most kHaloCap positions, else count[t] = -1 and no list): the columns below
+// the tile's own rows, then the own rows themselves (every row holds its
+// diagonal), then the columns above. Only the columns outside the own rows
+// are sorted (bitonic, in LDS) and made distinct; an own row's index in the
+// list follows from its offset. Pass 0 writes the list length to count[t];
+// pass 1 writes the list at hidx + hptr[t] and, at every position, the index
+// of its column in the list.
 __global__ void __launch_bounds__(kHaloThreads) k_halo(
     int32_t pass, const int32_t *__restrict__ tb, const int32_t *__restrict__ sptr,
     const int32_t *__restrict__ col, int32_t *__restrict__ count,
     const int32_t *__restrict__ hptr, int32_t *__restrict__ hidx, uint16_t *__restrict__ lcol) {
   __shared__ int32_t keys[kHaloCap];
   __shared__ int32_t part[kHaloThreads];
-  __shared__ int32_t wmax;
+  __shared__ int32_t wmax, nout;
   const int32_t t = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   const int32_t r0 = tb[t], r1 = tb[t + 1], rows = r1 - r0;
-  if (tid == 0) wmax = 0;
+  if (tid == 0) {
+    wmax = 0;
+    nout = 0;
+  }
   __syncthreads();
   if (rows > 0) {
     int32_t wl = 0;
@@ -2162,17 +2168,20 @@ __global__ void __launch_bounds__(kHaloThreads) k_halo(
     if (pass == 0 && tid == 0) count[t] = -1;
     return;
   }
-  int32_t P = 1;
-  while (P < E) P <<= 1;
-  for (int32_t i = tid; i < P; i += nt) {
-    int32_t key = INT32_MAX;
-    if (i < E) {
-      int32_t base, w;
-      sell_row(sptr, r0 + i / W, &base, &w);
-      if (i % W < w) key = col[base + (i % W) * kSlice];
+  // the columns outside [r0, r1), in any order
+  for (int32_t i = tid; i < E; i += nt) {
+    int32_t base, w;
+    sell_row(sptr, r0 + i / W, &base, &w);
+    if (i % W < w) {
+      const int32_t c = col[base + (i % W) * kSlice];
+      if (c < r0 || c >= r1) keys[atomicAdd(&nout, 1)] = c;
     }
-    keys[i] = key;
   }
+  __syncthreads();
+  const int32_t no = nout;
+  int32_t P = 1;
+  while (P < no) P <<= 1;
+  for (int32_t i = no + tid; i < P; i += nt) keys[i] = INT32_MAX;
   __syncthreads();
   for (int32_t size = 2; size <= P; size <<= 1)  // bitonic sort, ascending
     for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
@@ -2209,17 +2218,26 @@ __global__ void __launch_bounds__(kHaloThreads) k_halo(
     part[tid] += add;
     __syncthreads();
   }
-  const int32_t u = part[nt - 1];
+  const int32_t uo = part[nt - 1];
   int32_t pos = part[tid] - mine;
   for (int32_t q = 0; q < per; ++q)  // every key was read before the scan
     if (first & (1u << q)) keys[pos++] = kv[q];
   __syncthreads();
   if (pass == 0) {
-    if (tid == 0) count[t] = u;
+    if (tid == 0) count[t] = uo + rows;
     return;
   }
+  // nb = distinct outside columns below r0 (they precede the own rows)
+  int32_t lo = 0, hi = uo;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (keys[mid] < r0) lo = mid + 1;
+    else hi = mid;
+  }
+  const int32_t nb = lo;
   const int32_t h0 = hptr[t];
-  for (int32_t j = tid; j < u; j += nt) hidx[h0 + j] = keys[j];
+  for (int32_t j = tid; j < uo + rows; j += nt)
+    hidx[h0 + j] = j < nb ? keys[j] : (j < nb + rows ? r0 + (j - nb) : keys[j - rows]);
   for (int64_t i = tid; i < E; i += nt) {
     int32_t base, w;
     sell_row(sptr, r0 + (int32_t)(i / W), &base, &w);
@@ -2227,13 +2245,19 @@ __global__ void __launch_bounds__(kHaloThreads) k_halo(
     if (k >= w) continue;
     const int32_t idx = base + k * kSlice;
     const int32_t c = col[idx];
-    int32_t lo = 0, hi = u - 1;  // c is in the list
-    while (lo < hi) {
-      const int32_t mid = (lo + hi) >> 1;
-      if (keys[mid] < c) lo = mid + 1;
-      else hi = mid;
+    int32_t at;
+    if (c >= r0 && c < r1) {
+      at = nb + (c - r0);
+    } else {
+      int32_t a = 0, b = uo - 1;  // c is in the list
+      while (a < b) {
+        const int32_t mid = (a + b) >> 1;
+        if (keys[mid] < c) a = mid + 1;
+        else b = mid;
+      }
+      at = a < nb ? a : a + rows;
     }
-    lcol[idx] = (uint16_t)lo;
+    lcol[idx] = (uint16_t)at;
   }
 }
 
