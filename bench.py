@@ -267,6 +267,9 @@ def counter_summary(fetch_csv, write_csv):
         for counter, v in d.items():
             top = max(g for g, _ in v)
             sel = [b for g, b in v if g == top]
+            # levels with the same (capped) grid: keep the largest level's dispatches
+            big = max(sel)
+            sel = [b for b in sel if b >= 0.5 * big]
             vals[counter] = (len(sel), sum(sel) / len(sel))
         f = vals.get("FETCH_SIZE", (0, 0.0))
         w = vals.get("WRITE_SIZE", (0, 0.0))

@@ -335,9 +335,13 @@ __global__ void k_match_accept(int32_t n, int32_t *mate, const int32_t *cand) {
 // nobody writes in this round). A stale read of mate[x] can only show a
 // vertex that becomes a singleton in this round as free; a proposal to it is
 // then repeated next round, while no free vertex is ever taken for matched.
+// `prev` is the previous round's flag (null for the first round of a batch):
+// once a round has no proposing vertex left, every free vertex has been
+// matched or made a singleton, and the rounds queued after it return at once.
 __global__ void k_match_round(int32_t n, const int32_t *rp, const int32_t *ci, const double *c,
                               int32_t *mate, const int32_t *cur, int32_t *nxt,
-                              int32_t *active) {
+                              const int32_t *prev, int32_t *active) {
+  if (prev && *prev == 0) return;
   const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   bool live = false;
   if (v < n && mate[v] == kFree) {
@@ -795,7 +799,7 @@ amg_status pairwise_sweep(amg_hierarchy *h, Tmp &tmp, const Mat &A, SweepOut &o,
   AMG_TRY(tmp.get(&mate, n));
   AMG_TRY(tmp.get(&cand, n));
   AMG_TRY(tmp.get(&cand2, n));
-  constexpr int kMaxBatch = 64;
+  constexpr int kMaxBatch = 128;
   AMG_TRY(tmp.get(&counters, kMaxBatch));
   k_diag_pos<<<grid(n), kBlock, 0, s>>>(n, A.rp, A.ci, dpos);
   k_weights<<<grid(n), kBlock, 0, s>>>(n, A.rp, A.ci, A.val, dpos, A.w, c);
@@ -805,7 +809,9 @@ amg_status pairwise_sweep(amg_hierarchy *h, Tmp &tmp, const Mat &A, SweepOut &o,
   // each batch (rounds past the last live one do nothing)
   // first proposals, then one fused accept-and-propose kernel per round with
   // the proposals double-buffered; the last round's accept is applied after
-  int32_t rounds = 0, batch = 4;
+  // rounds queued after the last live one return at once, so batches can be
+  // long: 8, 16, ... up to kMaxBatch rounds between host checks
+  int32_t rounds = 0, batch = 8;
   int32_t hc[kMaxBatch];
   int32_t *cur = cand, *nxt = cand2;
   k_fill<int32_t><<<1, kMaxBatch, 0, s>>>(counters, 0, kMaxBatch);
@@ -813,7 +819,8 @@ amg_status pairwise_sweep(amg_hierarchy *h, Tmp &tmp, const Mat &A, SweepOut &o,
   for (;;) {
     k_fill<int32_t><<<1, kMaxBatch, 0, s>>>(counters, 0, kMaxBatch);
     for (int32_t r = 0; r < batch; ++r) {
-      k_match_round<<<grid(n), kBlock, 0, s>>>(n, A.rp, A.ci, c, mate, cur, nxt, counters + r);
+      k_match_round<<<grid(n), kBlock, 0, s>>>(n, A.rp, A.ci, c, mate, cur, nxt,
+                                               r > 0 ? counters + r - 1 : nullptr, counters + r);
       std::swap(cur, nxt);
     }
     AMG_HIP(hipMemcpyAsync(hc, counters, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, s));
