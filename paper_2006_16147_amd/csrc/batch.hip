@@ -198,11 +198,48 @@ __global__ void __launch_bounds__(kBlock) kb_pre_residual(
   }
 }
 
+// Indices and values of entries k0 .. k0 + kRowBatch - 1 of a SELL row (0
+// past its end). The KT lanes of a row would all load the same addresses;
+// with SHF lane u loads entry u and the others take it by shuffle (needs
+// KT >= kRowBatch and every lane of the row active).
+template <int KT, bool SHF, typename TA>
+__device__ __forceinline__ void row_batch(const int32_t *__restrict__ col,
+                                          const TA *__restrict__ val, int32_t base, int32_t k0,
+                                          int32_t w, int32_t (&c)[kRowBatch],
+                                          TA (&va)[kRowBatch]) {
+  if constexpr (SHF && KT >= kRowBatch) {
+    const int32_t lane = (int32_t)threadIdx.x % KT;
+    int32_t cl = 0;
+    TA vl = 0;
+    if (lane < kRowBatch && k0 + lane < w) {
+      const int32_t idx = base + (k0 + lane) * kSlice;
+      cl = ld_stream(&col[idx]);
+      vl = ld_stream(&val[idx]);
+    }
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      c[u] = __shfl(cl, u, KT);
+      va[u] = __shfl(vl, u, KT);
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      c[u] = 0;
+      va[u] = 0;
+      if (k0 + u < w) {
+        const int32_t idx = base + (k0 + u) * kSlice;
+        c[u] = ld_stream(&col[idx]);
+        va[u] = ld_stream(&val[idx]);
+      }
+    }
+  }
+}
+
 // kb_pre_residual for a residual block already in the hierarchy precision,
 // with VW consecutive columns per lane and each gathered block row entry
 // loaded as one 16-byte vector (k a multiple of VW, blocks 16-byte aligned,
 // kv = k / VW); the same sums in the same order
-template <typename TV, int KT>
+template <typename TV, int KT, bool SHF>
 __global__ void __launch_bounds__(kBlock) kb_pre_residual_v(
     int32_t n, int32_t kv, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
     const TV *__restrict__ val, const TV *__restrict__ minv, const TV *__restrict__ R,
@@ -225,16 +262,7 @@ __global__ void __launch_bounds__(kBlock) kb_pre_residual_v(
       int32_t c[kRowBatch];
       TV v[kRowBatch];
       V g[kRowBatch];
-#pragma unroll
-      for (int u = 0; u < kRowBatch; ++u) {
-        c[u] = 0;
-        v[u] = 0;
-        if (k0 + u < w) {
-          const int32_t idx = base + (k0 + u) * kSlice;
-          c[u] = ld_stream(&col[idx]);
-          v[u] = ld_stream(&val[idx]);
-        }
-      }
+      row_batch<KT, SHF>(col, val, base, k0, w, c, v);
 #pragma unroll
       for (int u = 0; u < kRowBatch; ++u)
         if (k0 + u < w) g[u] = Rv[(int64_t)c[u] * kv + jv];
@@ -314,7 +342,7 @@ __global__ void __launch_bounds__(kBlock) kb_post(
 // kb_post with VW = Vec16<TV>::width consecutive columns per lane and each
 // gathered entry of Z loaded as one 16-byte vector (k a multiple of VW, blocks
 // 16-byte aligned, kv = k / VW); the same sums in the same order
-template <typename TV, typename TR, typename TO, int KT, bool DOT>
+template <typename TV, typename TR, typename TO, int KT, bool DOT, bool SHF>
 __global__ void __launch_bounds__(kBlock) kb_post_v(
     int32_t n, int32_t kv, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
     const TV *__restrict__ val, const TV *__restrict__ minv, const TR *__restrict__ R,
@@ -343,16 +371,7 @@ __global__ void __launch_bounds__(kBlock) kb_post_v(
         int32_t c[kRowBatch];
         TV v[kRowBatch];
         V g[kRowBatch];
-#pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) {
-          c[u] = 0;
-          v[u] = 0;
-          if (k0 + u < w) {
-            const int32_t idx = base + (k0 + u) * kSlice;
-            c[u] = ld_stream(&col[idx]);
-            v[u] = ld_stream(&val[idx]);
-          }
-        }
+        row_batch<KT, SHF>(col, val, base, k0, w, c, v);
 #pragma unroll
         for (int u = 0; u < kRowBatch; ++u)
           if (k0 + u < w) g[u] = Zv[(int64_t)c[u] * kv + jv];
@@ -619,7 +638,7 @@ __global__ void __launch_bounds__(kBlock) kb_spmv(
 // kb_spmv with two consecutive columns per lane, each gathered block row
 // entry loaded as one 16-byte vector (k even, blocks 16-byte aligned, kv =
 // k / 2): half the gather instructions; the same sums in the same order
-template <int KT, typename TA>
+template <int KT, typename TA, bool SHF>
 __global__ void __launch_bounds__(kBlock) kb_spmv_v(
     int32_t n, int32_t kv, const int32_t *__restrict__ sptr, const int32_t *__restrict__ col,
     const TA *__restrict__ val, const double *__restrict__ Xin,
@@ -642,16 +661,7 @@ __global__ void __launch_bounds__(kBlock) kb_spmv_v(
         int32_t c[kRowBatch];
         TA va[kRowBatch];  // as stored: converted at the product, not inside the guard
         double2 g[kRowBatch];
-#pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) {
-          c[u] = 0;
-          va[u] = 0;
-          if (k0 + u < w) {
-            const int32_t idx = base + (k0 + u) * kSlice;
-            c[u] = ld_stream(&col[idx]);
-            va[u] = ld_stream(&val[idx]);
-          }
-        }
+        row_batch<KT, SHF>(col, val, base, k0, w, c, va);
         double v[kRowBatch];
 #pragma unroll
         for (int u = 0; u < kRowBatch; ++u) v[u] = (double)va[u];
@@ -1084,8 +1094,12 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
       with_vec_tile(B, k / VW, [&](auto kt) {
         constexpr int KV = decltype(kt)::value;
         const BGeom gv = bgeom(F.n, k / VW, KV);
-        kb_pre_residual_v<TV, KV><<<gv.grid, kBlock, 0, s>>>(
-            F.n, k / VW, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), Rl, z, t, stop);
+        if ((k / VW) % KV == 0)  // every lane of a row active: shuffled index loads
+          kb_pre_residual_v<TV, KV, true><<<gv.grid, kBlock, 0, s>>>(
+              F.n, k / VW, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), Rl, z, t, stop);
+        else
+          kb_pre_residual_v<TV, KV, false><<<gv.grid, kBlock, 0, s>>>(
+              F.n, k / VW, F.S.sptr, F.S.col, svals<TV>(F), minv<TV>(F), Rl, z, t, stop);
       });
     else if (l == 0 && R0v)
       kb_pre_residual<TV, TV, KT><<<tgrid(g, k, KT), kBlock, 0, s>>>(
@@ -1188,9 +1202,14 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
           with_vec_tile(B, k / VW, [&](auto kt) {
             constexpr int KV = decltype(kt)::value;
             const BGeom gv = bgeom(F.n, k / VW, KV);
-            kb_post_v<TV, double, float, KV, true><<<gv.grid, kBlock, 0, s>>>(
-                F.n, k / VW, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, B.Zf,
-                B.partials, stop);
+            if ((k / VW) % KV == 0)
+              kb_post_v<TV, double, float, KV, true, true><<<gv.grid, kBlock, 0, s>>>(
+                  F.n, k / VW, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, B.Zf,
+                  B.partials, stop);
+            else
+              kb_post_v<TV, double, float, KV, true, false><<<gv.grid, kBlock, 0, s>>>(
+                  F.n, k / VW, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, B.Zf,
+                  B.partials, stop);
             np = (int32_t)gv.grid.x;
           });
           bfinalize(h, rz_op, np, maxit, stop);
@@ -1199,9 +1218,14 @@ void vcycle_b(amg_hierarchy *h, const double *R0, double *Z0, int32_t rz_op, int
           with_vec_tile(B, k / VW, [&](auto kt) {
             constexpr int KV = decltype(kt)::value;
             const BGeom gv = bgeom(F.n, k / VW, KV);
-            kb_post_v<TV, double, double, KV, true><<<gv.grid, kBlock, 0, s>>>(
-                F.n, k / VW, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, Z0,
-                B.partials, stop);
+            if ((k / VW) % KV == 0)
+              kb_post_v<TV, double, double, KV, true, true><<<gv.grid, kBlock, 0, s>>>(
+                  F.n, k / VW, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, Z0,
+                  B.partials, stop);
+            else
+              kb_post_v<TV, double, double, KV, true, false><<<gv.grid, kBlock, 0, s>>>(
+                  F.n, k / VW, F.S.sptr, F.S.col, vals<TV>(F), minv<TV>(F), R0, z, Z0,
+                  B.partials, stop);
             np = (int32_t)gv.grid.x;
           });
           bfinalize(h, rz_op, np, maxit, stop);
@@ -1235,14 +1259,21 @@ int32_t spmv_vec(amg_hierarchy *h, const double *Xin, const double *Bv, double *
     constexpr int KV = decltype(kt)::value;
     const BGeom g = bgeom(n, k / 2, KV);
     // level 0's exact FP32 copy of A when there is one: same numbers, half the bytes
-    if (L0.S.exact32)
-      kb_spmv_v<KV, float><<<g.grid, kBlock, 0, h->stream>>>(n, k / 2, L0.S.sptr, L0.S.col,
-                                                             L0.S.v32, Xin, Bv, Out, OutF,
-                                                             B.partials, mode, stop);
+    // with every lane of a row active, the row's index and value loads are
+    // shuffled from eight lanes
+    const bool shf = (k / 2) % KV == 0;
+    if (L0.S.exact32 && shf)
+      kb_spmv_v<KV, float, true><<<g.grid, kBlock, 0, h->stream>>>(
+          n, k / 2, L0.S.sptr, L0.S.col, L0.S.v32, Xin, Bv, Out, OutF, B.partials, mode, stop);
+    else if (L0.S.exact32)
+      kb_spmv_v<KV, float, false><<<g.grid, kBlock, 0, h->stream>>>(
+          n, k / 2, L0.S.sptr, L0.S.col, L0.S.v32, Xin, Bv, Out, OutF, B.partials, mode, stop);
+    else if (shf)
+      kb_spmv_v<KV, double, true><<<g.grid, kBlock, 0, h->stream>>>(
+          n, k / 2, L0.S.sptr, L0.S.col, L0.S.v64, Xin, Bv, Out, OutF, B.partials, mode, stop);
     else
-      kb_spmv_v<KV, double><<<g.grid, kBlock, 0, h->stream>>>(n, k / 2, L0.S.sptr, L0.S.col,
-                                                              L0.S.v64, Xin, Bv, Out, OutF,
-                                                              B.partials, mode, stop);
+      kb_spmv_v<KV, double, false><<<g.grid, kBlock, 0, h->stream>>>(
+          n, k / 2, L0.S.sptr, L0.S.col, L0.S.v64, Xin, Bv, Out, OutF, B.partials, mode, stop);
     nparts = (int32_t)g.grid.x;
   });
   return nparts;

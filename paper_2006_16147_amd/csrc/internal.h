@@ -83,8 +83,10 @@ struct Sell {
   double *s64 = nullptr;
   float *s32 = nullptr;
   int32_t max_width = 0;  // widest slice (entries per row); set for levels of <= 1024 rows
-  // every value of A is an FP32 number: v32 holds A exactly and the FP64
+  // every value of A is an FP32 number (checked on level 0 also when the
+  // FP32 copy is switched off); exact32: v32 holds A exactly and the FP64
   // kernels of level 0 read it (half the value bytes, identical arithmetic)
+  bool fp32_values = false;
   bool exact32 = false;
 };
 

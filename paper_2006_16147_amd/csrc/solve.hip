@@ -1701,14 +1701,16 @@ bool reads32(const Level &F, int32_t l) {
 }
 
 // whether level F's one-sweep down step forms z = M^-1 r in LDS and reads
-// the plain A: an FP64 level with down-step tiles. With level 0's exact
-// FP32 copy of A that is 4 value bytes per entry instead of the 8 of
-// A M^-1; without it the same bytes, and the same arithmetic either way, so
-// that the FP32 copy changes no result bit.
+// the plain A: an FP64 level with down-step tiles whose values are all FP32
+// numbers. With level 0's exact FP32 copy of A that is 4 value bytes per
+// entry instead of the 8 of A M^-1; with the copy switched off the same
+// arithmetic (so the copy changes no result bit) at 8 bytes. Other operators
+// stage r alone and read A M^-1: staging M^-1 r would gather 1 / m as well
+// for no saving.
 template <typename TV>
 bool staged_down(const amg_hierarchy *h, const Level &F, const Level &C) {
   const int32_t G = coarse_per_block(h) * down_rows(F.n);
-  return sizeof(TV) == 8 && F.hseg.ok() && F.hseg.param == G &&
+  return sizeof(TV) == 8 && F.S.fp32_values && F.hseg.ok() && F.hseg.param == G &&
          F.hseg.ntiles == ceil_div(C.n, G);
 }
 
@@ -2309,6 +2311,10 @@ amg_status build_halo(amg_hierarchy *h, const Level &L, const int32_t *tb, int32
 amg_status build_level0_halos(amg_hierarchy *h) {
   hipStream_t s = h->stream;
   Level &F = h->lv[0];
+  // none on levels of kManyRows rows or more: there the kernels take one row
+  // per thread (256-row tiles), and staging lost to the gathers from memory
+  // (256^3 anisotropic blocks: 144.2 -> 138.6 ms per FP64 solve without tiles)
+  if (F.n >= kManyRows) return AMG_OK;
   const Level &C = h->lv[1];
   int32_t *tb;
   const Geom g = geom(F.n);
@@ -2369,9 +2375,10 @@ amg_status build_solve_formats(amg_hierarchy *h) {
     // hierarchy precision (plain and scaled); the coarsest uses A_L^-1 only
     const bool need64 = (l == 0) || (!coarsest && !fp32);
     bool need32 = !coarsest && fp32;
-    if (l == 0 && !(h->params.flags & AMG_FLAG_NO_VALUE_COMPRESSION)) {
+    if (l == 0) {
       // every value of A an FP32 number: the FP64 products of level 0 read
       // the exact FP32 copy (identical arithmetic, half the value bytes)
+      // unless AMG_FLAG_NO_VALUE_COMPRESSION switches it off
       int32_t *flag;
       AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&flag), sizeof(int32_t), s));
       AMG_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
@@ -2380,7 +2387,8 @@ amg_status build_solve_formats(amg_hierarchy *h) {
       AMG_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
       AMG_HIP(hipStreamSynchronize(s));
       AMG_HIP(hipFreeAsync(flag, s));
-      L.S.exact32 = hflag == 0;
+      L.S.fp32_values = hflag == 0;
+      L.S.exact32 = L.S.fp32_values && !(h->params.flags & AMG_FLAG_NO_VALUE_COMPRESSION);
       need32 = need32 || L.S.exact32;
     }
     if (need64 || need32) {
