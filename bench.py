@@ -239,6 +239,39 @@ def kernel_summary(trace_csv):
             continue
         out.append("| `%s` | %d | %.2f | %.1f | %.1f |" % (
             _short(name), len(full), sum(full) / len(full), min(full), max(full)))
+    # The same kernels inside CG iterations only: the launches that follow a
+    # finalize (the down step after the CG update's sum) or p = z + beta p
+    # (the outer SpMV), or that a finalize follows (the post-smoothing and
+    # its CG dot). The back-to-back timing loops, whose launches find their
+    # data in L2, and the V-cycle timing loop (bracketed by the permutations)
+    # are left out; this is what the benchmark's in-solve figure times.
+    seqs = {}
+    for r in rows:
+        q = r.get("Queue_Id") or r.get("Stream_Id") or "0"
+        seqs.setdefault(q, []).append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]),
+                                       _short(r["Kernel_Name"]), _grid(r)))
+    insolve = {}
+    for seq in seqs.values():
+        seq.sort()
+        for i, (t0, t1, name, g) in enumerate(seq):
+            if not level0.match(name):
+                continue
+            prev = seq[i - 1][2] if i > 0 else ""
+            nxt = seq[i + 1][2] if i + 1 < len(seq) else ""
+            if prev.startswith(("k_finalize", "k_xpay")) or nxt.startswith("k_finalize"):
+                insolve.setdefault(name, []).append(((t1 - t0) / 1e3, g))
+    out += ["", "The same kernels inside CG iterations (launches next to the iteration's "
+            "finalize or p update; full launches only):", "",
+            "| kernel | launches | avg us | min us | max us |", "|---|---|---|---|---|"]
+    for name, v in sorted(insolve.items(), key=lambda kv: -sum(d for d, _ in kv[1])):
+        top = max(g for _, g in v)
+        ds = sorted(d for d, g in v if g == top)
+        med = ds[len(ds) // 2]
+        full = [d for d in ds if d >= 0.5 * med]
+        if sum(full) / len(full) < 20.0:
+            continue
+        out.append("| `%s` | %d | %.2f | %.1f | %.1f |" % (
+            name, len(full), sum(full) / len(full), min(full), max(full)))
     print("\n".join(out))
 
 
