@@ -691,20 +691,96 @@ __global__ void __launch_bounds__(1024) k_cholesky(int32_t n, double *D, int32_t
   }
 }
 
-// X = L^-1, one thread per column: forward substitution of L x = e_j.
-__global__ void k_tri_inverse(int32_t n, const double *L, double *X, double *XT) {
-  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  for (int32_t i = 0; i < j; ++i) {
-    X[(int64_t)i * n + j] = 0.0;
-    XT[(int64_t)j * n + i] = 0.0;
+// k_cholesky on the packed lower triangle held in LDS (n (n + 1) / 2 doubles,
+// up to 64 KB: n <= 127): the same steps on the same numbers, with every
+// access of the n steps in LDS instead of L2.
+constexpr int kCholLdsMax = 127;
+static_assert(kCholLdsMax * (kCholLdsMax + 1) / 2 * sizeof(double) <= 65536, "LDS triangle");
+__global__ void __launch_bounds__(1024) k_cholesky_lds(int32_t n, double *D, int32_t *err) {
+  extern __shared__ double tri[];  // row i of the lower triangle at i (i + 1) / 2
+  __shared__ int32_t bad;
+  auto at = [&](int32_t i, int32_t j) -> double & { return tri[i * (i + 1) / 2 + j]; };
+  for (int32_t e = threadIdx.x; e < n * (n + 1) / 2; e += blockDim.x) {
+    int32_t i = (int32_t)((sqrt(8.0 * e + 1.0) - 1.0) / 2.0);
+    while (i * (i + 1) / 2 > e) --i;
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    tri[e] = D[(int64_t)i * n + (e - i * (i + 1) / 2)];
   }
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int32_t k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      const double d = at(k, k);
+      if (!(d > 0.0)) bad = 1;
+      else at(k, k) = sqrt(d);
+    }
+    __syncthreads();
+    if (bad) break;
+    const double d = at(k, k);
+    for (int32_t i = k + 1 + threadIdx.x; i < n; i += blockDim.x) at(i, k) /= d;
+    __syncthreads();
+    const int32_t m = n - k - 1;
+    for (int32_t e = threadIdx.x; e < m * m; e += blockDim.x) {
+      const int32_t i = k + 1 + e / m, j = k + 1 + e % m;
+      if (j <= i) at(i, j) -= at(i, k) * at(j, k);
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (threadIdx.x == 0) atomicOr(err, kErrSpd);
+    return;
+  }
+  for (int32_t e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int32_t i = e / n, j = e % n;
+    D[e] = j > i ? 0.0 : at(i, j);
+  }
+}
+
+// X = L^-1, one block per column j: forward substitution of L x = e_j in its
+// right-looking form. Once x_i = t_i / L_ii is known, every later row r takes
+// off its term L_ri x_i, so each partial sum t_r loses its terms in the order
+// k = j, j + 1, ..., r - 1 of the row-by-row substitution (the same numbers).
+// t and the diagonal of L live in LDS; each thread owns the rows tid + s *
+// kTriThreads and loads their entries of the next column of L while the
+// current step runs, so a step waits on no memory access.
+constexpr int kTriThreads = 256;
+static_assert(AMG_MAX_DENSE % kTriThreads == 0, "whole rows per thread");
+static_assert(2 * sizeof(double) * AMG_MAX_DENSE <= 65536, "t and the diagonal fit in LDS");
+template <int S>  // rows per thread: S * kTriThreads >= n
+__global__ void __launch_bounds__(kTriThreads) k_tri_inverse(int32_t n,
+                                                             const double *__restrict__ L,
+                                                             double *__restrict__ X) {
+  extern __shared__ double tri_sh[];  // t[n], then the diagonal of L
+  double *t = tri_sh, *dg = tri_sh + n;
+  const int32_t j = blockIdx.x, tid = threadIdx.x;
+  for (int32_t r = tid; r < n; r += kTriThreads) {
+    t[r] = r == j ? 1.0 : 0.0;
+    dg[r] = L[(int64_t)r * n + r];
+    if (r < j) X[(int64_t)r * n + j] = 0.0;
+  }
+  double ln[S];  // this thread's rows' entries of column i of L
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    const int32_t r = tid + q * kTriThreads;
+    ln[q] = r > j && r < n ? L[(int64_t)r * n + j] : 0.0;
+  }
+  __syncthreads();
   for (int32_t i = j; i < n; ++i) {
-    double t = i == j ? 1.0 : 0.0;
-    for (int32_t k = j; k < i; ++k) t -= L[(int64_t)i * n + k] * X[(int64_t)k * n + j];
-    const double x = t / L[(int64_t)i * n + i];
-    X[(int64_t)i * n + j] = x;
-    XT[(int64_t)j * n + i] = x;
+    const double x = t[i] / dg[i];
+    if (tid == 0) X[(int64_t)i * n + j] = x;
+    double lc[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const int32_t r = tid + q * kTriThreads;
+      lc[q] = ln[q];
+      ln[q] = r > i + 1 && r < n ? L[(int64_t)r * n + i + 1] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const int32_t r = tid + q * kTriThreads;
+      if (r > i && r < n) t[r] -= lc[q] * x;
+    }
+    __syncthreads();
   }
 }
 
@@ -1126,15 +1202,23 @@ amg_status build_hierarchy(amg_hierarchy *h, const amg_csr *A) {
     AMG_HIP(hipMemsetAsync(D, 0, sizeof(double) * (size_t)nL * nL, s));
     k_dense_scatter<<<grid(nL), kBlock, 0, s>>>(nL, L.rp, L.ci, L.val, D);
     k_fill<int32_t><<<1, 1, 0, s>>>(err, 0, 1);
-    k_cholesky<<<1, 1024, 0, s>>>(nL, D, err);
+    if (nL <= kCholLdsMax)
+      k_cholesky_lds<<<1, 1024, sizeof(double) * (size_t)nL * (nL + 1) / 2, s>>>(nL, D, err);
+    else
+      k_cholesky<<<1, 1024, 0, s>>>(nL, D, err);
     AMG_TRY(read_i32(err, &herr, s));
     if (herr) return AMG_ERR_NOT_SPD;
     h->C.n = nL;
-    double *LinvT;
-    AMG_TRY(tmp.get(&LinvT, (size_t)nL * nL));
     AMG_TRY(dalloc(h, &h->C.Linv, (size_t)nL * nL));
     AMG_TRY(dalloc(h, &h->C.Ainv, (size_t)nL * nL));
-    k_tri_inverse<<<grid(nL), kBlock, 0, s>>>(nL, D, h->C.Linv, LinvT);
+    const size_t tri_lds = 2 * sizeof(double) * (size_t)nL;  // <= 64 KB (nL <= AMG_MAX_DENSE)
+    if (nL <= kTriThreads)
+      k_tri_inverse<1><<<nL, kTriThreads, tri_lds, s>>>(nL, D, h->C.Linv);
+    else if (nL <= 4 * kTriThreads)
+      k_tri_inverse<4><<<nL, kTriThreads, tri_lds, s>>>(nL, D, h->C.Linv);
+    else
+      k_tri_inverse<AMG_MAX_DENSE / kTriThreads><<<nL, kTriThreads, tri_lds, s>>>(nL, D,
+                                                                                  h->C.Linv);
     k_inverse_from_factor<<<grid((int64_t)nL * nL), kBlock, 0, s>>>(nL, h->C.Linv, h->C.Ainv);
     AMG_HIP(hipStreamSynchronize(s));
   }
