@@ -674,11 +674,10 @@ __global__ void __launch_bounds__(1024) k_cholesky(int32_t n, double *D, int32_t
     const double d = D[(int64_t)k * n + k];
     for (int32_t i = k + 1 + threadIdx.x; i < n; i += blockDim.x) D[(int64_t)i * n + k] /= d;
     __syncthreads();
-    const int64_t m = n - k - 1;
-    for (int64_t e = threadIdx.x; e < m * m; e += blockDim.x) {
-      const int32_t i = k + 1 + (int32_t)(e / m), j = k + 1 + (int32_t)(e % m);
-      if (j <= i) D[(int64_t)i * n + j] -= D[(int64_t)i * n + k] * D[(int64_t)j * n + k];
-    }
+    // trailing update of the lower triangle, threads in rows of 32 over (i, j)
+    for (int32_t i = k + 1 + (int32_t)threadIdx.x / 32; i < n; i += (int32_t)blockDim.x / 32)
+      for (int32_t j = k + 1 + (int32_t)threadIdx.x % 32; j <= i; j += 32)
+        D[(int64_t)i * n + j] -= D[(int64_t)i * n + k] * D[(int64_t)j * n + k];
     __syncthreads();
   }
   if (bad) {
@@ -719,11 +718,9 @@ __global__ void __launch_bounds__(1024) k_cholesky_lds(int32_t n, double *D, int
     const double d = at(k, k);
     for (int32_t i = k + 1 + threadIdx.x; i < n; i += blockDim.x) at(i, k) /= d;
     __syncthreads();
-    const int32_t m = n - k - 1;
-    for (int32_t e = threadIdx.x; e < m * m; e += blockDim.x) {
-      const int32_t i = k + 1 + e / m, j = k + 1 + e % m;
-      if (j <= i) at(i, j) -= at(i, k) * at(j, k);
-    }
+    for (int32_t i = k + 1 + (int32_t)threadIdx.x / 32; i < n; i += (int32_t)blockDim.x / 32)
+      for (int32_t j = k + 1 + (int32_t)threadIdx.x % 32; j <= i; j += 32)
+        at(i, j) -= at(i, k) * at(j, k);
     __syncthreads();
   }
   if (bad) {
