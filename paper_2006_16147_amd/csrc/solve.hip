@@ -513,6 +513,24 @@ __global__ void __launch_bounds__(kBlock) k_pre_restrict_lds(
   const int32_t J1 = min(nc, J0 + G);
   const int32_t f0 = seg[J0], f1 = seg[J1];
   const int32_t h0 = hptr[tb];
+  // the operands that do not come from the staged tile are loaded first, so
+  // their latency overlaps the staging
+  int32_t pb[R], pw[R];
+  TV pr[R], pm[R], pq[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int32_t row = f0 + (int32_t)threadIdx.x + u * kBlock;
+    pb[u] = pw[u] = 0;
+    pr[u] = pm[u] = pq[u] = TV(0);
+    if (row < f1) {
+      sell_row(sptr, row, &pb[u], &pw[u]);
+      pr[u] = (TV)r[row];
+      if (MODE != kPreFromZ) pm[u] = minv[row];
+      pq[u] = pp[row];
+    }
+  }
+  const int32_t Jt = J0 + (int32_t)threadIdx.x;
+  const int32_t sb = Jt < J1 ? seg[Jt] : 0, se = Jt < J1 ? seg[Jt + 1] : 0;
   if (MODE == kPreFromZ)
     stage_tile(xs, hidx, h0, hptr[tb + 1] - h0, [&](int32_t c) { return z[c]; });
   else if (MODE == kPreStagedZ)
@@ -524,17 +542,15 @@ __global__ void __launch_bounds__(kBlock) k_pre_restrict_lds(
   for (int u = 0; u < R; ++u) {
     const int32_t row = f0 + (int32_t)threadIdx.x + u * kBlock;
     if (row < f1) {
-      int32_t base, w;
-      sell_row(sptr, row, &base, &w);
-      const TV acc = sell_dot_lds<TV, TA>(lcol, val, base, w, xs);
-      const TV ri = (TV)r[row];
-      if (MODE != kPreFromZ) z[row] = ri * minv[row];
-      sh[threadIdx.x + u * kBlock] = pp[row] * (ri - acc);
+      const TV acc = sell_dot_lds<TV, TA>(lcol, val, pb[u], pw[u], xs);
+      const TV ri = pr[u];
+      if (MODE != kPreFromZ) z[row] = ri * pm[u];
+      sh[threadIdx.x + u * kBlock] = pq[u] * (ri - acc);
     }
   }
   __syncthreads();
-  for (int32_t J = J0 + (int32_t)threadIdx.x; J < J1; J += kBlock) {
-    const int32_t b = seg[J] - f0, e = seg[J + 1] - f0;
+  for (int32_t J = Jt; J < J1; J += kBlock) {
+    const int32_t b = (J == Jt ? sb : seg[J]) - f0, e = (J == Jt ? se : seg[J + 1]) - f0;
     TV s = 0;
     for (int32_t m = b; m < e; ++m) s += sh[m];
     rc[J] = s;
@@ -557,11 +573,13 @@ __global__ void __launch_bounds__(kBlock) k_post_lds(
   rb = (int32_t)((int64_t)tb * chunk);
   re = (int32_t)min((int64_t)n, (int64_t)rb + chunk);
   const int32_t h0 = hptr[tb];
+  int32_t row = rb + (int32_t)threadIdx.x, nb = 0, nw = 0;
+  if (row < re) sell_row(sptr, row, &nb, &nw);
   stage_tile(xs, hidx, h0, hptr[tb + 1] - h0, [&](int32_t c) { return z[c]; });
   double d[1] = {0.0};
-  for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
-    int32_t base, w;
-    sell_row(sptr, row, &base, &w);
+  for (; row < re; row += kBlock) {
+    const int32_t base = nb, w = nw;
+    if (row + kBlock < re) sell_row(sptr, row + kBlock, &nb, &nw);
     const TV acc = sell_dot_lds<TV, TA>(lcol, val, base, w, xs);
     const TR rr = r[row];
     const TO yo = (TO)(z[row] + ((TV)rr - acc) * minv[row]);
@@ -1011,11 +1029,13 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot_lds(
   rb = (int32_t)((int64_t)tb * chunk);
   re = (int32_t)min((int64_t)n, (int64_t)rb + chunk);
   const int32_t h0 = hptr[tb];
+  int32_t row = rb + (int32_t)threadIdx.x, nb = 0, nw = 0;
+  if (row < re) sell_row(sptr, row, &nb, &nw);
   stage_tile(lds_d, hidx, h0, hptr[tb + 1] - h0, [&](int32_t c) { return p[c]; });
   double d[1] = {0.0};
-  for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
-    int32_t base, w;
-    sell_row(sptr, row, &base, &w);
+  for (; row < re; row += kBlock) {
+    const int32_t base = nb, w = nw;
+    if (row + kBlock < re) sell_row(sptr, row + kBlock, &nb, &nw);
     const double acc = sell_dot_lds<double, TA>(lcol, val, base, w, lds_d);
     q[row] = acc;
     d[0] += p[row] * acc;
