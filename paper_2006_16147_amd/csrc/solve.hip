@@ -392,24 +392,30 @@ __global__ void __launch_bounds__(kBlock) k_pre_restrict(
   const int32_t J0 = blockIdx.x * G;
   const int32_t J1 = min(nc, J0 + G);
   const int32_t f0 = seg[J0], f1 = seg[J1];
+  // the thread's segment bounds for the sums after the barrier, loaded now
+  const int32_t Jt = J0 + (int32_t)threadIdx.x;
+  const int32_t sb = Jt < J1 ? seg[Jt] : 0, se = Jt < J1 ? seg[Jt + 1] : 0;
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     const int32_t row = f0 + (int32_t)threadIdx.x + u * kBlock;
     if (row < f1) {
+      // the row's own operands first: their loads overlap the gathers
+      const TV ri = (TV)r[row];
+      const TV mi = MODE == kPreScaled ? minv[row] : TV(0);
+      const TV pv = pp[row];
       int32_t base, w;
       sell_row(sptr, row, &base, &w);
       const TV acc =
           MODE == kPreFromZ
               ? sell_dot_t<TV, TA>(col, val, base, w, [&](int32_t c) { return z[c]; })
               : sell_dot_t<TV, TA>(col, val, base, w, [&](int32_t c) { return (TV)r[c]; });
-      const TV ri = (TV)r[row];
-      if (MODE == kPreScaled) z[row] = ri * minv[row];
-      sh[threadIdx.x + u * kBlock] = pp[row] * (ri - acc);
+      if (MODE == kPreScaled) z[row] = ri * mi;
+      sh[threadIdx.x + u * kBlock] = pv * (ri - acc);
     }
   }
   __syncthreads();
-  for (int32_t J = J0 + (int32_t)threadIdx.x; J < J1; J += kBlock) {
-    const int32_t b = seg[J] - f0, e = seg[J + 1] - f0;
+  for (int32_t J = Jt; J < J1; J += kBlock) {
+    const int32_t b = (J == Jt ? sb : seg[J]) - f0, e = (J == Jt ? se : seg[J + 1]) - f0;
     TV s = 0;
     for (int32_t m = b; m < e; ++m) s += sh[m];
     rc[J] = s;
