@@ -435,11 +435,12 @@ __global__ void __launch_bounds__(kBlock) k_post(
   rows_of_block(n, chunk, &rb, &re);
   double d[1] = {0.0};
   for (int32_t row = rb + threadIdx.x; row < re; row += kBlock) {
+    const TR rr = r[row];
+    const TV zr = z[row], mr = minv[row];
     int32_t base, w;
     sell_row(sptr, row, &base, &w);
     const TV acc = sell_dot_t<TV, TA>(col, val, base, w, [&](int32_t c) { return z[c]; });
-    const TR rr = r[row];
-    const TO yo = (TO)(z[row] + ((TV)rr - acc) * minv[row]);
+    const TO yo = (TO)(zr + ((TV)rr - acc) * mr);
     y[row] = yo;
     if (DOT) d[0] += (dv ? dv[row] : (double)rr) * (double)yo;
   }
@@ -759,15 +760,17 @@ __global__ void __launch_bounds__(kBlock) k_post_prolong(
   if (*done) return;
   const int32_t J0 = blockIdx.x * kBlock;
   const int32_t J = J0 + threadIdx.x;
+  // the fine range and the row's own operands first: their loads overlap the gathers
+  const int32_t J1 = min(nc, J0 + kBlock);
+  const int32_t f0 = seg[J0], f1 = seg[J1];
   if (J < nc) {
+    const TV zj = zc[J], rj = rcv[J], mj = minv[J];
     int32_t base, w;
     sell_row(sptr, J, &base, &w);
     const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return zc[c]; });
-    sh[threadIdx.x] = zc[J] + (rcv[J] - acc) * minv[J];
+    sh[threadIdx.x] = zj + (rj - acc) * mj;
   }
   __syncthreads();
-  const int32_t J1 = min(nc, J0 + kBlock);
-  const int32_t f0 = seg[J0], f1 = seg[J1];
   prolong_add(f0, f1, (int32_t)threadIdx.x, kBlock, aggp, pp, zf,
               [&](int32_t a) { return sh[a - J0]; });
 }
