@@ -854,6 +854,23 @@ __global__ void __launch_bounds__(1024) k_tail(
     const int32_t k = part + m * kCoarseSplit;
     av[m] = one_pass && irow < nL && k < nL ? Ainv[(int64_t)irow * nL + k] : 0.0;
   }
+  // the thread's first row of level t: its slice position, p, its coarse
+  // position and its segment bounds, loaded with r so that the later phases
+  // start without a round trip to memory
+  int32_t b0 = 0, w0 = 0, a0 = 0, sb0 = 0, se0 = 0;
+  TV p0 = 0;
+  if (tid < nt) {
+    const int32_t s = tid / kSlice;
+    const int32_t s0 = sptr[s], s1 = sptr[s + 1];
+    b0 = s0 + tid % kSlice;
+    w0 = (s1 - s0) / kSlice;
+    p0 = pp[tid];
+    a0 = aggp[tid];
+  }
+  if (tid < nL) {
+    sb0 = seg[tid];
+    se0 = seg[tid + 1];
+  }
   for (int32_t k = tid; k < nt; k += nth) {
     const TV r = rt[k];
     rs[k] = r;
@@ -862,14 +879,20 @@ __global__ void __launch_bounds__(1024) k_tail(
   __syncthreads();
   // t = p (r - A M^-1 r), kept in ys
   for (int32_t k = tid; k < nt; k += nth) {
-    const int32_t s = k / kSlice, base = sptr[s] + k % kSlice, w = (sptr[s + 1] - sptr[s]) / kSlice;
+    int32_t base = b0, w = w0;
+    if (k != tid) {
+      const int32_t s = k / kSlice;
+      base = sptr[s] + k % kSlice;
+      w = (sptr[s + 1] - sptr[s]) / kSlice;
+    }
     const TV acc = sell_dot(col, sval, base, w, [&](int32_t c) { return rs[c]; });
-    ys[k] = pp[k] * (rs[k] - acc);
+    ys[k] = (k == tid ? p0 : pp[k]) * (rs[k] - acc);
   }
   __syncthreads();
   for (int32_t J = tid; J < nL; J += nth) {
     TV a = 0;
-    for (int32_t m = seg[J]; m < seg[J + 1]; ++m) a += ys[m];
+    const int32_t mb = J == tid ? sb0 : seg[J], me = J == tid ? se0 : seg[J + 1];
+    for (int32_t m = mb; m < me; ++m) a += ys[m];
     rl[J] = (double)a;
   }
   __syncthreads();
@@ -895,11 +918,17 @@ __global__ void __launch_bounds__(1024) k_tail(
     }
   }
   __syncthreads();
-  for (int32_t k = tid; k < nt; k += nth) zs[k] += pp[k] * (TV)zl[aggp[k]];
+  for (int32_t k = tid; k < nt; k += nth)
+    zs[k] += (k == tid ? p0 : pp[k]) * (TV)zl[k == tid ? a0 : aggp[k]];
   __syncthreads();
   // post-smoothing on level t
   for (int32_t k = tid; k < nt; k += nth) {
-    const int32_t s = k / kSlice, base = sptr[s] + k % kSlice, w = (sptr[s + 1] - sptr[s]) / kSlice;
+    int32_t base = b0, w = w0;
+    if (k != tid) {
+      const int32_t s = k / kSlice;
+      base = sptr[s] + k % kSlice;
+      w = (sptr[s + 1] - sptr[s]) / kSlice;
+    }
     const TV acc = sell_dot(col, val, base, w, [&](int32_t c) { return zs[c]; });
     ys[k] = zs[k] + (rs[k] - acc) * minv[k];
   }
