@@ -136,6 +136,38 @@ def test_setup_error_codes(orc):
     assert setup_status(M)[0] == amg.Status.ERR_NOT_SPD
 
 
+@pytest.mark.parametrize("N", [5, 6, 9, 12])
+def test_coarsest_factor_forms(N):
+    """Single-level hierarchies whose dense factor takes each form of the
+    kernels: the Cholesky on the packed triangle in LDS (n = 125) or in global
+    memory (n = 216, 729, 1728), and L^-1 with 1, 1, 4 and 16 rows per thread.
+    The cycle is then z = A^-1 r, checked against a dense FP64 solve."""
+    import torch
+
+    from paper_2006_16147_amd import amg
+
+    A = inputs.laplacian7(N)
+    h = setup(A, max_coarse=A.n)
+    assert h.sizes() == [A.n]
+    r = np.random.default_rng(N).uniform(-1.0, 1.0, A.n)
+    z = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+    amg.amg_vcycle_apply(h, to_dev(r), z)
+    ref = np.linalg.solve(A.to_dense(), r)
+    err = np.linalg.norm(z.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err < 1e-11, err  # kappa(A) < 70: a wrong factor errs by O(1)
+
+
+def test_indefinite_coarsest_in_global_memory():
+    """The global-memory Cholesky (n > 127) reports an indefinite matrix:
+    symmetric with a positive diagonal, eigenvalues 1 + 2 (n - 1) and -1."""
+    from paper_2006_16147_amd import amg
+
+    n = 200
+    D = 2.0 * np.ones((n, n)) - np.eye(n)
+    M = inputs.Csr(n, np.arange(n + 1) * n, np.tile(np.arange(n), n), D.ravel())
+    assert setup_status(M, max_coarse=n)[0] == amg.Status.ERR_NOT_SPD
+
+
 def test_setup_is_deterministic():
     A = inputs.diffusion7(16, 0.01, 1.0, 0.3)
     h1, h2 = setup(A), setup(A)
