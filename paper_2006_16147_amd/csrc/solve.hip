@@ -1695,23 +1695,29 @@ int32_t coarse_per_block(const amg_hierarchy *h) {
   return g < 1 ? 1 : g;
 }
 
-// Down step of level F into C with down_rows(n) fine rows per thread; with
-// LDS-staged gathers where the level has tiles of this geometry.
+// coarse rows per block of the LDS-staged down step (one fine row per thread:
+// with its operands loaded ahead of the staging barrier, two rows per thread
+// held more registers than they hid latency)
+int32_t staged_down_G(const amg_hierarchy *h) { return coarse_per_block(h); }
+
+// Down step of level F into C: LDS-staged gathers where the level has tiles of
+// that geometry, else down_rows(n) fine rows per thread gathering from memory.
 template <typename TV, typename TR, int MODE, typename TA>
 void pre_restrict(const amg_hierarchy *h, const Level &F, const Level &C, const TA *val,
                   const TV *mv, const TV *pp, const TR *r, TV *z, TV *rc, const int32_t *done) {
   hipStream_t s = h->stream;
+  const int32_t Gt = staged_down_G(h);
+  if (F.hseg.ok() && F.hseg.param == Gt && F.hseg.ntiles == ceil_div(C.n, Gt)) {
+    const Halo &H = F.hseg;
+    launch_k(h, k_pre_restrict_lds<TV, TR, MODE, TA, 1>, dim3(ceil_div(C.n, Gt)), dim3(kBlock),
+             (uint32_t)(sizeof(TV) * H.umax), s, C.n, Gt, F.seg, F.S.sptr,
+             (const uint16_t *)H.lcol, (const int32_t *)H.hptr, (const int32_t *)H.hidx, val, mv,
+             pp, r, z, rc, done);
+    return;
+  }
   const int R = down_rows(F.n);
   const int32_t G = coarse_per_block(h) * R;
   const int32_t grid = ceil_div(C.n, G);
-  if (F.hseg.ok() && F.hseg.param == G && F.hseg.ntiles == grid) {
-    const Halo &H = F.hseg;
-    auto k = R == 2 ? k_pre_restrict_lds<TV, TR, MODE, TA, 2> : k_pre_restrict_lds<TV, TR, MODE, TA, 1>;
-    launch_k(h, k, dim3(grid), dim3(kBlock), (uint32_t)(sizeof(TV) * H.umax), s, C.n, G, F.seg,
-             F.S.sptr, (const uint16_t *)H.lcol, (const int32_t *)H.hptr, (const int32_t *)H.hidx,
-             val, mv, pp, r, z, rc, done);
-    return;
-  }
   auto k = R == 2 ? k_pre_restrict<TV, TR, MODE, TA, 2> : k_pre_restrict<TV, TR, MODE, TA, 1>;
   launch_k(h, k, dim3(grid), dim3(kBlock), 0u, s, C.n, G, F.seg, F.S.sptr, F.S.col, val, mv, pp,
            r, z, rc, done);
@@ -1780,7 +1786,7 @@ bool reads32(const Level &F, int32_t l) {
 // for no saving.
 template <typename TV>
 bool staged_down(const amg_hierarchy *h, const Level &F, const Level &C) {
-  const int32_t G = coarse_per_block(h) * down_rows(F.n);
+  const int32_t G = staged_down_G(h);
   return sizeof(TV) == 8 && F.S.fp32_values && F.hseg.ok() && F.hseg.param == G &&
          F.hseg.ntiles == ceil_div(C.n, G);
 }
@@ -2389,7 +2395,7 @@ amg_status build_level0_halos(amg_hierarchy *h) {
   const Level &C = h->lv[1];
   int32_t *tb;
   const Geom g = geom(F.n);
-  const int32_t G = coarse_per_block(h) * down_rows(F.n);
+  const int32_t G = staged_down_G(h);
   const int32_t nseg = ceil_div(C.n, G);
   const int32_t most = std::max(g.grid, nseg);
   AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&tb), sizeof(int32_t) * (most + 1), s));
