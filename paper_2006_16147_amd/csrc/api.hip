@@ -500,8 +500,10 @@ size_t amg_estimate_footprint(int64_t n, int64_t nnz, const amg_params *params) 
   b += 6 * 8.0 * n;                             // CG vectors (x, r, z, p, q, b)
   b += (double)kPartPlanes * kMaxParts * 8.0;   // block partials
   if (P.cycle == AMG_CYCLE_K) b += 5 * V * (sn - n);  // K-cycle FCG vectors
-  // peak of the setup temporaries (weights, Galerkin staging, sweep matrices)
-  b += 8.0 * nnz + 12.0 * nnz + 2 * (12.0 * nnz + 16.0 * n);
+  // the setup's temporaries (weights, matching state, Galerkin staging, sweep
+  // matrices), all held until the setup ends: about twice the first sweep's,
+  // plus one partly used arena block (a quarter of the first sweep's)
+  b += 2 * (46.0 * n + 28.0 * nnz) + (36.0 * n + 32.0 * nnz) / 4;
   const double nL = P.max_coarse;
   b += 3 * 8.0 * nL * nL;
   if (P.smooth_p) {

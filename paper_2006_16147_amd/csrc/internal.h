@@ -226,6 +226,7 @@ struct amg_hierarchy {
   double *kscal = nullptr;  // K-cycle scalars, kKScal per level
   amg::PcgScal *scal = nullptr;   // device
   amg::PcgScal *scal_host = nullptr;  // pinned mirror
+  void *setup_arena = nullptr;  // the running setup's temporaries (setup.hip), else null
   int32_t *zero_flag = nullptr;   // device int 0 (for kernels outside CG)
   // batch (multi-right-hand-side) solve state, allocated for the last k used
   amg::Batch *batch = nullptr;

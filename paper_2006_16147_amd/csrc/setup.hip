@@ -797,13 +797,75 @@ __global__ void k_inverse_from_factor(int32_t n, const double *X, double *Ainv) 
 
 inline int32_t grid(int64_t n) { return ceil_div(n > 0 ? n : 1, kBlock); }
 
-// temporaries of one setup call (not owned by the hierarchy)
-// (released in stream order on the setup stream when dropped or destroyed)
+// block count of the exclusive scan of n values (its block sums take nb + 1)
+int32_t scan_blocks(int32_t n) { return ceil_div(n > 0 ? n : 1, kScanBlock * kScanPer); }
+
+// exclusive scan with the caller's block-sum scratch (scan_blocks(n) + 1 ints)
+void scan_exclusive_i32_with(const int32_t *in, int32_t *out, int32_t n, int32_t *bsum,
+                             hipStream_t s) {
+  const int32_t nb = scan_blocks(n);
+  k_scan_local<<<nb, kScanBlock, 0, s>>>(in, out, bsum, n);
+  k_scan_sums<<<1, kScanBlock, 0, s>>>(bsum, nb);
+  k_scan_add<<<grid((int64_t)n + 1), kBlock, 0, s>>>(out, bsum, n, nb);
+}
+
+// Device memory for the temporaries of one setup call: a few large pool
+// blocks, cut in order and given back together when the setup ends. On this
+// runtime a stream-ordered allocation or free takes tens of microseconds of
+// host time, a setup needs hundreds of them, and between its latency-bound
+// kernels the GPU waits for the host; cut from the arena they cost nothing,
+// at the price of keeping every temporary of the setup until its end.
+struct Arena {
+  int device;
+  hipStream_t s;
+  size_t chunk;  // block size: a quarter of the first sweep's temporaries, 1-256 MB
+  std::vector<void *> blocks;
+  char *cur = nullptr;
+  size_t left = 0;
+  Arena(const amg_hierarchy *h, int64_t n, int64_t nnz) : device(h->device), s(h->stream) {
+    const double q = (36.0 * (double)n + 32.0 * (double)nnz) / 4;
+    const double mb = double(1 << 20);
+    chunk = (size_t)(q < mb ? mb : (q > 256 * mb ? 256 * mb : q));
+    chunk = (chunk + (1 << 20) - 1) / (1 << 20) * (1 << 20);
+  }
+  Arena(const Arena &) = delete;
+  Arena &operator=(const Arena &) = delete;
+  ~Arena() {
+    for (void *p : blocks) stream_free(device, s, p);
+  }
+  amg_status get(void **p, size_t bytes) {
+    bytes = (bytes + 255) / 256 * 256;
+    if (bytes > chunk / 4) {  // a large request gets a block of its own
+      void *q = nullptr;
+      AMG_TRY(stream_alloc(device, s, &q, bytes));
+      blocks.push_back(q);
+      *p = q;
+      return AMG_OK;
+    }
+    if (bytes > left) {
+      void *q = nullptr;
+      AMG_TRY(stream_alloc(device, s, &q, chunk));
+      blocks.push_back(q);
+      cur = static_cast<char *>(q);
+      left = chunk;
+    }
+    *p = cur;
+    cur += bytes;
+    left -= bytes;
+    return AMG_OK;
+  }
+};
+
+// temporaries of one setup call (not owned by the hierarchy): cut from the
+// setup's arena while one runs (dropping them then does nothing), else pool
+// allocations released in stream order when dropped or destroyed
 struct Tmp {
   int device;
   hipStream_t s;
+  Arena *arena;
   std::vector<void *> ptrs;
-  explicit Tmp(const amg_hierarchy *h) : device(h->device), s(h->stream) {}
+  explicit Tmp(const amg_hierarchy *h)
+      : device(h->device), s(h->stream), arena(static_cast<Arena *>(h->setup_arena)) {}
   Tmp(const Tmp &) = delete;
   Tmp &operator=(const Tmp &) = delete;
   ~Tmp() {
@@ -812,8 +874,12 @@ struct Tmp {
   template <typename T>
   amg_status get(T **p, size_t count) {
     void *q = nullptr;
-    AMG_TRY(stream_alloc(device, s, &q, count * sizeof(T) + 16));
-    ptrs.push_back(q);
+    if (arena) {
+      AMG_TRY(arena->get(&q, count * sizeof(T) + 16));
+    } else {
+      AMG_TRY(stream_alloc(device, s, &q, count * sizeof(T) + 16));
+      ptrs.push_back(q);
+    }
     *p = reinterpret_cast<T *>(q);
     return AMG_OK;
   }
@@ -823,6 +889,13 @@ struct Tmp {
         stream_free(device, s, q);
         q = nullptr;
       }
+  }
+  // exclusive scan of n values, its block sums in this object's memory
+  amg_status scan(const int32_t *in, int32_t *out, int32_t n) {
+    int32_t *bsum = nullptr;
+    AMG_TRY(get(&bsum, (size_t)scan_blocks(n) + 1));
+    scan_exclusive_i32_with(in, out, n, bsum, s);
+    return AMG_OK;
   }
 };
 
@@ -920,7 +993,7 @@ amg_status pairwise_sweep(amg_hierarchy *h, Tmp &tmp, const Mat &A, SweepOut &o,
   AMG_TRY(tmp.get(&flag, n));
   AMG_TRY(tmp.get(&id, n + 1));
   k_leader<<<grid(n), kBlock, 0, s>>>(n, mate, flag);
-  AMG_TRY(scan_exclusive_i32(flag, id, n, s));
+  AMG_TRY(tmp.scan(flag, id, n));
   int32_t nc = 0;
   AMG_TRY(read_i32(id + n, &nc, s));
   o.nc = nc;
@@ -949,7 +1022,7 @@ amg_status pairwise_sweep(amg_hierarchy *h, Tmp &tmp, const Mat &A, SweepOut &o,
   err = novf + 1;
   k_fill<int32_t><<<1, 2, 0, s>>>(novf, 0, 2);
   k_rap_inlen<<<grid(nc), kBlock, 0, s>>>(nc, o.lead, mate, A.rp, inlen);
-  AMG_TRY(scan_exclusive_i32(inlen, toff, nc, s));
+  AMG_TRY(tmp.scan(inlen, toff, nc));
   AMG_TRY(tmp.get(&tJ, A.nnz));
   AMG_TRY(tmp.get(&tV, A.nnz));
   k_rap_rows<<<grid(nc), kBlock, 0, s>>>(nc, o.lead, mate, A.rp, A.ci, A.val, o.agg, o.p, toff,
@@ -962,7 +1035,7 @@ amg_status pairwise_sweep(amg_hierarchy *h, Tmp &tmp, const Mat &A, SweepOut &o,
   Mat &C = o.Ac;
   C.n = nc;
   AMG_TRY(tmp.get(&C.rp, nc + 1));
-  AMG_TRY(scan_exclusive_i32(cnt, C.rp, nc, s));
+  AMG_TRY(tmp.scan(cnt, C.rp, nc));
   int32_t nnzc = 0;
   AMG_TRY(read_i32(C.rp + nc, &nnzc, s));
   C.nnz = nnzc;
@@ -1002,13 +1075,10 @@ amg_status adopt_level(amg_hierarchy *h, const Mat &M, Level &L) {
 }  // namespace
 
 amg_status scan_exclusive_i32(const int32_t *in, int32_t *out, int32_t n, hipStream_t s) {
-  const int32_t per_block = kScanBlock * kScanPer;
-  const int32_t nb = ceil_div(n > 0 ? n : 1, per_block);
+  const int32_t nb = scan_blocks(n);
   int32_t *bsum = nullptr;
   AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&bsum), sizeof(int32_t) * (nb + 1), s));
-  k_scan_local<<<nb, kScanBlock, 0, s>>>(in, out, bsum, n);
-  k_scan_sums<<<1, kScanBlock, 0, s>>>(bsum, nb);
-  k_scan_add<<<grid((int64_t)n + 1), kBlock, 0, s>>>(out, bsum, n, nb);
+  scan_exclusive_i32_with(in, out, n, bsum, s);
   AMG_HIP(hipFreeAsync(bsum, s));
   return AMG_OK;
 }
@@ -1019,6 +1089,14 @@ amg_status build_hierarchy(amg_hierarchy *h, const amg_csr *A) {
   const int32_t n0 = (int32_t)A->n;
   double T[8] = {0};
   double t_start = now_ms();
+  // every temporary of this setup comes from one arena (declared before the
+  // Tmp objects, so it outlives them), detached again on every way out
+  Arena arena(h, A->n, A->nnz);
+  struct Attach {
+    amg_hierarchy *h;
+    ~Attach() { h->setup_arena = nullptr; }
+  } attach{h};
+  h->setup_arena = &arena;
   Tmp tmp(h);
 
   // validation
@@ -1112,7 +1190,7 @@ amg_status build_hierarchy(amg_hierarchy *h, const amg_csr *A) {
       AMG_TRY(sweep_tmp.get(&mptr_n, o.nc + 1));
       AMG_TRY(sweep_tmp.get(&mem_n, n));
       k_member_size<<<grid(o.nc), kBlock, 0, s>>>(o.nc, o.lead, o.mate, mptr, msz);
-      AMG_TRY(scan_exclusive_i32(msz, mptr_n, o.nc, s));
+      AMG_TRY(sweep_tmp.scan(msz, mptr_n, o.nc));
       k_member_merge<<<grid(o.nc), kBlock, 0, s>>>(o.nc, o.lead, o.mate, mptr, mem, mptr_n,
                                                    mem_n);
       AMG_HIP(hipStreamSynchronize(s));
