@@ -251,9 +251,12 @@ struct amg_hierarchy {
   bool async_pending = false;
   std::atomic<int> async_finished{0};
   amg_status async_status = AMG_OK;
-  // bookkeeping
+  // bookkeeping: the pool blocks the hierarchy's arrays are cut from (see
+  // dev_alloc), the bytes requested, and the free tail of the current block
   std::vector<void *> allocs;
   size_t bytes = 0;
+  char *block_cur = nullptr;
+  size_t block_left = 0;
   double setup_ms[8] = {0};
 };
 
@@ -272,7 +275,6 @@ template <typename T>
 inline amg_status dalloc(amg_hierarchy *h, T **p, size_t count) {
   return dev_alloc(h, reinterpret_cast<void **>(p), count * sizeof(T) + 16);
 }
-void dev_release(amg_hierarchy *h, void *p);
 
 // orders the work stream after everything queued so far on the caller's stream
 amg_status join_user_stream(amg_hierarchy *h);
