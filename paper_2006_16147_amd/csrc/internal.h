@@ -282,6 +282,13 @@ amg_status join_user_stream(amg_hierarchy *h);
 // exclusive prefix sum of n int32 values; writes n + 1 outputs (out[n] = total)
 amg_status scan_exclusive_i32(const int32_t *in, int32_t *out, int32_t n, hipStream_t s);
 
+// temporaries of a setup step: cut from the running setup's arena (releasing
+// them is then a no-op), else stream-ordered pool memory; and the same scan
+// with its block sums taken that way
+amg_status setup_tmp_alloc(amg_hierarchy *h, void **p, size_t bytes);
+void setup_tmp_free(amg_hierarchy *h, void *p);
+amg_status setup_scan(amg_hierarchy *h, const int32_t *in, int32_t *out, int32_t n);
+
 // setup (setup.hip)
 amg_status build_hierarchy(amg_hierarchy *h, const amg_csr *A);
 

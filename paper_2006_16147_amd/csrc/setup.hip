@@ -1074,6 +1074,24 @@ amg_status adopt_level(amg_hierarchy *h, const Mat &M, Level &L) {
 
 }  // namespace
 
+amg_status setup_tmp_alloc(amg_hierarchy *h, void **p, size_t bytes) {
+  if (h->setup_arena) return static_cast<Arena *>(h->setup_arena)->get(p, bytes);
+  return stream_alloc(h->device, h->stream, p, bytes);
+}
+
+void setup_tmp_free(amg_hierarchy *h, void *p) {
+  if (!h->setup_arena) stream_free(h->device, h->stream, p);
+}
+
+amg_status setup_scan(amg_hierarchy *h, const int32_t *in, int32_t *out, int32_t n) {
+  int32_t *bsum = nullptr;
+  AMG_TRY(setup_tmp_alloc(h, reinterpret_cast<void **>(&bsum),
+                          sizeof(int32_t) * ((size_t)scan_blocks(n) + 1)));
+  scan_exclusive_i32_with(in, out, n, bsum, h->stream);
+  setup_tmp_free(h, bsum);
+  return AMG_OK;
+}
+
 amg_status scan_exclusive_i32(const int32_t *in, int32_t *out, int32_t n, hipStream_t s) {
   const int32_t nb = scan_blocks(n);
   int32_t *bsum = nullptr;

@@ -2347,7 +2347,7 @@ amg_status build_halo(amg_hierarchy *h, const Level &L, const int32_t *tb, int32
                       int32_t param, Halo *H) {
   hipStream_t s = h->stream;
   int32_t *count;
-  AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&count), sizeof(int32_t) * (ntiles + 1), s));
+  AMG_TRY(setup_tmp_alloc(h, reinterpret_cast<void **>(&count), sizeof(int32_t) * (ntiles + 1)));
   k_halo<<<ntiles, kHaloThreads, 0, s>>>(0, tb, L.S.sptr, L.S.col, count, nullptr, nullptr,
                                         nullptr);
   std::vector<int32_t> hc(ntiles);
@@ -2362,7 +2362,7 @@ amg_status build_halo(amg_hierarchy *h, const Level &L, const int32_t *tb, int32
     total += c > 0 ? c : 0;
   }
   if (!fits || umax > kHaloMaxList || total > INT32_MAX) {
-    (void)hipFreeAsync(count, s);
+    setup_tmp_free(h, count);
     return AMG_OK;
   }
   Halo G;
@@ -2370,13 +2370,13 @@ amg_status build_halo(amg_hierarchy *h, const Level &L, const int32_t *tb, int32
   G.param = param;
   G.umax = umax;
   amg_status st = dalloc(h, &G.hptr, (size_t)ntiles + 1);
-  if (st == AMG_OK) st = scan_exclusive_i32(count, G.hptr, ntiles, s);
+  if (st == AMG_OK) st = setup_scan(h, count, G.hptr, ntiles);
   if (st == AMG_OK) st = dalloc(h, &G.hidx, (size_t)(total > 0 ? total : 1));
   if (st == AMG_OK) st = dalloc(h, &G.lcol, (size_t)L.S.nnz_padded);
   if (st == AMG_OK)
     k_halo<<<ntiles, kHaloThreads, 0, s>>>(1, tb, L.S.sptr, L.S.col, nullptr, G.hptr, G.hidx,
                                           G.lcol);
-  (void)hipFreeAsync(count, s);
+  setup_tmp_free(h, count);
   AMG_TRY(st);
   AMG_HIP(hipGetLastError());
   *H = G;
@@ -2398,7 +2398,7 @@ amg_status build_level0_halos(amg_hierarchy *h) {
   const int32_t G = staged_down_G(h);
   const int32_t nseg = ceil_div(C.n, G);
   const int32_t most = std::max(g.grid, nseg);
-  AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&tb), sizeof(int32_t) * (most + 1), s));
+  AMG_TRY(setup_tmp_alloc(h, reinterpret_cast<void **>(&tb), sizeof(int32_t) * (most + 1)));
   k_tile_starts<<<ceil_div(g.grid + 1, kBlock), kBlock, 0, s>>>(g.grid, g.chunk, F.n, nullptr,
                                                                 tb);
   amg_status st = build_halo(h, F, tb, g.grid, g.chunk, &F.hrow);
@@ -2406,7 +2406,7 @@ amg_status build_level0_halos(amg_hierarchy *h) {
     k_tile_starts<<<ceil_div(nseg + 1, kBlock), kBlock, 0, s>>>(nseg, G, C.n, F.seg, tb);
     st = build_halo(h, F, tb, nseg, G, &F.hseg);
   }
-  (void)hipFreeAsync(tb, s);
+  setup_tmp_free(h, tb);
   return st;
 }
 
@@ -2432,11 +2432,11 @@ amg_status build_solve_formats(amg_hierarchy *h) {
     Level &F = h->lv[l];
     Level &C = h->lv[l + 1];
     int32_t *cnt;
-    AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&cnt), sizeof(int32_t) * C.n + 16, s));
+    AMG_TRY(setup_tmp_alloc(h, reinterpret_cast<void **>(&cnt), sizeof(int32_t) * C.n + 16));
     AMG_TRY(dalloc(h, &F.seg, (size_t)C.n + 1));
     k_seg_count<<<grid1(C.n), kBlock, 0, s>>>(C.n, C.perm, F.mptr, cnt);
-    AMG_TRY(scan_exclusive_i32(cnt, F.seg, C.n, s));
-    AMG_HIP(hipFreeAsync(cnt, s));
+    AMG_TRY(setup_scan(h, cnt, F.seg, C.n));
+    setup_tmp_free(h, cnt);
     AMG_TRY(dalloc(h, &F.perm, (size_t)F.n));
     AMG_TRY(dalloc(h, &F.iperm, (size_t)F.n));
     AMG_TRY(dalloc(h, &F.aggp, (size_t)F.n));
@@ -2457,13 +2457,13 @@ amg_status build_solve_formats(amg_hierarchy *h) {
       // the exact FP32 copy (identical arithmetic, half the value bytes)
       // unless AMG_FLAG_NO_VALUE_COMPRESSION switches it off
       int32_t *flag;
-      AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&flag), sizeof(int32_t), s));
+      AMG_TRY(setup_tmp_alloc(h, reinterpret_cast<void **>(&flag), sizeof(int32_t)));
       AMG_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
       k_not_fp32_exact<<<grid1(L.nnz), kBlock, 0, s>>>(L.nnz, L.val, flag);
       int32_t hflag = 1;
       AMG_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
       AMG_HIP(hipStreamSynchronize(s));
-      AMG_HIP(hipFreeAsync(flag, s));
+      setup_tmp_free(h, flag);
       L.S.fp32_values = hflag == 0;
       L.S.exact32 = L.S.fp32_values && !(h->params.flags & AMG_FLAG_NO_VALUE_COMPRESSION);
       need32 = need32 || L.S.exact32;
@@ -2473,22 +2473,22 @@ amg_status build_solve_formats(amg_hierarchy *h) {
       S.n = L.n;
       S.nslices = ceil_div(L.n, kSlice);
       int32_t *w64;
-      AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&w64), sizeof(int32_t) * S.nslices + 16, s));
+      AMG_TRY(setup_tmp_alloc(h, reinterpret_cast<void **>(&w64), sizeof(int32_t) * S.nslices + 16));
       unsigned long long *total;
-      AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&total), sizeof(unsigned long long), s));
+      AMG_TRY(setup_tmp_alloc(h, reinterpret_cast<void **>(&total), sizeof(unsigned long long)));
       AMG_HIP(hipMemsetAsync(total, 0, sizeof(unsigned long long), s));
       AMG_TRY(dalloc(h, &S.sptr, (size_t)S.nslices + 1));
       k_sell_width<<<grid1(S.nslices), kBlock, 0, s>>>(L.n, S.nslices, L.rp, L.perm, w64, total);
       unsigned long long htotal = 0;
       AMG_HIP(hipMemcpyAsync(&htotal, total, sizeof(htotal), hipMemcpyDeviceToHost, s));
       AMG_HIP(hipStreamSynchronize(s));
-      AMG_HIP(hipFreeAsync(total, s));
+      setup_tmp_free(h, total);
       if (htotal > (unsigned long long)INT32_MAX) {
-        (void)hipFreeAsync(w64, s);
+        setup_tmp_free(h, w64);
         return AMG_ERR_ARG;  // padded rows exceed the format's 32-bit offsets
       }
-      AMG_TRY(scan_exclusive_i32(w64, S.sptr, S.nslices, s));
-      AMG_HIP(hipFreeAsync(w64, s));
+      AMG_TRY(setup_scan(h, w64, S.sptr, S.nslices));
+      setup_tmp_free(h, w64);
       int32_t padded = 0;
       AMG_HIP(hipMemcpyAsync(&padded, S.sptr + S.nslices, sizeof(int32_t),
                              hipMemcpyDeviceToHost, s));
